@@ -1,0 +1,164 @@
+/*
+ * fmm.h -- C ABI of the MI355X (gfx950) collisional FMM force pass.
+ *
+ * One call computes, for N point masses, the gravitational acceleration and
+ * potential of every body with the fast multipole method of Mukherjee, Zhu,
+ * Trac & Rodriguez (2021): an octree over Morton-sorted bodies, P2M/M2M in
+ * regular solid harmonics (section 2.2), a scalar-force estimate and a
+ * dual-tree walk with the error-controlled mutual acceptance criterion
+ * (section 2.3), rotation-accelerated M2L (section 2.4), L2L, L2P and direct
+ * P2P for the near field (section 2.1).
+ *
+ * Conventions: G = 1; acc_i = sum_{j != i} m_j (x_j - x_i) / (r_ij^2 + eps^2)^{3/2};
+ * pot_i = -sum_{j != i} m_j / (r_ij^2 + eps^2)^{1/2}  (eps = Plummer softening,
+ * applied to the direct near field only; the far field is unsoftened).
+ * Pairs with r_ij^2 + eps^2 == 0 contribute nothing.
+ *
+ * Memory: unless stated otherwise every pointer argument is a HIP DEVICE
+ * pointer on the context's device; positions are n x 3 row-major FP64,
+ * masses FP64.  The caller owns inputs and outputs; the context owns all
+ * scratch (tree, expansions, lists), grows it on demand and frees it in
+ * fmm_destroy.  Work is enqueued on the given stream; functions that return
+ * host-visible values synchronise that stream.  No function throws; every
+ * status other than FMM_OK leaves outputs unspecified and the context usable.
+ * A context must not be used from two host threads at once.
+ */
+#ifndef FMM_H
+#define FMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FMM_OK = 0,
+  FMM_EINVAL = -1,       /* bad argument (checked on the host before any launch) */
+  FMM_ENOMEM = -2,       /* device allocation failed / workspace cap exceeded    */
+  FMM_EHIP = -3,         /* a HIP runtime call failed (message in fmm_last_error) */
+  FMM_ENOTBUILT = -4,    /* export asked for data no call has produced yet        */
+  FMM_EDATA = -5,        /* non-finite position or negative/non-finite mass       */
+  FMM_EUNSUPPORTED = -6  /* valid but not supported by this build                 */
+} fmm_status;
+
+typedef enum {
+  FMM_FP64 = 0,   /* every stage in FP64                                            */
+  FMM_MIXED = 1,  /* P2P and M2L below the root levels in FP32 (scaled, relative
+                     coordinates, compensated sums); tree, acceptance test, P2M/M2M,
+                     L2L, L2P and the final sum in FP64                              */
+  FMM_DIRECT = 2  /* plain O(N^2) direct summation (FP64), for checks               */
+} fmm_precision;
+
+typedef enum {
+  FMM_MAC_ERROR = 0,     /* error-controlled mutual criterion, section 2.3       */
+  FMM_MAC_GEOMETRIC = 1  /* opening angle only: (r_A + r_B) < theta * r          */
+} fmm_mac;
+
+typedef struct {
+  int p;            /* expansion order, 1..30 (swap tables exist for p <= 30, section 2.4) */
+  double err_tol;   /* epsilon of the acceptance criterion, > 0 (section 2.3)             */
+  double theta;     /* opening-angle cap, (0, 1], default 1 ("theta < 1", section 2.3)    */
+  double theta_est; /* opening angle of the scalar-force estimate walk, default 1         */
+  int n_leaf;       /* a cell with more bodies is split, 1..1024, default 64              */
+  int precision;    /* fmm_precision                                                      */
+  int mac;          /* fmm_mac                                                            */
+  int check_inputs; /* 1: reject NaN/Inf positions, negative or NaN masses (FMM_EDATA)    */
+  int root_levels;  /* mixed precision: M2L touching a cell above this level stays FP64 */
+} fmm_params;
+
+/* counts of the last call (filled by fmm_stats) */
+typedef struct {
+  int64_t n;              /* bodies                                       */
+  int64_t ncell;          /* cells (root = 0, breadth-first ids)          */
+  int64_t nleaf;          /* leaves                                       */
+  int32_t depth;          /* deepest level                                */
+  int64_t n_m2l;          /* directed M2L pairs                           */
+  int64_t n_p2p_cells;    /* directed P2P leaf pairs (incl. self pairs)   */
+  int64_t n_p2p_pairs;    /* directed body-body interactions in P2P       */
+  int64_t n_est_far;      /* directed accepted pairs of the estimate walk */
+  int64_t n_est_near;     /* directed leaf pairs of the estimate walk     */
+  int64_t n_m2l_fp32;     /* M2L pairs evaluated in FP32 (mixed mode)     */
+  double ms_tree, ms_upward, ms_estimate, ms_walk, ms_m2l, ms_local, ms_p2p, ms_total;
+  size_t workspace_bytes; /* device memory held by the context            */
+} fmm_stats_t;
+
+/* export selectors for fmm_export (host buffer, element counts from fmm_stats) */
+typedef enum {
+  FMM_X_KEYS = 0,       /* uint64[n]   sorted 63-bit Morton keys                    */
+  FMM_X_PERM = 1,       /* int32[n]    caller index of each sorted body             */
+  FMM_X_CELL_LEVEL = 2, /* int32[ncell]                                             */
+  FMM_X_CELL_BEGIN = 3, /* int32[ncell] first sorted body                          */
+  FMM_X_CELL_END = 4,   /* int32[ncell] one past the last                           */
+  FMM_X_CELL_PARENT = 5,/* int32[ncell] -1 for the root                             */
+  FMM_X_CELL_CHILD0 = 6,/* int32[ncell] first child, -1 for leaves                  */
+  FMM_X_CELL_NCHILD = 7,/* int32[ncell]                                             */
+  FMM_X_CELL_MASS = 8,  /* double[ncell]                                            */
+  FMM_X_CELL_COM = 9,   /* double[ncell*3] centre of mass (expansion centre)        */
+  FMM_X_CELL_RAD = 10,  /* double[ncell] max distance of a body from the centre     */
+  FMM_X_MULT = 11,      /* double[ncell*ncoef*2] multipoles, (re, im) interleaved,
+                           coefficient (n, m>=0) at n(n+1)/2 + m                    */
+  FMM_X_PK = 12,        /* double[ncell*(p+1)] per-order norms P_k (section 2.3)    */
+  FMM_X_FCELL = 13,     /* double[ncell] far-field scalar-force sums of the estimate */
+  FMM_X_FPART = 14,     /* double[n] scalar force f_i in sorted order               */
+  FMM_X_FMIN = 15,      /* double[ncell] min of f over the cell's bodies            */
+  FMM_X_EST_FAR = 16,   /* int32[2*n_est_far] (sink, source) pairs, CSR by sink     */
+  FMM_X_EST_NEAR = 17,  /* int32[2*n_est_near]                                      */
+  FMM_X_M2L = 18,       /* int32[2*n_m2l]                                           */
+  FMM_X_P2P = 19,       /* int32[2*n_p2p_cells]                                     */
+  FMM_X_LOCAL = 20,     /* double[ncell*ncoef*2] local expansions after L2L         */
+  FMM_X_ROOTBOX = 21    /* double[5] lo_x, lo_y, lo_z, edge L, key scale 2^21/L    */
+} fmm_export_what;
+
+typedef struct fmm_ctx fmm_ctx;
+
+/* Defaults: p = 10, err_tol = 1e-7, theta = 1, theta_est = 1, n_leaf = 64,
+ * precision = FMM_FP64, mac = FMM_MAC_ERROR, check_inputs = 0, root_levels = 3. */
+void fmm_default_params(fmm_params* out /* host */);
+
+/* Creates a context on the current HIP device.  prm (host) may be NULL for the
+ * defaults.  *out receives the context (host pointer). */
+fmm_status fmm_create(fmm_ctx** out, const fmm_params* prm);
+
+/* Replaces the parameters used by later calls (validated as in fmm_create). */
+fmm_status fmm_set_params(fmm_ctx* ctx, const fmm_params* prm);
+
+/* Tree and upward pass only (keys, sort, cells, P2M, M2M, P_k): planning and
+ * parity export.  pos/mass: device, n >= 1. */
+fmm_status fmm_build(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass,
+                     void* stream /* hipStream_t, NULL = default stream */);
+
+/* One full force evaluation: rebuilds the tree from pos, then estimate, walk,
+ * M2L, L2L, L2P and P2P.  p and err_tol override the context's parameters for
+ * this call.  acc (n x 3) and pot (n) are device buffers in the caller's body
+ * order and are overwritten.  n == 1 gives acc = 0, pot = 0. */
+fmm_status fmm_forces(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass,
+                      double eps_soft, int p, double err_tol, double* acc, double* pot,
+                      void* stream);
+
+/* Counts and per-stage times of the last call (synchronises its stream). */
+fmm_status fmm_stats(fmm_ctx* ctx, fmm_stats_t* out /* host */);
+
+/* Copies an array of the last call into host memory (synchronises).  bytes
+ * must be at least the size listed beside the selector. */
+fmm_status fmm_export(fmm_ctx* ctx, int what, void* host_buf, size_t bytes);
+
+/* Caps the context's device workspace (0 = no cap); exceeding it -> FMM_ENOMEM. */
+fmm_status fmm_set_workspace_limit(fmm_ctx* ctx, size_t bytes);
+
+/* Plain O(N^2) direct sum on the GPU for the sinks listed (device int32
+ * indices, or all bodies when sinks == NULL), sources = all bodies.  Outputs
+ * indexed like the sink list.  Used to measure force errors at large N. */
+fmm_status fmm_direct(int64_t n, const double* pos, const double* mass, double eps_soft,
+                      int64_t nsink, const int32_t* sinks, double* acc, double* pot,
+                      void* stream);
+
+const char* fmm_strerror(fmm_status s);
+const char* fmm_last_error(fmm_ctx* ctx); /* detail of the last failure, "" if none */
+void fmm_destroy(fmm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMM_H */

@@ -1,0 +1,413 @@
+// C ABI of the gfx950 FMM library (declared in include/fmm.h): argument
+// validation, workspace ownership, stage orchestration, statistics and export.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "fmm_device.h"
+
+struct fmm_ctx {
+  fmm::Ctx c;
+};
+
+namespace fmm {
+
+void check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw hip_error{e, what};
+}
+
+void* ws_alloc(Workspace& w, size_t bytes) {
+  if (w.limit && w.bytes + bytes > w.limit) throw oom_error{};
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes ? bytes : 1);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+    (void)hipGetLastError();
+    throw oom_error{};
+  }
+  check(e, "hipMalloc");
+  w.bytes += bytes;
+  return p;
+}
+
+void ws_free(Workspace& w, void* p, size_t bytes) {
+  (void)hipFree(p);
+  w.bytes -= bytes;
+}
+
+// leaves list, built by the upward pass at this offset of c_split
+static const int* leaves_of(Ctx& c) { return c.c_split.p + 2 * (c.ncell + 32); }
+
+void launch_leaf_eval(Ctx& c, const int* leaves, double* acc, double* pot);
+void launch_l2l(Ctx& c);
+
+__global__ void k_count_p2p_pairs(const int* off, const int* src, const int* cb, const int* ce,
+                                  int ncell, unsigned long long* out) {
+  int B = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long s = 0;
+  if (B < ncell) {
+    long long nb = ce[B] - cb[B];
+    for (int k = off[B]; k < off[B + 1]; k++) {
+      int A = src[k];
+      long long na = ce[A] - cb[A];
+      s += (unsigned long long)(A == B ? nb * (nb - 1) : na * nb);
+    }
+  }
+  if (s) atomicAdd(out, s);
+}
+
+void evaluate(Ctx& c, double* acc, double* pot) {
+  hipStream_t s = c.stream;
+  int nc = (int)c.ncell;
+  size_t nl = (size_t)nc * ncoef(c.p) * 2;
+  ensure(c.ws, c.loc, nl);
+  if (c.have_events) HIPCHK(hipEventRecord(c.ev[4], s));
+  if (c.prm.precision == FMM_MIXED)
+    launch_m2l_mixed(c);
+  else {
+    HIPCHK(hipMemsetAsync(c.loc.p, 0, nl * sizeof(double), s));
+    launch_m2l_fp64(c);
+  }
+  if (c.have_events) HIPCHK(hipEventRecord(c.ev[5], s));
+  launch_l2l(c);
+  if (c.have_events) HIPCHK(hipEventRecord(c.ev[6], s));
+  launch_leaf_eval(c, leaves_of(c), acc, pot);
+  if (c.have_events) HIPCHK(hipEventRecord(c.ev[7], s));
+}
+
+}  // namespace fmm
+
+using namespace fmm;
+
+static fmm_status validate_params(const fmm_params* p) {
+  if (p->p < 1 || p->p > 30) return FMM_EINVAL;
+  if (!(p->err_tol > 0) || !std::isfinite(p->err_tol)) return FMM_EINVAL;
+  if (!(p->theta > 0) || p->theta > 1.0 || !(p->theta_est > 0) || p->theta_est > 1.0) return FMM_EINVAL;
+  if (p->n_leaf < 1 || p->n_leaf > 1024) return FMM_EINVAL;
+  if (p->precision < FMM_FP64 || p->precision > FMM_DIRECT) return FMM_EINVAL;
+  if (p->mac != FMM_MAC_ERROR && p->mac != FMM_MAC_GEOMETRIC) return FMM_EINVAL;
+  if (p->root_levels < 0 || p->root_levels > FMM_MAX_LEVEL + 1) return FMM_EINVAL;
+  return FMM_OK;
+}
+
+template <class F>
+static fmm_status guarded(fmm_ctx* ctx, F&& f) {
+  try {
+    return f();
+  } catch (const hip_error& e) {
+    if (ctx) {
+      ctx->c.err = std::string(e.where) + ": " + hipGetErrorString(e.code);
+      (void)hipGetLastError();
+    }
+    return FMM_EHIP;
+  } catch (const oom_error&) {
+    if (ctx) ctx->c.err = "device workspace allocation failed or exceeded the cap";
+    return FMM_ENOMEM;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->c.err = "host allocation failed";
+    return FMM_ENOMEM;
+  }
+}
+
+extern "C" {
+
+void fmm_default_params(fmm_params* out) {
+  if (!out) return;
+  out->p = 10;
+  out->err_tol = 1e-7;
+  out->theta = 1.0;
+  out->theta_est = 1.0;
+  out->n_leaf = 64;
+  out->precision = FMM_FP64;
+  out->mac = FMM_MAC_ERROR;
+  out->check_inputs = 0;
+  out->root_levels = 3;
+}
+
+fmm_status fmm_create(fmm_ctx** out, const fmm_params* prm) {
+  if (!out) return FMM_EINVAL;
+  *out = nullptr;
+  fmm_params p;
+  fmm_default_params(&p);
+  if (prm) p = *prm;
+  fmm_status st = validate_params(&p);
+  if (st != FMM_OK) return st;
+  fmm_ctx* ctx = new (std::nothrow) fmm_ctx();
+  if (!ctx) return FMM_ENOMEM;
+  ctx->c.prm = p;
+  st = guarded(ctx, [&]() {
+    HIPCHK(hipGetDevice(&ctx->c.device));
+    HIPCHK(hipHostMalloc((void**)&ctx->c.hbuf, 64 * sizeof(long long), hipHostMallocDefault));
+    for (auto& e : ctx->c.ev) HIPCHK(hipEventCreate(&e));
+    return FMM_OK;
+  });
+  if (st != FMM_OK) {
+    fmm_destroy(ctx);
+    return st;
+  }
+  *out = ctx;
+  return FMM_OK;
+}
+
+fmm_status fmm_set_params(fmm_ctx* ctx, const fmm_params* prm) {
+  if (!ctx || !prm) return FMM_EINVAL;
+  fmm_status st = validate_params(prm);
+  if (st != FMM_OK) return st;
+  ctx->c.prm = *prm;
+  return FMM_OK;
+}
+
+static fmm_status common_checks(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass) {
+  if (!ctx || !pos || !mass || n < 1) return FMM_EINVAL;
+  if (n > (int64_t)0x3fffffff) return FMM_EUNSUPPORTED;
+  return FMM_OK;
+}
+
+static void run_build(Ctx& c, int64_t n, const double* pos, const double* mass) {
+  c.built = c.estimated = c.walked = c.evaluated = false;
+  build_tree(c, n, pos, mass);
+  if (c.have_events) HIPCHK(hipEventRecord(c.ev[1], c.stream));
+  upward_pass(c);
+  if (c.have_events) HIPCHK(hipEventRecord(c.ev[2], c.stream));
+  c.built = true;
+}
+
+fmm_status fmm_build(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass, void* stream) {
+  fmm_status st = common_checks(ctx, n, pos, mass);
+  if (st != FMM_OK) return st;
+  Ctx& c = ctx->c;
+  if (c.prm.p > FMM_GPU_PMAX) return FMM_EUNSUPPORTED;
+  return guarded(ctx, [&]() {
+    c.stream = (hipStream_t)stream;
+    c.err.clear();
+    c.p = c.prm.p;
+    c.err_tol = c.prm.err_tol;
+    if (c.prm.check_inputs && !check_inputs_dev(c, pos, mass, n)) return FMM_EDATA;
+    c.have_events = true;
+    HIPCHK(hipEventRecord(c.ev[0], c.stream));
+    run_build(c, n, pos, mass);
+    return FMM_OK;
+  });
+}
+
+fmm_status fmm_forces(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass, double eps_soft,
+                      int p, double err_tol, double* acc, double* pot, void* stream) {
+  fmm_status st = common_checks(ctx, n, pos, mass);
+  if (st != FMM_OK) return st;
+  if (!acc || !pot) return FMM_EINVAL;
+  if (!(eps_soft >= 0) || !std::isfinite(eps_soft)) return FMM_EINVAL;
+  if (p < 1 || p > 30) return FMM_EINVAL;
+  if (!(err_tol > 0) || !std::isfinite(err_tol)) return FMM_EINVAL;
+  Ctx& c = ctx->c;
+  if (c.prm.precision != FMM_DIRECT && p > FMM_GPU_PMAX) return FMM_EUNSUPPORTED;
+  if (c.prm.precision == FMM_MIXED && !mixed_supported(p)) return FMM_EUNSUPPORTED;
+  return guarded(ctx, [&]() {
+    c.stream = (hipStream_t)stream;
+    c.err.clear();
+    c.p = p;
+    c.err_tol = err_tol;
+    c.eps_soft = eps_soft;
+    if (c.prm.check_inputs && !check_inputs_dev(c, pos, mass, n)) return FMM_EDATA;
+    if (c.prm.precision == FMM_DIRECT) {
+      c.have_events = false;
+      direct_sum(n, pos, mass, eps_soft * eps_soft, n, nullptr, acc, pot, c.stream);
+      return FMM_OK;
+    }
+    c.have_events = true;
+    HIPCHK(hipEventRecord(c.ev[0], c.stream));
+    run_build(c, n, pos, mass);
+    estimate_walk(c);
+    c.estimated = true;
+    HIPCHK(hipEventRecord(c.ev[3], c.stream));
+    mac_walk(c);
+    c.walked = true;
+    evaluate(c, acc, pot);
+    c.evaluated = true;
+    HIPCHK(hipEventRecord(c.ev[8], c.stream));
+    return FMM_OK;
+  });
+}
+
+fmm_status fmm_stats(fmm_ctx* ctx, fmm_stats_t* out) {
+  if (!ctx || !out) return FMM_EINVAL;
+  Ctx& c = ctx->c;
+  std::memset(out, 0, sizeof(*out));
+  if (!c.built) return FMM_ENOTBUILT;
+  return guarded(ctx, [&]() {
+    HIPCHK(hipStreamSynchronize(c.stream));
+    out->n = c.n;
+    out->ncell = c.ncell;
+    out->nleaf = c.nleaf;
+    out->depth = c.depth;
+    out->workspace_bytes = c.ws.bytes;
+    if (c.walked) {
+      out->n_m2l = c.m2l.count;
+      out->n_p2p_cells = c.p2p.count;
+      out->n_m2l_fp32 = c.prm.precision == FMM_MIXED ? c.n_m2l_fp32 : 0;
+      // body-pair count of the near field
+      unsigned long long* d = (unsigned long long*)(c.counters.p + 40);
+      HIPCHK(hipMemsetAsync(d, 0, 8, c.stream));
+      hipLaunchKernelGGL(k_count_p2p_pairs, dim3((unsigned)((c.ncell + 255) / 256)), dim3(256), 0,
+                         c.stream, c.p2p.off.p, c.p2p.src.p, c.c_begin.p, c.c_end.p, (int)c.ncell, d);
+      HIPCHK(hipMemcpyAsync(c.hbuf, d, 8, hipMemcpyDeviceToHost, c.stream));
+      HIPCHK(hipStreamSynchronize(c.stream));
+      out->n_p2p_pairs = c.hbuf[0];
+    }
+    if (c.estimated) {
+      out->n_est_far = c.est_far.count;
+      out->n_est_near = c.est_near.count;
+    }
+    auto el = [&](int a, int b) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, c.ev[a], c.ev[b]) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0.0;
+      }
+      return (double)ms;
+    };
+    if (c.have_events) {
+      out->ms_tree = el(0, 1);
+      out->ms_upward = el(1, 2);
+      if (c.evaluated) {
+        out->ms_estimate = el(2, 3);
+        out->ms_walk = el(3, 4);
+        out->ms_m2l = el(4, 5);
+        out->ms_local = el(5, 6);
+        out->ms_p2p = el(6, 7);
+        out->ms_total = el(0, 8);
+      } else {
+        out->ms_total = el(0, 2);
+      }
+    }
+    return FMM_OK;
+  });
+}
+
+fmm_status fmm_export(fmm_ctx* ctx, int what, void* host_buf, size_t bytes) {
+  if (!ctx || !host_buf) return FMM_EINVAL;
+  Ctx& c = ctx->c;
+  if (!c.built) return FMM_ENOTBUILT;
+  int64_t nc = c.ncell, n = c.n;
+  size_t ncf = (size_t)ncoef(c.p) * 2;
+  const void* src = nullptr;
+  size_t need = 0;
+  const CellList* lst = nullptr;
+  switch (what) {
+    case FMM_X_KEYS: src = c.key[0].p; need = n * 8; break;
+    case FMM_X_PERM: src = c.idx[0].p; need = n * 4; break;
+    case FMM_X_CELL_LEVEL: src = c.c_level.p; need = nc * 4; break;
+    case FMM_X_CELL_BEGIN: src = c.c_begin.p; need = nc * 4; break;
+    case FMM_X_CELL_END: src = c.c_end.p; need = nc * 4; break;
+    case FMM_X_CELL_PARENT: src = c.c_parent.p; need = nc * 4; break;
+    case FMM_X_CELL_CHILD0: src = c.c_child0.p; need = nc * 4; break;
+    case FMM_X_CELL_NCHILD: src = c.c_nchild.p; need = nc * 4; break;
+    case FMM_X_CELL_MASS: src = c.c_mass.p; need = nc * 8; break;
+    case FMM_X_CELL_COM: break;
+    case FMM_X_CELL_RAD: src = c.c_rad.p; need = nc * 8; break;
+    case FMM_X_MULT: src = c.mult.p; need = nc * ncf * 8; break;
+    case FMM_X_PK: src = c.pk.p; need = nc * (c.p + 1) * 8; break;
+    case FMM_X_FCELL: if (!c.estimated) return FMM_ENOTBUILT; src = c.fcell.p; need = nc * 8; break;
+    case FMM_X_FPART: if (!c.estimated) return FMM_ENOTBUILT; src = c.fpart.p; need = n * 8; break;
+    case FMM_X_FMIN: if (!c.estimated) return FMM_ENOTBUILT; src = c.fmin.p; need = nc * 8; break;
+    case FMM_X_EST_FAR: if (!c.estimated) return FMM_ENOTBUILT; lst = &c.est_far; break;
+    case FMM_X_EST_NEAR: if (!c.estimated) return FMM_ENOTBUILT; lst = &c.est_near; break;
+    case FMM_X_M2L: if (!c.walked) return FMM_ENOTBUILT; lst = &c.m2l; break;
+    case FMM_X_P2P: if (!c.walked) return FMM_ENOTBUILT; lst = &c.p2p; break;
+    case FMM_X_LOCAL: if (!c.evaluated) return FMM_ENOTBUILT; src = c.loc.p; need = nc * ncf * 8; break;
+    case FMM_X_ROOTBOX: src = c.rootbox.p; need = 5 * 8; break;
+    default: return FMM_EINVAL;
+  }
+  return guarded(ctx, [&]() {
+    HIPCHK(hipStreamSynchronize(c.stream));
+    if (what == FMM_X_CELL_COM) {
+      if (bytes < (size_t)nc * 24) return FMM_EINVAL;
+      std::vector<double> t((size_t)nc);
+      double* o = (double*)host_buf;
+      const double* parts[3] = {c.c_cx.p, c.c_cy.p, c.c_cz.p};
+      for (int d = 0; d < 3; d++) {
+        HIPCHK(hipMemcpy(t.data(), parts[d], nc * 8, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < nc; i++) o[3 * i + d] = t[i];
+      }
+      return FMM_OK;
+    }
+    if (lst) {
+      size_t cnt = (size_t)lst->count;
+      if (bytes < cnt * 8) return FMM_EINVAL;
+      std::vector<int> off((size_t)nc + 1), srcv(cnt);
+      HIPCHK(hipMemcpy(off.data(), lst->off.p, (nc + 1) * 4, hipMemcpyDeviceToHost));
+      if (cnt) HIPCHK(hipMemcpy(srcv.data(), lst->src.p, cnt * 4, hipMemcpyDeviceToHost));
+      int* o = (int*)host_buf;
+      for (int64_t s = 0; s < nc; s++)
+        for (int k = off[s]; k < off[s + 1]; k++) {
+          o[2 * k] = (int)s;
+          o[2 * k + 1] = srcv[k];
+        }
+      return FMM_OK;
+    }
+    if (bytes < need) return FMM_EINVAL;
+    HIPCHK(hipMemcpy(host_buf, src, need, hipMemcpyDeviceToHost));
+    return FMM_OK;
+  });
+}
+
+fmm_status fmm_set_workspace_limit(fmm_ctx* ctx, size_t bytes) {
+  if (!ctx) return FMM_EINVAL;
+  ctx->c.ws.limit = bytes;
+  return FMM_OK;
+}
+
+fmm_status fmm_direct(int64_t n, const double* pos, const double* mass, double eps_soft, int64_t nsink,
+                      const int32_t* sinks, double* acc, double* pot, void* stream) {
+  if (n < 1 || !pos || !mass || !acc || !pot || nsink < 0) return FMM_EINVAL;
+  if (!(eps_soft >= 0) || !std::isfinite(eps_soft)) return FMM_EINVAL;
+  if (!sinks) nsink = n;
+  if (nsink == 0) return FMM_OK;
+  return guarded(nullptr, [&]() {
+    direct_sum(n, pos, mass, eps_soft * eps_soft, nsink, sinks, acc, pot, (hipStream_t)stream);
+    return FMM_OK;
+  });
+}
+
+const char* fmm_strerror(fmm_status s) {
+  switch (s) {
+    case FMM_OK: return "ok";
+    case FMM_EINVAL: return "invalid argument";
+    case FMM_ENOMEM: return "out of device memory or workspace cap exceeded";
+    case FMM_EHIP: return "HIP runtime error";
+    case FMM_ENOTBUILT: return "requested data has not been produced yet";
+    case FMM_EDATA: return "non-finite position or negative/non-finite mass";
+    case FMM_EUNSUPPORTED: return "not supported by this build";
+  }
+  return "unknown status";
+}
+
+const char* fmm_last_error(fmm_ctx* ctx) { return ctx ? ctx->c.err.c_str() : ""; }
+
+void fmm_destroy(fmm_ctx* ctx) {
+  if (!ctx) return;
+  Ctx& c = ctx->c;
+  (void)hipDeviceSynchronize();
+  auto rel = [&](auto& b) { release(c.ws, b); };
+  for (int k = 0; k < 2; k++) {
+    rel(c.key[k]);
+    rel(c.idx[k]);
+    rel(c.front[k]);
+  }
+  rel(c.sx); rel(c.sy); rel(c.sz); rel(c.sm); rel(c.fpart); rel(c.leaf_of); rel(c.sort_hist);
+  rel(c.bbox_part); rel(c.rootbox); rel(c.c_level); rel(c.c_begin); rel(c.c_end); rel(c.c_parent);
+  rel(c.c_child0); rel(c.c_nchild); rel(c.c_split); rel(c.c_mass); rel(c.c_sx); rel(c.c_sy);
+  rel(c.c_sz); rel(c.c_cx); rel(c.c_cy); rel(c.c_cz); rel(c.c_rad); rel(c.c_rad2bits); rel(c.mult);
+  rel(c.pk); rel(c.fcell); rel(c.fmin); rel(c.loc); rel(c.counters); rel(c.scan_tmp);
+  rel(c.scan_tmp64);
+  for (CellList* L : {&c.est_far, &c.est_near, &c.m2l, &c.p2p}) {
+    rel(L->raw); rel(L->off); rel(L->src); rel(L->cursor);
+  }
+  if (c.hbuf) (void)hipHostFree(c.hbuf);
+  for (auto& e : c.ev)
+    if (e) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+}  // extern "C"

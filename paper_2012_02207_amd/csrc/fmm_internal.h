@@ -1,0 +1,165 @@
+// Internal declarations of the gfx950 FMM library (not part of the C ABI).
+//
+// All translation units are compiled with -ffp-contract=off: every product and
+// sum that feeds the acceptance test (centres, radii, P2M, M2M, P_k, the
+// scalar-force estimate) is rounded exactly as written, in a fixed order, so
+// the tree, the estimate and the interaction lists are reproducible bit for bit.
+// Evaluation kernels (M2L, L2L, L2P, P2P) request fused multiply-adds
+// explicitly with fma().
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fmm.h"
+
+#define FMM_MAX_LEVEL 21
+#define FMM_GPU_PMAX 16  // orders with a compiled M2L kernel
+
+namespace fmm {
+
+constexpr int ncoef(int p) { return (p + 1) * (p + 2) / 2; }
+__host__ __device__ constexpr int cidx(int n, int m) { return n * (n + 1) / 2 + m; }
+
+// ------------------------------------------------------------------ buffers
+struct hip_error {
+  hipError_t code;
+  std::string where;
+};
+
+void check(hipError_t e, const char* what);
+#define HIPCHK(x) ::fmm::check((x), #x)
+
+template <class T>
+struct dbuf {
+  T* p = nullptr;
+  size_t cap = 0;  // elements
+};
+
+struct Workspace;
+
+// growable device allocation, tracked against the context's cap
+void* ws_alloc(Workspace& w, size_t bytes);
+void ws_free(Workspace& w, void* p, size_t bytes);
+
+struct Workspace {
+  size_t bytes = 0;
+  size_t limit = 0;  // 0 = unlimited
+};
+
+struct oom_error {};
+
+template <class T>
+void ensure(Workspace& w, dbuf<T>& b, size_t n, bool keep = false, hipStream_t s = nullptr) {
+  if (n <= b.cap) return;
+  size_t ncap = n + n / 4 + 64;
+  T* np = (T*)ws_alloc(w, ncap * sizeof(T));
+  if (keep && b.p && b.cap) HIPCHK(hipMemcpyAsync(np, b.p, b.cap * sizeof(T), hipMemcpyDeviceToDevice, s));
+  if (b.p) {
+    if (keep) HIPCHK(hipStreamSynchronize(s));
+    ws_free(w, b.p, b.cap * sizeof(T));
+  }
+  b.p = np;
+  b.cap = ncap;
+}
+
+template <class T>
+void release(Workspace& w, dbuf<T>& b) {
+  if (b.p) ws_free(w, b.p, b.cap * sizeof(T));
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+// ------------------------------------------------------------------ lists
+// directed (sink, source) cell pairs grouped by sink: off[ncell+1], src[count]
+struct CellList {
+  dbuf<int2> raw;     // emitted pairs (any order)
+  dbuf<int> off;      // CSR offsets by sink
+  dbuf<int> src;      // sources, ascending within each sink
+  dbuf<int> cursor;   // scatter cursors
+  int64_t count = 0;
+};
+
+// ------------------------------------------------------------------ context
+struct Ctx {
+  fmm_params prm{};
+  int device = 0;
+  std::string err;
+  Workspace ws;
+  hipStream_t stream = nullptr;
+
+  int64_t n = 0;
+  int p = 0;            // order of the last call
+  double err_tol = 0;
+  double eps_soft = 0;
+  bool built = false, estimated = false, walked = false, evaluated = false;
+
+  // bodies (sorted order)
+  dbuf<uint64_t> key[2];
+  dbuf<int> idx[2];
+  dbuf<double> sx, sy, sz, sm;
+  dbuf<double> fpart;
+  dbuf<int> leaf_of;  // leaf id of each sorted body
+
+  // radix sort scratch
+  dbuf<int> sort_hist;
+
+  // bbox scratch: per-block min/max, then lo[3], L, s
+  dbuf<double> bbox_part;
+  dbuf<double> rootbox;  // 5 doubles
+
+  // cells (breadth-first ids)
+  int64_t ncell = 0, nleaf = 0;
+  int depth = 0;
+  std::vector<int> lvl_first, lvl_count;
+  dbuf<int> c_level, c_begin, c_end, c_parent, c_child0, c_nchild;
+  dbuf<int> c_split;  // per-cell scratch for the level build (9 octant starts)
+  dbuf<double> c_mass, c_sx, c_sy, c_sz;  // mass and first moments
+  dbuf<double> c_cx, c_cy, c_cz, c_rad;   // centre of mass and radius
+  dbuf<unsigned long long> c_rad2bits;
+  dbuf<double> mult;  // ncell x ncoef x 2
+  dbuf<double> pk;    // ncell x (p+1)
+  dbuf<double> fcell, fmin;
+  dbuf<double> loc;   // ncell x ncoef x 2
+
+  // walks
+  dbuf<int2> front[2];
+  dbuf<int> counters;  // device counters
+  CellList est_far, est_near, m2l, p2p;
+  int64_t n_p2p_pairs = 0;
+  int64_t n_m2l_fp32 = 0;
+
+  // scan scratch
+  dbuf<int> scan_tmp;
+  dbuf<long long> scan_tmp64;
+
+  // host pinned scratch for small read-backs
+  long long* hbuf = nullptr;
+
+  // timing
+  hipEvent_t ev[10] = {};
+  bool have_events = false;
+};
+
+// ------------------------------------------------------------------ stages
+void exclusive_scan(Ctx& c, const int* in, int* out, int64_t n, long long* total_dev);
+long long read_total(Ctx& c, const long long* total_dev);
+
+void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass);
+void upward_pass(Ctx& c);
+void estimate_walk(Ctx& c);
+void mac_walk(Ctx& c);
+void evaluate(Ctx& c, double* acc, double* pot);
+void direct_sum(int64_t n, const double* pos, const double* mass, double eps2, int64_t nsink,
+                const int32_t* sinks, double* acc, double* pot, hipStream_t s);
+bool check_inputs_dev(Ctx& c, const double* pos, const double* mass, int64_t n);
+
+// M2L launchers (one per compiled order)
+void launch_m2l_fp64(Ctx& c);
+void launch_m2l_mixed(Ctx& c);
+bool mixed_supported(int p);
+
+}  // namespace fmm

@@ -1,0 +1,293 @@
+// Downward pass and near field on gfx950 (section 2.1): L2L shifts each cell's
+// local expansion to its children, L2P evaluates the leaf expansion at every
+// body (potential and force), P2P adds the direct sum over the near-field leaf
+// pairs, and the results are written in the caller's body order.  Also the
+// plain O(N^2) direct sum used for checks.
+#include <hip/hip_runtime.h>
+
+#include "fmm_device.h"
+
+namespace fmm {
+
+// Regular harmonics with fused multiply-adds (evaluation only, not fed to the
+// acceptance test), written to LDS at stride `st`.
+__device__ inline void regular_fast(int p, double x, double y, double z, double* re, double* im,
+                                    int st) {
+  double r2 = fma(x, x, fma(y, y, z * z));
+  re[0] = 1.0;
+  im[0] = 0.0;
+  double pr = 1.0, pi = 0.0;
+  for (int n = 1; n <= p; n++) {
+    double inv = -1.0 / (double)(2 * n);
+    double tr = fma(x, pr, -y * pi), ti = fma(x, pi, y * pr);
+    pr = tr * inv;
+    pi = ti * inv;
+    re[cidx(n, n) * st] = pr;
+    im[cidx(n, n) * st] = pi;
+  }
+  for (int m = 0; m < p; m++) {
+    double ar2 = 0.0, ai2 = 0.0, ar1 = re[cidx(m, m) * st], ai1 = im[cidx(m, m) * st];
+    for (int n = m + 1; n <= p; n++) {
+      double k = (double)(2 * n - 1) * z, inv = 1.0 / (double)((n + m) * (n - m));
+      double vr = fma(k, ar1, -r2 * ar2) * inv, vi = fma(k, ai1, -r2 * ai2) * inv;
+      re[cidx(n, m) * st] = vr;
+      im[cidx(n, m) * st] = vi;
+      ar2 = ar1;
+      ai2 = ai1;
+      ar1 = vr;
+      ai1 = vi;
+    }
+  }
+}
+
+// L_child(j, i) += sum_{k <= p-j} sum_l L_parent(j+k, i+l) conj(Y_k^l(z_child - z_parent))
+__global__ void __launch_bounds__(64) k_l2l(int p, int first, int count, const int* parent,
+                                            const double* cx, const double* cy, const double* cz,
+                                            double* loc) {
+  __shared__ double yre[ncoef(FMM_GPU_PMAX)], yim[ncoef(FMM_GPU_PMAX)];
+  int c = first + blockIdx.x;
+  if (blockIdx.x >= count) return;
+  int P = parent[c];
+  if (threadIdx.x == 0) regular_fast(p, cx[c] - cx[P], cy[c] - cy[P], cz[c] - cz[P], yre, yim, 1);
+  __syncthreads();
+  int nc = ncoef(p);
+  const double* Lp = loc + (size_t)P * nc * 2;
+  double* Lc = loc + (size_t)c * nc * 2;
+  for (int t = threadIdx.x; t < nc; t += 64) {
+    int j = 0;
+    while (cidx(j + 1, 0) <= t) j++;
+    int i = t - cidx(j, 0);
+    double sr = 0.0, si = 0.0;
+    for (int k = 0; k <= p - j; k++)
+      for (int l = -k; l <= k; l++) {
+        int n = j + k, m = i + l;
+        double ar, ai;
+        if (m >= 0) {
+          ar = Lp[2 * cidx(n, m)];
+          ai = Lp[2 * cidx(n, m) + 1];
+        } else {
+          double s = (m & 1) ? -1.0 : 1.0;
+          ar = s * Lp[2 * cidx(n, -m)];
+          ai = -s * Lp[2 * cidx(n, -m) + 1];
+        }
+        double br, bi;  // conj(Y_k^l)
+        if (l >= 0) {
+          br = yre[cidx(k, l)];
+          bi = -yim[cidx(k, l)];
+        } else {
+          double s = (l & 1) ? -1.0 : 1.0;
+          br = s * yre[cidx(k, -l)];
+          bi = s * yim[cidx(k, -l)];
+        }
+        sr = fma(ar, br, fma(-ai, bi, sr));
+        si = fma(ar, bi, fma(ai, br, si));
+      }
+    Lc[2 * t] += sr;
+    Lc[2 * t + 1] += si;
+  }
+}
+
+// reciprocal square root to full FP64 accuracy: hardware estimate + 2 Newton steps
+__device__ __forceinline__ double rsqrt_d(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
+// One wavefront per leaf; lane = sink body.  Far field by L2P (the local
+// expansion shifted to the body: Phi = -Re L'_0^0, a = (-Re L'_1^1,
+// -Im L'_1^1, Re L'_1^0)), near field by direct summation over the leaf's
+// P2P sources (ascending), FP64.
+__global__ void __launch_bounds__(64) k_leaf_eval(int p, const int* __restrict__ leaves, int nleaves,
+                                                  const int* __restrict__ cb, const int* __restrict__ ce,
+                                                  const int* __restrict__ off, const int* __restrict__ srcl,
+                                                  const double* __restrict__ cx, const double* __restrict__ cy,
+                                                  const double* __restrict__ cz, const double* __restrict__ loc,
+                                                  const double* __restrict__ sx, const double* __restrict__ sy,
+                                                  const double* __restrict__ sz, const double* __restrict__ sm,
+                                                  const int* __restrict__ perm, double eps2, double* acc,
+                                                  double* pot) {
+  int per = (nleaves + 7) >> 3;
+  int li = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (li >= nleaves) return;
+  int B = leaves[li];
+  int nc = ncoef(p);
+  const double* L = loc + (size_t)B * nc * 2;
+  int b = cb[B], e = ce[B];
+  for (int i0 = b; i0 < e; i0 += 64) {
+    int i = i0 + threadIdx.x;
+    bool act = i < e;
+    int ii = act ? i : b;
+    double xi = sx[ii], yi = sy[ii], zi = sz[ii];
+    // ---- L2P: harmonics of X = x_i - z_B column by column, each used once
+    double X = xi - cx[B], Y = yi - cy[B], Z = zi - cz[B];
+    double r2 = fma(X, X, fma(Y, Y, Z * Z));
+    double s00 = 0.0, s10 = 0.0, s11r = 0.0, s11i = 0.0;
+    double dr = 1.0, di = 0.0;  // Y_m^m
+    for (int m = 0; m <= p; m++) {
+      if (m > 0) {
+        double inv = -1.0 / (double)(2 * m);
+        double tr = fma(X, dr, -Y * di), ti = fma(X, di, Y * dr);
+        dr = tr * inv;
+        di = ti * inv;
+      }
+      double yr = dr, yi2 = di, pr2 = 0.0, pi2 = 0.0;
+      for (int k = m; k <= p; k++) {
+        if (k > m) {
+          double kk = (double)(2 * k - 1) * Z, inv = 1.0 / (double)((k + m) * (k - m));
+          double vr = fma(kk, yr, -r2 * pr2) * inv, vi = fma(kk, yi2, -r2 * pi2) * inv;
+          pr2 = yr;
+          pi2 = yi2;
+          yr = vr;
+          yi2 = vi;
+        }
+        // Y_k^m = (yr, yi2); contributions of +m and -m terms
+        double w = m == 0 ? 1.0 : 2.0;
+        double Lr = L[2 * cidx(k, m)], Li = L[2 * cidx(k, m) + 1];
+        s00 = fma(w, fma(Lr, yr, Li * yi2), s00);
+        if (k + 1 <= p) {
+          double Ur = L[2 * cidx(k + 1, m)], Ui = L[2 * cidx(k + 1, m) + 1];
+          s10 = fma(w, fma(Ur, yr, Ui * yi2), s10);
+          // + L_{k+1}^{m+1} conj(Y_k^m)
+          double Vr = L[2 * cidx(k + 1, m + 1)], Vi = L[2 * cidx(k + 1, m + 1) + 1];
+          s11r = fma(Vr, yr, fma(Vi, yi2, s11r));
+          s11i = fma(Vi, yr, fma(-Vr, yi2, s11i));
+          if (m >= 2) {  // the -m term: -conj(L_{k+1}^{m-1}) Y_k^m
+            double Wr = L[2 * cidx(k + 1, m - 1)], Wi = L[2 * cidx(k + 1, m - 1) + 1];
+            s11r = fma(-Wr, yr, fma(-Wi, yi2, s11r));
+            s11i = fma(-Wr, yi2, fma(Wi, yr, s11i));
+          } else if (m == 1) {  // the -1 term: -L_{k+1}^0 Y_k^1
+            double Wr = L[2 * cidx(k + 1, 0)], Wi = L[2 * cidx(k + 1, 0) + 1];
+            s11r = fma(-Wr, yr, fma(Wi, yi2, s11r));
+            s11i = fma(-Wr, yi2, fma(-Wi, yr, s11i));
+          }
+        }
+      }
+    }
+    double ax = -s11r, ay = -s11i, az = s10, ph = -s00;
+    // ---- P2P
+    double nx = 0.0, ny = 0.0, nz = 0.0, np = 0.0;
+    for (int q = off[B]; q < off[B + 1]; q++) {
+      int A = srcl[q];
+      int jb = cb[A], je = ce[A];
+      for (int j = jb; j < je; j++) {
+        double dx = sx[j] - xi, dy = sy[j] - yi, dz = sz[j] - zi;
+        double d2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+        double rinv = rsqrt_d(d2);
+        rinv = (j != i && d2 > 0.0) ? rinv : 0.0;
+        double mr = sm[j] * rinv;
+        double mr3 = mr * rinv * rinv;
+        nx = fma(mr3, dx, nx);
+        ny = fma(mr3, dy, ny);
+        nz = fma(mr3, dz, nz);
+        np -= mr;
+      }
+    }
+    if (act) {
+      int o = perm[i];
+      acc[3 * (int64_t)o] = ax + nx;
+      acc[3 * (int64_t)o + 1] = ay + ny;
+      acc[3 * (int64_t)o + 2] = az + nz;
+      pot[o] = ph + np;
+    }
+  }
+}
+
+void launch_leaf_eval(Ctx& c, const int* leaves, double* acc, double* pot) {
+  unsigned grid = 8u * (unsigned)((c.nleaf + 7) / 8);
+  hipLaunchKernelGGL(k_leaf_eval, dim3(grid), dim3(64), 0, c.stream, c.p, leaves, (int)c.nleaf,
+                     c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.c_cx.p, c.c_cy.p, c.c_cz.p,
+                     c.loc.p, c.sx.p, c.sy.p, c.sz.p, c.sm.p, c.idx[0].p, c.eps_soft * c.eps_soft, acc,
+                     pot);
+  HIPCHK(hipGetLastError());
+}
+
+void launch_l2l(Ctx& c) {
+  for (int level = 1; level <= c.depth; level++) {
+    int first = c.lvl_first[level], count = c.lvl_count[level];
+    hipLaunchKernelGGL(k_l2l, dim3(count), dim3(64), 0, c.stream, c.p, first, count, c.c_parent.p,
+                       c.c_cx.p, c.c_cy.p, c.c_cz.p, c.loc.p);
+  }
+  HIPCHK(hipGetLastError());
+}
+
+// ---- plain direct sum (FP64, compensated accumulation), LDS source tiles
+constexpr int DS_T = 256;
+
+__device__ __forceinline__ void two_sum_acc(double& s, double& c, double v) {
+  double t = s + v;
+  double bp = t - s;
+  c += (s - (t - bp)) + (v - bp);
+  s = t;
+}
+
+__global__ void __launch_bounds__(DS_T) k_direct(int64_t n, const double* pos, const double* mass,
+                                                 double eps2, int64_t nsink, const int32_t* sinks,
+                                                 double* acc, double* pot) {
+  __shared__ double tx[DS_T], ty[DS_T], tz[DS_T], tm[DS_T];
+  int64_t s = (int64_t)blockIdx.x * DS_T + threadIdx.x;
+  bool act = s < nsink;
+  int64_t i = act ? (sinks ? sinks[s] : s) : 0;
+  double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+  double ax = 0, cxx = 0, ay = 0, cyy = 0, az = 0, czz = 0, ph = 0, cph = 0;
+  for (int64_t j0 = 0; j0 < n; j0 += DS_T) {
+    int64_t j = j0 + threadIdx.x;
+    if (j < n) {
+      tx[threadIdx.x] = pos[3 * j];
+      ty[threadIdx.x] = pos[3 * j + 1];
+      tz[threadIdx.x] = pos[3 * j + 2];
+      tm[threadIdx.x] = mass[j];
+    }
+    __syncthreads();
+    int lim = (int)(n - j0 < DS_T ? n - j0 : DS_T);
+    for (int t = 0; t < lim; t++) {
+      double dx = tx[t] - xi, dy = ty[t] - yi, dz = tz[t] - zi;
+      double d2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+      bool ok = (j0 + t != i) && d2 > 0.0;
+      double rinv = ok ? 1.0 / sqrt(d2) : 0.0;
+      double mr = tm[t] * rinv, mr3 = mr * rinv * rinv;
+      two_sum_acc(ax, cxx, mr3 * dx);
+      two_sum_acc(ay, cyy, mr3 * dy);
+      two_sum_acc(az, czz, mr3 * dz);
+      two_sum_acc(ph, cph, -mr);
+    }
+    __syncthreads();
+  }
+  if (act) {
+    acc[3 * s] = ax + cxx;
+    acc[3 * s + 1] = ay + cyy;
+    acc[3 * s + 2] = az + czz;
+    pot[s] = ph + cph;
+  }
+}
+
+void direct_sum(int64_t n, const double* pos, const double* mass, double eps2, int64_t nsink,
+                const int32_t* sinks, double* acc, double* pot, hipStream_t s) {
+  hipLaunchKernelGGL(k_direct, dim3((unsigned)ceil_div(nsink, DS_T)), dim3(DS_T), 0, s, n, pos, mass,
+                     eps2, nsink, sinks, acc, pot);
+  HIPCHK(hipGetLastError());
+}
+
+// ---- input validation (optional): non-finite positions, negative / NaN masses
+__global__ void k_check(const double* pos, const double* mass, int64_t n, int* bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  bool ok = isfinite(pos[3 * i]) && isfinite(pos[3 * i + 1]) && isfinite(pos[3 * i + 2]) &&
+            isfinite(mass[i]) && mass[i] >= 0.0;
+  if (!ok) atomicOr(bad, 1);
+}
+
+bool check_inputs_dev(Ctx& c, const double* pos, const double* mass, int64_t n) {
+  ensure(c.ws, c.counters, 64);
+  int* bad = c.counters.p + 32;
+  HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), c.stream));
+  hipLaunchKernelGGL(k_check, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c.stream, pos, mass, n, bad);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c.hbuf, bad, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(hipStreamSynchronize(c.stream));
+  return ((int*)c.hbuf)[0] == 0;
+}
+
+}  // namespace fmm

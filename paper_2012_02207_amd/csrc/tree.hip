@@ -1,0 +1,602 @@
+// Tree construction on gfx950: root box, 63-bit Morton keys, stable LSD radix
+// sort, sorted SoA gather, breadth-first cells, masses, centres and radii.
+//
+// The paper builds an octree over the bodies (section 2.1, flowchart caption)
+// and reuses the tree of its base code without describing it; the reading
+// implemented here: cubic root box over the bodies' extent, 21 bits per axis,
+// x most significant within each octal digit, a stable sort (ties keep the
+// caller's order), cells = maximal runs of keys sharing a prefix, a cell with
+// more than n_leaf bodies split into its non-empty octants (unless at level 21),
+// ids breadth first (by level, then key order).  Expansion centre = centre of
+// mass; size = largest distance of a body from it (section 2.3, "sizes").
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "fmm_device.h"
+
+namespace fmm {
+
+// ===================================================================== scan
+constexpr int SCAN_T = 256, SCAN_I = 8, SCAN_TILE = SCAN_T * SCAN_I;
+
+__device__ inline int block_excl_scan(int v, int* sh, int& total) {
+  // sh: SCAN_T ints; returns exclusive prefix of v over the block
+  int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int o = 1; o < SCAN_T; o <<= 1) {
+    int a = t >= o ? sh[t - o] : 0;
+    __syncthreads();
+    sh[t] += a;
+    __syncthreads();
+  }
+  total = sh[SCAN_T - 1];
+  int ex = sh[t] - v;
+  __syncthreads();
+  return ex;
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_reduce(const int* in, int64_t n, int* bsum) {
+  __shared__ int sh[SCAN_T];
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  int s = 0;
+  for (int i = 0; i < SCAN_I; i++) {
+    int64_t j = base + (int64_t)i * SCAN_T + threadIdx.x;
+    if (j < n) s += in[j];
+  }
+  int tot;
+  block_excl_scan(s, sh, tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// exclusive scan of one tile per block, plus a per-block offset
+__global__ void __launch_bounds__(SCAN_T) k_scan_apply(const int* in, int* out, int64_t n,
+                                                      const int* boff, long long* total,
+                                                      int64_t nblocks) {
+  __shared__ int sh[SCAN_T];
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_I;
+  int v[SCAN_I];
+  int s = 0;
+  for (int i = 0; i < SCAN_I; i++) {
+    int64_t j = base + i;
+    v[i] = j < n ? in[j] : 0;
+    s += v[i];
+  }
+  int tot;
+  int ex = block_excl_scan(s, sh, tot);
+  int off = (boff ? boff[blockIdx.x] : 0) + ex;
+  for (int i = 0; i < SCAN_I; i++) {
+    int64_t j = base + i;
+    if (j < n) out[j] = off;
+    off += v[i];
+  }
+  if (total && blockIdx.x == nblocks - 1 && threadIdx.x == SCAN_T - 1)
+    *total = (long long)(boff ? boff[blockIdx.x] : 0) + (long long)tot;
+}
+
+void exclusive_scan(Ctx& c, const int* in, int* out, int64_t n, long long* total_dev) {
+  // recursive three-phase scan; scratch from c.scan_tmp
+  std::vector<int64_t> sizes;
+  int64_t m = n;
+  while (m > SCAN_TILE) {
+    m = ceil_div(m, SCAN_TILE);
+    sizes.push_back(m);
+  }
+  size_t need = 0;
+  for (auto s : sizes) need += 2 * (size_t)s + 64;
+  ensure(c.ws, c.scan_tmp, need + 64);
+  if (n == 0) {
+    if (total_dev) HIPCHK(hipMemsetAsync(total_dev, 0, sizeof(long long), c.stream));
+    return;
+  }
+  if (sizes.empty()) {
+    hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(SCAN_T), 0, c.stream, in, out, n, nullptr,
+                       total_dev, (int64_t)1);
+    HIPCHK(hipGetLastError());
+    return;
+  }
+  // level 0
+  int* bsum = c.scan_tmp.p;
+  int* boff = bsum + sizes[0] + 32;
+  int64_t nb = sizes[0];
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SCAN_T), 0, c.stream, in, n, bsum);
+  HIPCHK(hipGetLastError());
+  // scan of block sums (recursive via a nested context-free call)
+  {
+    // temporarily carve the remaining scratch for the recursion
+    dbuf<int> saved = c.scan_tmp;
+    c.scan_tmp.p = boff + nb + 32;
+    c.scan_tmp.cap = saved.cap - (size_t)(c.scan_tmp.p - saved.p);
+    exclusive_scan(c, bsum, boff, nb, nullptr);
+    c.scan_tmp = saved;
+  }
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(SCAN_T), 0, c.stream, in, out, n, boff,
+                     total_dev, nb);
+  HIPCHK(hipGetLastError());
+}
+
+long long read_total(Ctx& c, const long long* total_dev) {
+  HIPCHK(hipMemcpyAsync(c.hbuf, total_dev, sizeof(long long), hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(hipStreamSynchronize(c.stream));
+  return c.hbuf[0];
+}
+
+// ===================================================================== root box
+constexpr int BB_T = 256;
+
+__global__ void __launch_bounds__(BB_T) k_bbox_partial(const double* pos, int64_t n, double* part) {
+  __shared__ double sh[6][BB_T];
+  double lo[3], hi[3];
+  int64_t i0 = (int64_t)blockIdx.x * BB_T + threadIdx.x;
+  int64_t first = i0 < n ? i0 : 0;
+  for (int d = 0; d < 3; d++) lo[d] = hi[d] = pos[3 * first + d];
+  for (int64_t i = i0; i < n; i += (int64_t)gridDim.x * BB_T)
+    for (int d = 0; d < 3; d++) {
+      double v = pos[3 * i + d];
+      if (v < lo[d]) lo[d] = v;
+      if (v > hi[d]) hi[d] = v;
+    }
+  for (int d = 0; d < 3; d++) {
+    sh[d][threadIdx.x] = lo[d];
+    sh[3 + d][threadIdx.x] = hi[d];
+  }
+  __syncthreads();
+  for (int o = BB_T / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+      for (int d = 0; d < 3; d++) {
+        double a = sh[d][threadIdx.x + o], b = sh[3 + d][threadIdx.x + o];
+        if (a < sh[d][threadIdx.x]) sh[d][threadIdx.x] = a;
+        if (b > sh[3 + d][threadIdx.x]) sh[3 + d][threadIdx.x] = b;
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// lo = min, L = largest extent (1 if zero), s = 2^21 / L  (rootbox = lo[3], L, s)
+__global__ void k_bbox_final(const double* part, int nb, double* rootbox) {
+  if (threadIdx.x != 0) return;
+  double lo[3], hi[3];
+  for (int d = 0; d < 3; d++) {
+    lo[d] = part[d];
+    hi[d] = part[3 + d];
+  }
+  for (int b = 1; b < nb; b++)
+    for (int d = 0; d < 3; d++) {
+      if (part[6 * b + d] < lo[d]) lo[d] = part[6 * b + d];
+      if (part[6 * b + 3 + d] > hi[d]) hi[d] = part[6 * b + 3 + d];
+    }
+  double L = hi[0] - lo[0];
+  if (hi[1] - lo[1] > L) L = hi[1] - lo[1];
+  if (hi[2] - lo[2] > L) L = hi[2] - lo[2];
+  if (L == 0.0) L = 1.0;
+  rootbox[0] = lo[0];
+  rootbox[1] = lo[1];
+  rootbox[2] = lo[2];
+  rootbox[3] = L;
+  rootbox[4] = 2097152.0 / L;
+}
+
+// ===================================================================== keys
+__device__ __forceinline__ uint64_t spread3(uint64_t x) {
+  x &= 0x1fffffull;
+  x = (x | (x << 32)) & 0x1f00000000ffffull;
+  x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+__device__ __forceinline__ uint64_t compact3(uint64_t x) {
+  x &= 0x1249249249249249ull;
+  x = (x ^ (x >> 2)) & 0x10c30c30c30c30c3ull;
+  x = (x ^ (x >> 4)) & 0x100f00f00f00f00full;
+  x = (x ^ (x >> 8)) & 0x1f0000ff0000ffull;
+  x = (x ^ (x >> 16)) & 0x1f00000000ffffull;
+  x = (x ^ (x >> 32)) & 0x1fffffull;
+  return x;
+}
+
+__global__ void k_keys(const double* pos, int64_t n, const double* rootbox, uint64_t* key, int* idx) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = rootbox[4];
+  uint64_t q[3];
+  for (int d = 0; d < 3; d++) {
+    double t = floor((pos[3 * i + d] - rootbox[d]) * s);
+    uint64_t v = (uint64_t)t;
+    q[d] = v > 2097151ull ? 2097151ull : v;
+  }
+  key[i] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+  idx[i] = (int)i;
+}
+
+// ===================================================================== radix sort
+// Stable LSD sort of (63-bit key, int payload), 8-bit digits.  Each block ranks a
+// tile of RS_TILE keys: waves walk their sub-tile in 64-key chunks, computing
+// for every key its rank among equal digits with 8 ballots, so the rank order
+// equals the input order (stability).  Global digit offsets come from an
+// exclusive scan over the digit-major block histograms.
+constexpr int RS_T = 256, RS_W = RS_T / 64, RS_I = 16, RS_TILE = RS_T * RS_I;
+
+__global__ void __launch_bounds__(RS_T) k_rs_hist(const uint64_t* key, int64_t n, int shift,
+                                                  int* hist, int nblocks) {
+  __shared__ int cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  for (int i = 0; i < RS_I; i++) {
+    int64_t j = base + (int64_t)i * RS_T + threadIdx.x;
+    if (j < n) atomicAdd(&cnt[(key[j] >> shift) & 255], 1);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t* kin, const int* vin,
+                                                     uint64_t* kout, int* vout, int64_t n,
+                                                     int shift, const int* offs, int nblocks) {
+  __shared__ int wcnt[RS_W][256];
+  __shared__ int goff[256];
+  int w = threadIdx.x >> 6;
+  int lane = threadIdx.x & 63;
+  for (int t = threadIdx.x; t < RS_W * 256; t += RS_T) (&wcnt[0][0])[t] = 0;
+  goff[threadIdx.x] = offs[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * RS_TILE + (int64_t)w * (RS_TILE / RS_W);
+  uint64_t k[RS_I];
+  int v[RS_I], rank[RS_I];
+  uint64_t lt = lanemask_lt();
+  for (int c = 0; c < RS_I; c++) {
+    int64_t j = base + (int64_t)c * 64 + lane;
+    bool valid = j < n;
+    k[c] = valid ? kin[j] : 0;
+    v[c] = valid ? vin[j] : 0;
+    int d = (int)((k[c] >> shift) & 255);
+    uint64_t peers = ballot(valid);
+    for (int b = 0; b < 8; b++) {
+      bool bit = (d >> b) & 1;
+      uint64_t bb = ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    int before = __popcll(peers & lt);
+    int cnt = wcnt[w][d];
+    rank[c] = cnt + before;
+    // the highest peer publishes the new running count for this digit
+    if (valid && (peers >> lane) == 1ull) wcnt[w][d] = cnt + __popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  {
+    int d = threadIdx.x, s = 0;
+    for (int ww = 0; ww < RS_W; ww++) {
+      int t = wcnt[ww][d];
+      wcnt[ww][d] = s;
+      s += t;
+    }
+  }
+  __syncthreads();
+  for (int c = 0; c < RS_I; c++) {
+    int64_t j = base + (int64_t)c * 64 + lane;
+    if (j >= n) continue;
+    int d = (int)((k[c] >> shift) & 255);
+    int64_t dst = (int64_t)goff[d] + wcnt[w][d] + rank[c];
+    if (dst < n) {  // always true when the ranks are consistent with the histogram
+      kout[dst] = k[c];
+      vout[dst] = v[c];
+    }
+  }
+}
+
+// sorts c.key[0]/c.idx[0] (n entries) over bits [0, nbits); result in key[0]/idx[0]
+void radix_sort_keys(Ctx& c, int64_t n, int nbits) {
+  int nb = (int)ceil_div(n, RS_TILE);
+  ensure(c.ws, c.sort_hist, (size_t)256 * nb * 2 + 64);
+  int* hist = c.sort_hist.p;
+  int* offs = hist + (size_t)256 * nb;
+  int src = 0;
+  for (int shift = 0; shift < nbits; shift += 8) {
+    hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_T), 0, c.stream, c.key[src].p, n, shift, hist, nb);
+    HIPCHK(hipGetLastError());
+    exclusive_scan(c, hist, offs, (int64_t)256 * nb, nullptr);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(RS_T), 0, c.stream, c.key[src].p, c.idx[src].p,
+                       c.key[1 - src].p, c.idx[1 - src].p, n, shift, offs, nb);
+    HIPCHK(hipGetLastError());
+    src = 1 - src;
+  }
+  if (src != 0) {
+    std::swap(c.key[0], c.key[1]);
+    std::swap(c.idx[0], c.idx[1]);
+  }
+}
+
+__global__ void k_gather(const double* pos, const double* mass, const int* idx, int64_t n, double* sx,
+                         double* sy, double* sz, double* sm) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int o = idx[i];
+  sx[i] = pos[3 * (int64_t)o];
+  sy[i] = pos[3 * (int64_t)o + 1];
+  sz[i] = pos[3 * (int64_t)o + 2];
+  sm[i] = mass[o];
+}
+
+// ===================================================================== cells
+__device__ inline int octant_lower_bound(const uint64_t* key, int b, int e, int o, int shift) {
+  // first index in [b, e) whose digit (at `shift`) is >= o; digits are non-decreasing
+  int lo = b, hi = e;
+  while (lo < hi) {
+    int mid = lo + ((hi - lo) >> 1);
+    int d = (int)((key[mid] >> shift) & 7);
+    if (d < o)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_split_level(int first, int count, int level, int n_leaf, const uint64_t* key,
+                              const int* cb, const int* ce, int* split, int* nch) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  int c = first + t;
+  int b = cb[c], e = ce[c];
+  int cnt = 0;
+  if (e - b > n_leaf && level < FMM_MAX_LEVEL) {
+    int shift = 3 * (FMM_MAX_LEVEL - (level + 1));
+    int prev = b;
+    split[9 * t] = b;
+    for (int o = 1; o <= 8; o++) {
+      int s = o < 8 ? octant_lower_bound(key, prev, e, o, shift) : e;
+      split[9 * t + o] = s;
+      if (s > prev) cnt++;
+      prev = s;
+    }
+  }
+  nch[t] = cnt;
+}
+
+__global__ void k_emit_children(int first, int count, int level, int next_first, const int* split,
+                                const int* nch, const int* choff, int* c_level, int* c_begin,
+                                int* c_end, int* c_parent, int* c_child0, int* c_nchild) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  int c = first + t;
+  int k = nch[t];
+  c_nchild[c] = k;
+  if (k == 0) {
+    c_child0[c] = -1;
+    return;
+  }
+  int id = next_first + choff[t];
+  c_child0[c] = id;
+  for (int o = 0; o < 8; o++) {
+    int s0 = split[9 * t + o], s1 = split[9 * t + o + 1];
+    if (s1 > s0) {
+      c_level[id] = level + 1;
+      c_begin[id] = s0;
+      c_end[id] = s1;
+      c_parent[id] = c;
+      id++;
+    }
+  }
+}
+
+__global__ void k_root(int n, int* c_level, int* c_begin, int* c_end, int* c_parent) {
+  c_level[0] = 0;
+  c_begin[0] = 0;
+  c_end[0] = n;
+  c_parent[0] = -1;
+}
+
+// mass, first moments and centre of mass, one level (deepest first); leaves sum
+// their bodies in sorted order, internal cells their children in octant order
+__global__ void k_mass_com(int first, int count, int level, const int* cb, const int* ce,
+                           const int* c0, const int* nch, const double* sx, const double* sy,
+                           const double* sz, const double* sm, const uint64_t* key,
+                           const double* rootbox, double* cm, double* csx, double* csy, double* csz,
+                           double* cx, double* cy, double* cz) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  int c = first + t;
+  double M = 0.0, X = 0.0, Y = 0.0, Z = 0.0;
+  if (nch[c] == 0) {
+    for (int i = cb[c]; i < ce[c]; i++) {
+      double m = sm[i];
+      M = M + m;
+      X = X + m * sx[i];
+      Y = Y + m * sy[i];
+      Z = Z + m * sz[i];
+    }
+  } else {
+    for (int k = c0[c]; k < c0[c] + nch[c]; k++) {
+      M = M + cm[k];
+      X = X + csx[k];
+      Y = Y + csy[k];
+      Z = Z + csz[k];
+    }
+  }
+  cm[c] = M;
+  csx[c] = X;
+  csy[c] = Y;
+  csz[c] = Z;
+  if (M != 0.0) {
+    cx[c] = X / M;
+    cy[c] = Y / M;
+    cz[c] = Z / M;
+  } else {  // massless cell: centre of its cubic box
+    uint64_t k0 = key[cb[c]];
+    int sh = FMM_MAX_LEVEL - level;
+    double h = ldexp(rootbox[3], -level);
+    double q0 = (double)(compact3(k0 >> 2) >> sh), q1 = (double)(compact3(k0 >> 1) >> sh),
+           q2 = (double)(compact3(k0) >> sh);
+    cx[c] = rootbox[0] + (q0 + 0.5) * h;
+    cy[c] = rootbox[1] + (q1 + 0.5) * h;
+    cz[c] = rootbox[2] + (q2 + 0.5) * h;
+  }
+}
+
+// radius: exact max over each cell's bodies of the squared distance to its
+// centre (order independent), in chunks of RAD_CH bodies
+constexpr int RAD_T = 256, RAD_CH = 2048;
+
+__global__ void k_rad_chunks(const int* cb, const int* ce, int ncell, int* nchunk) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  nchunk[c] = (int)ceil_div(ce[c] - cb[c], RAD_CH);
+}
+
+__global__ void __launch_bounds__(RAD_T) k_radius(const int* cb, const int* ce, const int* choff,
+                                                 int ncell, const double* sx, const double* sy,
+                                                 const double* sz, const double* cx, const double* cy,
+                                                 const double* cz, unsigned long long* r2bits) {
+  __shared__ double sh[RAD_T];
+  int blk = blockIdx.x;
+  // cell owning this chunk: last c with choff[c] <= blk
+  int lo = 0, hi = ncell - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (choff[mid] <= blk)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  int c = lo;
+  int64_t b = cb[c] + (int64_t)(blk - choff[c]) * RAD_CH;
+  int64_t e = b + RAD_CH < ce[c] ? b + RAD_CH : ce[c];
+  double x0 = cx[c], y0 = cy[c], z0 = cz[c];
+  double best = 0.0;
+  for (int64_t i = b + threadIdx.x; i < e; i += RAD_T) {
+    double dx = sx[i] - x0, dy = sy[i] - y0, dz = sz[i] - z0;
+    double d2 = (dx * dx + dy * dy) + dz * dz;
+    if (d2 > best) best = d2;
+  }
+  sh[threadIdx.x] = best;
+  __syncthreads();
+  for (int o = RAD_T / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o && sh[threadIdx.x + o] > sh[threadIdx.x]) sh[threadIdx.x] = sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(&r2bits[c], (unsigned long long)__double_as_longlong(sh[0]));
+}
+
+__global__ void k_radius_final(const unsigned long long* r2bits, int ncell, double* rad) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  rad[c] = sqrt(__longlong_as_double((long long)r2bits[c]));
+}
+
+__global__ void k_leaf_of(const int* cb, const int* ce, const int* nch, int ncell, int* leaf_of) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell || nch[c] != 0) return;
+  for (int i = cb[c]; i < ce[c]; i++) leaf_of[i] = c;
+}
+
+static inline dim3 grid1(int64_t n, int t = 256) { return dim3((unsigned)ceil_div(n, t)); }
+
+void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
+  hipStream_t s = c.stream;
+  c.n = n;
+  for (int k = 0; k < 2; k++) {
+    ensure(c.ws, c.key[k], n);
+    ensure(c.ws, c.idx[k], n);
+  }
+  ensure(c.ws, c.sx, n);
+  ensure(c.ws, c.sy, n);
+  ensure(c.ws, c.sz, n);
+  ensure(c.ws, c.sm, n);
+  ensure(c.ws, c.leaf_of, n);
+  ensure(c.ws, c.rootbox, 8);
+  int nbb = (int)std::min<int64_t>(1024, ceil_div(n, BB_T));
+  ensure(c.ws, c.bbox_part, (size_t)6 * nbb);
+  hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(BB_T), 0, s, pos, n, c.bbox_part.p);
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, c.bbox_part.p, nbb, c.rootbox.p);
+  hipLaunchKernelGGL(k_keys, grid1(n), dim3(256), 0, s, pos, n, c.rootbox.p, c.key[0].p, c.idx[0].p);
+  HIPCHK(hipGetLastError());
+  radix_sort_keys(c, n, 64);
+  hipLaunchKernelGGL(k_gather, grid1(n), dim3(256), 0, s, pos, mass, c.idx[0].p, n, c.sx.p, c.sy.p,
+                     c.sz.p, c.sm.p);
+  HIPCHK(hipGetLastError());
+
+  // breadth-first levels
+  size_t cap = (size_t)std::max<int64_t>(1024, 4 * n / std::max(1, c.prm.n_leaf) + 64);
+  auto ensure_cells = [&](size_t need, bool keep) {
+    ensure(c.ws, c.c_level, need, keep, s);
+    ensure(c.ws, c.c_begin, need, keep, s);
+    ensure(c.ws, c.c_end, need, keep, s);
+    ensure(c.ws, c.c_parent, need, keep, s);
+    ensure(c.ws, c.c_child0, need, keep, s);
+    ensure(c.ws, c.c_nchild, need, keep, s);
+  };
+  ensure_cells(cap, false);
+  hipLaunchKernelGGL(k_root, dim3(1), dim3(1), 0, s, (int)n, c.c_level.p, c.c_begin.p, c.c_end.p,
+                     c.c_parent.p);
+  c.lvl_first.assign(1, 0);
+  c.lvl_count.assign(1, 1);
+  int64_t total_cells = 1;
+  ensure(c.ws, c.counters, 64);
+  long long* tot = (long long*)c.counters.p;
+  for (int level = 0;; level++) {
+    int first = c.lvl_first[level], count = c.lvl_count[level];
+    ensure(c.ws, c.c_split, (size_t)count * 11 + 64);
+    int* split = c.c_split.p;
+    int* nch = split + (size_t)9 * count;
+    int* choff = nch + count;
+    hipLaunchKernelGGL(k_split_level, grid1(count), dim3(256), 0, s, first, count, level,
+                       c.prm.n_leaf, c.key[0].p, c.c_begin.p, c.c_end.p, split, nch);
+    HIPCHK(hipGetLastError());
+    exclusive_scan(c, nch, choff, count, tot);
+    long long next = read_total(c, tot);
+    if ((size_t)(total_cells + next) > c.c_level.cap) ensure_cells((size_t)(total_cells + next) * 2, true);
+    hipLaunchKernelGGL(k_emit_children, grid1(count), dim3(256), 0, s, first, count, level,
+                       (int)total_cells, split, nch, choff, c.c_level.p, c.c_begin.p, c.c_end.p,
+                       c.c_parent.p, c.c_child0.p, c.c_nchild.p);
+    HIPCHK(hipGetLastError());
+    if (next == 0) break;
+    c.lvl_first.push_back((int)total_cells);
+    c.lvl_count.push_back((int)next);
+    total_cells += next;
+  }
+  c.ncell = total_cells;
+  c.depth = (int)c.lvl_first.size() - 1;
+  int nc = (int)c.ncell;
+
+  ensure(c.ws, c.c_mass, nc);
+  ensure(c.ws, c.c_sx, nc);
+  ensure(c.ws, c.c_sy, nc);
+  ensure(c.ws, c.c_sz, nc);
+  ensure(c.ws, c.c_cx, nc);
+  ensure(c.ws, c.c_cy, nc);
+  ensure(c.ws, c.c_cz, nc);
+  ensure(c.ws, c.c_rad, nc);
+  ensure(c.ws, c.c_rad2bits, nc);
+  for (int level = c.depth; level >= 0; level--) {
+    int first = c.lvl_first[level], count = c.lvl_count[level];
+    hipLaunchKernelGGL(k_mass_com, grid1(count, 128), dim3(128), 0, s, first, count, level,
+                       c.c_begin.p, c.c_end.p, c.c_child0.p, c.c_nchild.p, c.sx.p, c.sy.p, c.sz.p,
+                       c.sm.p, c.key[0].p, c.rootbox.p, c.c_mass.p, c.c_sx.p, c.c_sy.p, c.c_sz.p,
+                       c.c_cx.p, c.c_cy.p, c.c_cz.p);
+    HIPCHK(hipGetLastError());
+  }
+  // radii
+  ensure(c.ws, c.c_split, (size_t)2 * nc + 64);
+  int* nchunk = c.c_split.p;
+  int* choff = nchunk + nc + 32;
+  hipLaunchKernelGGL(k_rad_chunks, grid1(nc), dim3(256), 0, s, c.c_begin.p, c.c_end.p, nc, nchunk);
+  exclusive_scan(c, nchunk, choff, nc, tot);
+  long long nchunks = read_total(c, tot);
+  HIPCHK(hipMemsetAsync(c.c_rad2bits.p, 0, sizeof(unsigned long long) * nc, s));
+  hipLaunchKernelGGL(k_radius, dim3((unsigned)nchunks), dim3(RAD_T), 0, s, c.c_begin.p, c.c_end.p,
+                     choff, nc, c.sx.p, c.sy.p, c.sz.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.c_rad2bits.p);
+  hipLaunchKernelGGL(k_radius_final, grid1(nc), dim3(256), 0, s, c.c_rad2bits.p, nc, c.c_rad.p);
+  hipLaunchKernelGGL(k_leaf_of, grid1(nc), dim3(256), 0, s, c.c_begin.p, c.c_end.p, c.c_nchild.p, nc,
+                     c.leaf_of.p);
+  HIPCHK(hipGetLastError());
+  // leaf count (host, from the level loop is not available): count on device via scan of flags
+  c.nleaf = -1;  // filled lazily by fmm_stats
+}
+
+}  // namespace fmm

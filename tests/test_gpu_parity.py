@@ -1,0 +1,197 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bit-exact: Morton keys, sort order, cells, centres, radii, multipoles, P_k,
+the scalar-force estimate (per body and per cell) and the interaction lists
+(compared as sets).  Floating point: accelerations and potentials agree with
+the oracle's FP64 pass to a median relative difference <= 1e-12 (both sides
+are FP64 with different summation orders; the bound is ~1e4 ulps of headroom
+over the rounding of a few thousand terms) and a max of 1e-9."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2012_02207_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fmm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2012_02207_amd import fmm as F
+    return F
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _run(F, pos, mass, p, eps, n_leaf, stage="eval", mac="error", theta=1.0, eps_soft=0.0):
+    print(f"[gpu] N={len(mass)} p={p} eps={eps} n_leaf={n_leaf} mac={mac}", flush=True)
+    f = F.FMM(p=p, err_tol=eps, n_leaf=n_leaf, mac=mac, theta=theta)
+    acc, pot = f.forces(_dev(pos), _dev(mass), eps_soft=eps_soft)
+    torch.cuda.synchronize()
+    o = oracle.Oracle()
+    oacc, opot = o.run(pos, mass, p=p, err_tol=eps, n_leaf=n_leaf, mac=mac, theta=theta,
+                       eps_soft=eps_soft, stage=stage)
+    return f, acc.cpu().numpy(), pot.cpu().numpy(), o, oacc, opot
+
+
+def _sorted_pairs(a):
+    a = np.asarray(a, dtype=np.int64).reshape(-1, 2)
+    return a[np.lexsort((a[:, 1], a[:, 0]))]
+
+
+CASES = [
+    ("plummer_4k", lambda: W.plummer(4096, W.SEED_BASE)[::2], 6, 1e-6, 64),
+    ("plummer_3k_leaf16", lambda: W.plummer(3000, 7)[::2], 8, 1e-7, 16),
+    ("cube_ties_leaf8", lambda: _ties(), 4, 1e-5, 8),
+]
+
+
+def _ties():
+    pos, mass = W.uniform_cube(2500, 3)
+    pos[::5] = np.round(pos[::5], 1)
+    pos[7] = pos[8]
+    return pos, mass
+
+
+@pytest.mark.parametrize("name,gen,p,eps,n_leaf", CASES, ids=[c[0] for c in CASES])
+def test_tree_estimate_lists_bit_exact(fmm, name, gen, p, eps, n_leaf):
+    pos, mass = gen()
+    f, acc, pot, o, oacc, opot = _run(fmm, pos, mass, p, eps, n_leaf)
+    assert np.array_equal(f.export("keys"), o.get("keys"))
+    assert np.array_equal(f.export("perm").astype(np.int64), o.get("perm"))
+    assert np.array_equal(f.export("rootbox"), o.get("rootbox"))
+    for k in ("cell_level", "cell_begin", "cell_end", "cell_parent", "cell_child0", "cell_nchild"):
+        assert np.array_equal(f.export(k).astype(np.int64), o.get(k).astype(np.int64)), k
+    for k in ("cell_mass", "cell_com", "cell_rad", "mult", "pk", "fcell_est", "f_part", "fmin"):
+        g, r = f.export(k), o.get(k)
+        assert g.shape == r.shape and np.array_equal(g, r), (k, np.abs(g - r).max())
+    for k in ("est_far", "est_near", "m2l", "p2p"):
+        assert np.array_equal(_sorted_pairs(f.export(k)), _sorted_pairs(o.get(k))), k
+
+
+@pytest.mark.parametrize("name,gen,p,eps,n_leaf", CASES, ids=[c[0] for c in CASES])
+def test_forces_match_oracle(fmm, name, gen, p, eps, n_leaf):
+    pos, mass = gen()
+    f, acc, pot, o, oacc, opot = _run(fmm, pos, mass, p, eps, n_leaf)
+    rel = np.linalg.norm(acc - oacc, axis=1) / np.linalg.norm(oacc, axis=1)
+    relp = np.abs(pot - opot) / np.abs(opot)
+    assert np.median(rel) <= 1e-12 and rel.max() <= 1e-9, (np.median(rel), rel.max())
+    assert np.median(relp) <= 1e-12 and relp.max() <= 1e-9
+    loc_g, loc_o = f.export("local"), o.get("local")
+    scale = np.abs(loc_o).max(axis=1, keepdims=True) + 1e-300
+    assert np.median(np.abs(loc_g - loc_o) / scale) < 1e-12
+
+
+def test_config_4k_accuracy_vs_direct(fmm):
+    """The 4096-body Plummer configuration: p = 6, epsilon = 1e-6, FP64,
+    checked against the O(N^2) direct sum (median below epsilon, section 4.1)."""
+    cfg = W.CONFIGS["plummer_4k"]
+    pos, _, mass = W.plummer(cfg["n"], cfg["seed"])
+    f, acc, pot, o, oacc, opot = _run(fmm, pos, mass, cfg["p"], cfg["err_tol"], 64)
+    ad, pd = oracle.direct(pos, mass)
+    err = np.linalg.norm(acc - ad, axis=1) / np.linalg.norm(ad, axis=1)
+    assert np.median(err) < cfg["err_tol"]
+    rel = np.linalg.norm(acc - oacc, axis=1) / np.linalg.norm(oacc, axis=1)
+    assert np.median(rel) <= 1e-12
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 5, 9, 12, 16])
+def test_orders(fmm, p):
+    pos, _, mass = W.plummer(1500, 100 + p)
+    f, acc, pot, o, oacc, opot = _run(fmm, pos, mass, p, 1e-5, 16)
+    assert np.array_equal(_sorted_pairs(f.export("m2l")), _sorted_pairs(o.get("m2l")))
+    rel = np.linalg.norm(acc - oacc, axis=1) / np.linalg.norm(oacc, axis=1)
+    assert np.median(rel) <= 1e-12 and rel.max() <= 1e-9, (p, np.median(rel), rel.max())
+
+
+def test_geometric_mac_and_softening(fmm):
+    pos, _, mass = W.plummer(2000, 9)
+    f, acc, pot, o, oacc, opot = _run(fmm, pos, mass, 6, 1e-6, 32, mac="geometric", theta=0.6,
+                                      eps_soft=1.0 / 2000)
+    rel = np.linalg.norm(acc - oacc, axis=1) / np.linalg.norm(oacc, axis=1)
+    assert np.median(rel) <= 1e-12
+    assert np.array_equal(_sorted_pairs(f.export("p2p")), _sorted_pairs(o.get("p2p")))
+
+
+def test_large_leaves_and_level21(fmm):
+    """n_leaf above a wavefront (bodies looped in chunks) and duplicate bodies
+    that stop at level 21 with more than n_leaf bodies in a leaf."""
+    pos, _, mass = W.plummer(3000, 10)
+    pos[100:400] = pos[100]
+    f, acc, pot, o, oacc, opot = _run(fmm, pos, mass, 5, 1e-6, 100)
+    assert np.array_equal(f.export("keys"), o.get("keys"))
+    assert np.array_equal(f.export("cell_end"), o.get("cell_end").astype(np.int32))
+    rel = np.linalg.norm(acc - oacc, axis=1) / np.linalg.norm(oacc, axis=1)
+    assert np.median(rel) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 65])
+def test_tiny(fmm, n):
+    rng = np.random.default_rng(n)
+    pos = rng.normal(size=(n, 3))
+    mass = rng.uniform(0.5, 1, n)
+    f, acc, pot, o, oacc, opot = _run(fmm, pos, mass, 4, 1e-6, 64)
+    np.testing.assert_allclose(acc, oacc, rtol=1e-13, atol=1e-300)
+    np.testing.assert_allclose(pot, opot, rtol=1e-13, atol=1e-300)
+    if n == 1:
+        assert np.all(acc == 0) and pot[0] == 0
+
+
+def test_identical_bodies(fmm):
+    pos = np.tile([[0.3, -0.2, 0.1]], (50, 1))
+    mass = np.full(50, 0.02)
+    f, acc, pot, o, oacc, opot = _run(fmm, pos, mass, 4, 1e-6, 8)
+    assert np.all(acc == 0) and np.all(pot == 0)
+    assert np.array_equal(acc, oacc)
+
+
+def test_deterministic(fmm):
+    pos, _, mass = W.plummer(4000, 11)
+    f = fmm.FMM(p=8, err_tol=1e-7, n_leaf=32)
+    a1, p1 = f.forces(_dev(pos), _dev(mass))
+    a2, p2 = f.forces(_dev(pos), _dev(mass))
+    assert torch.equal(a1, a2) and torch.equal(p1, p2)
+
+
+def test_gpu_direct_matches_oracle(fmm):
+    pos, _, mass = W.plummer(3000, 12)
+    sinks = np.arange(0, 3000, 7, dtype=np.int32)
+    acc, pot = fmm.direct(_dev(pos), _dev(mass), sinks=_dev(sinks))
+    ad, pd = oracle.direct(pos, mass, sinks=sinks.astype(np.int64))
+    np.testing.assert_allclose(acc.cpu().numpy(), ad, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(pot.cpu().numpy(), pd, rtol=1e-14)
+
+
+def test_errors(fmm):
+    F = fmm
+    with pytest.raises(F.FmmError):
+        F.FMM(p=0)
+    with pytest.raises(F.FmmError):
+        F.FMM(n_leaf=0)
+    f = F.FMM(p=4, check_inputs=True)
+    pos, _, mass = W.plummer(100, 1)
+    bad = pos.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(F.FmmError) as e:
+        f.forces(_dev(bad), _dev(mass))
+    assert e.value.status == F.FMM_EDATA
+    with pytest.raises(F.FmmError) as e:
+        f.forces(_dev(pos), _dev(mass), p=40)
+    assert e.value.status == F.FMM_EINVAL
+    with pytest.raises(ValueError):
+        f.forces(_dev(pos.astype(np.float32)), _dev(mass))
+    g = F.FMM(p=4)
+    g.set_workspace_limit(1024)
+    with pytest.raises(F.FmmError) as e:
+        g.forces(_dev(pos), _dev(mass))
+    assert e.value.status == F.FMM_ENOMEM
+    # the context stays usable after an error
+    g.set_workspace_limit(0)
+    acc, pot = g.forces(_dev(pos), _dev(mass))
+    assert torch.isfinite(acc).all()
