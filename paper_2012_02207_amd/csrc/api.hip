@@ -37,10 +37,7 @@ void ws_free(Workspace& w, void* p, size_t bytes) {
   w.bytes -= bytes;
 }
 
-// leaves list, built by the upward pass at this offset of c_split
-static const int* leaves_of(Ctx& c) { return c.c_split.p + 2 * (c.ncell + 32); }
-
-void launch_leaf_eval(Ctx& c, const int* leaves, double* acc, double* pot);
+void launch_leaf_eval(Ctx& c, double* acc, double* pot);
 void launch_l2l(Ctx& c);
 
 __global__ void k_count_p2p_pairs(const int* off, const int* src, const int* cb, const int* ce,
@@ -73,7 +70,7 @@ void evaluate(Ctx& c, double* acc, double* pot) {
   if (c.have_events) HIPCHK(hipEventRecord(c.ev[5], s));
   launch_l2l(c);
   if (c.have_events) HIPCHK(hipEventRecord(c.ev[6], s));
-  launch_leaf_eval(c, leaves_of(c), acc, pot);
+  launch_leaf_eval(c, acc, pot);
   if (c.have_events) HIPCHK(hipEventRecord(c.ev[7], s));
 }
 
@@ -395,14 +392,14 @@ void fmm_destroy(fmm_ctx* ctx) {
     rel(c.idx[k]);
     rel(c.front[k]);
   }
-  rel(c.sx); rel(c.sy); rel(c.sz); rel(c.sm); rel(c.fpart); rel(c.leaf_of); rel(c.sort_hist);
+  rel(c.sx); rel(c.sy); rel(c.sz); rel(c.sm); rel(c.pm); rel(c.pkb); rel(c.fpart); rel(c.leaf_of); rel(c.sort_hist);
   rel(c.bbox_part); rel(c.rootbox); rel(c.c_level); rel(c.c_begin); rel(c.c_end); rel(c.c_parent);
   rel(c.c_child0); rel(c.c_nchild); rel(c.c_split); rel(c.c_mass); rel(c.c_sx); rel(c.c_sy);
   rel(c.c_sz); rel(c.c_cx); rel(c.c_cy); rel(c.c_cz); rel(c.c_rad); rel(c.c_rad2bits); rel(c.mult);
   rel(c.pk); rel(c.fcell); rel(c.fmin); rel(c.loc); rel(c.counters); rel(c.scan_tmp);
   rel(c.scan_tmp64);
   for (CellList* L : {&c.est_far, &c.est_near, &c.m2l, &c.p2p}) {
-    rel(L->raw); rel(L->off); rel(L->src); rel(L->cursor);
+    rel(L->raw); rel(L->tmp); rel(L->off); rel(L->src);
   }
   if (c.hbuf) (void)hipHostFree(c.hbuf);
   for (auto& e : c.ev)

@@ -76,10 +76,10 @@ void release(Workspace& w, dbuf<T>& b) {
 // ------------------------------------------------------------------ lists
 // directed (sink, source) cell pairs grouped by sink: off[ncell+1], src[count]
 struct CellList {
-  dbuf<int2> raw;     // emitted pairs (any order)
-  dbuf<int> off;      // CSR offsets by sink
-  dbuf<int> src;      // sources, ascending within each sink
-  dbuf<int> cursor;   // scatter cursors
+  dbuf<uint64_t> raw;  // emitted keys (sink << bits | source), any order
+  dbuf<uint64_t> tmp;  // radix-sort ping-pong
+  dbuf<int> off;       // CSR offsets by sink
+  dbuf<int> src;       // sources, ascending within each sink
   int64_t count = 0;
 };
 
@@ -101,6 +101,7 @@ struct Ctx {
   dbuf<uint64_t> key[2];
   dbuf<int> idx[2];
   dbuf<double> sx, sy, sz, sm;
+  dbuf<double4> pm;   // packed (x, y, z, m), sorted order
   dbuf<double> fpart;
   dbuf<int> leaf_of;  // leaf id of each sorted body
 
@@ -122,6 +123,7 @@ struct Ctx {
   dbuf<unsigned long long> c_rad2bits;
   dbuf<double> mult;  // ncell x ncoef x 2
   dbuf<double> pk;    // ncell x (p+1)
+  dbuf<double> pkb;   // ncell x (p+1): C(p, k) * P_k, as the acceptance test forms it
   dbuf<double> fcell, fmin;
   dbuf<double> loc;   // ncell x ncoef x 2
 
@@ -147,6 +149,7 @@ struct Ctx {
 // ------------------------------------------------------------------ stages
 void exclusive_scan(Ctx& c, const int* in, int* out, int64_t n, long long* total_dev);
 long long read_total(Ctx& c, const long long* total_dev);
+int radix_sort(Ctx& c, uint64_t* k0, int* v0, uint64_t* k1, int* v1, int64_t n, int nbits);
 
 void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass);
 void upward_pass(Ctx& c);

@@ -96,111 +96,102 @@ __device__ __forceinline__ double rsqrt_d(double x) {
   return y;
 }
 
-// One wavefront per leaf; lane = sink body.  Far field by L2P (the local
-// expansion shifted to the body: Phi = -Re L'_0^0, a = (-Re L'_1^1,
-// -Im L'_1^1, Re L'_1^0)), near field by direct summation over the leaf's
-// P2P sources (ascending), FP64.
-__global__ void __launch_bounds__(64) k_leaf_eval(int p, const int* __restrict__ leaves, int nleaves,
-                                                  const int* __restrict__ cb, const int* __restrict__ ce,
-                                                  const int* __restrict__ off, const int* __restrict__ srcl,
-                                                  const double* __restrict__ cx, const double* __restrict__ cy,
-                                                  const double* __restrict__ cz, const double* __restrict__ loc,
-                                                  const double* __restrict__ sx, const double* __restrict__ sy,
-                                                  const double* __restrict__ sz, const double* __restrict__ sm,
-                                                  const int* __restrict__ perm, double eps2, double* acc,
-                                                  double* pot) {
-  int per = (nleaves + 7) >> 3;
-  int li = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (li >= nleaves) return;
-  int B = leaves[li];
+// One thread per sink body (bodies in sorted order, so a wavefront covers one
+// or a few neighbouring leaves and its loads are mostly broadcasts).  Far field
+// by L2P: the leaf's local expansion shifted to the body (Phi = -Re L'_0^0,
+// a = (-Re L'_1^1, -Im L'_1^1, Re L'_1^0)); near field by direct summation over
+// the leaf's P2P sources (ascending), FP64.
+__global__ void __launch_bounds__(256) k_leaf_eval(int p, int n, const int* __restrict__ leaf_of,
+                                                   const int* __restrict__ cb, const int* __restrict__ ce,
+                                                   const int* __restrict__ off, const int* __restrict__ srcl,
+                                                   const double* __restrict__ cx, const double* __restrict__ cy,
+                                                   const double* __restrict__ cz, const double* __restrict__ loc,
+                                                   const double4* __restrict__ pm,
+                                                   const int* __restrict__ perm, double eps2, double* acc,
+                                                   double* pot) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int B = leaf_of[i];
   int nc = ncoef(p);
   const double* L = loc + (size_t)B * nc * 2;
-  int b = cb[B], e = ce[B];
-  for (int i0 = b; i0 < e; i0 += 64) {
-    int i = i0 + threadIdx.x;
-    bool act = i < e;
-    int ii = act ? i : b;
-    double xi = sx[ii], yi = sy[ii], zi = sz[ii];
-    // ---- L2P: harmonics of X = x_i - z_B column by column, each used once
-    double X = xi - cx[B], Y = yi - cy[B], Z = zi - cz[B];
-    double r2 = fma(X, X, fma(Y, Y, Z * Z));
-    double s00 = 0.0, s10 = 0.0, s11r = 0.0, s11i = 0.0;
-    double dr = 1.0, di = 0.0;  // Y_m^m
-    for (int m = 0; m <= p; m++) {
-      if (m > 0) {
-        double inv = -1.0 / (double)(2 * m);
-        double tr = fma(X, dr, -Y * di), ti = fma(X, di, Y * dr);
-        dr = tr * inv;
-        di = ti * inv;
+  double4 me = pm[i];
+  double xi = me.x, yi = me.y, zi = me.z;
+  // ---- L2P: harmonics of X = x_i - z_B column by column, each used once
+  double X = xi - cx[B], Y = yi - cy[B], Z = zi - cz[B];
+  double r2 = fma(X, X, fma(Y, Y, Z * Z));
+  double s00 = 0.0, s10 = 0.0, s11r = 0.0, s11i = 0.0;
+  double dr = 1.0, di = 0.0;  // Y_m^m
+  for (int m = 0; m <= p; m++) {
+    if (m > 0) {
+      double inv = -1.0 / (double)(2 * m);
+      double tr = fma(X, dr, -Y * di), ti = fma(X, di, Y * dr);
+      dr = tr * inv;
+      di = ti * inv;
+    }
+    double yr = dr, yi2 = di, pr2 = 0.0, pi2 = 0.0;
+    for (int k = m; k <= p; k++) {
+      if (k > m) {
+        double kk = (double)(2 * k - 1) * Z, inv = 1.0 / (double)((k + m) * (k - m));
+        double vr = fma(kk, yr, -r2 * pr2) * inv, vi = fma(kk, yi2, -r2 * pi2) * inv;
+        pr2 = yr;
+        pi2 = yi2;
+        yr = vr;
+        yi2 = vi;
       }
-      double yr = dr, yi2 = di, pr2 = 0.0, pi2 = 0.0;
-      for (int k = m; k <= p; k++) {
-        if (k > m) {
-          double kk = (double)(2 * k - 1) * Z, inv = 1.0 / (double)((k + m) * (k - m));
-          double vr = fma(kk, yr, -r2 * pr2) * inv, vi = fma(kk, yi2, -r2 * pi2) * inv;
-          pr2 = yr;
-          pi2 = yi2;
-          yr = vr;
-          yi2 = vi;
-        }
-        // Y_k^m = (yr, yi2); contributions of +m and -m terms
-        double w = m == 0 ? 1.0 : 2.0;
-        double Lr = L[2 * cidx(k, m)], Li = L[2 * cidx(k, m) + 1];
-        s00 = fma(w, fma(Lr, yr, Li * yi2), s00);
-        if (k + 1 <= p) {
-          double Ur = L[2 * cidx(k + 1, m)], Ui = L[2 * cidx(k + 1, m) + 1];
-          s10 = fma(w, fma(Ur, yr, Ui * yi2), s10);
-          // + L_{k+1}^{m+1} conj(Y_k^m)
-          double Vr = L[2 * cidx(k + 1, m + 1)], Vi = L[2 * cidx(k + 1, m + 1) + 1];
-          s11r = fma(Vr, yr, fma(Vi, yi2, s11r));
-          s11i = fma(Vi, yr, fma(-Vr, yi2, s11i));
-          if (m >= 2) {  // the -m term: -conj(L_{k+1}^{m-1}) Y_k^m
-            double Wr = L[2 * cidx(k + 1, m - 1)], Wi = L[2 * cidx(k + 1, m - 1) + 1];
-            s11r = fma(-Wr, yr, fma(-Wi, yi2, s11r));
-            s11i = fma(-Wr, yi2, fma(Wi, yr, s11i));
-          } else if (m == 1) {  // the -1 term: -L_{k+1}^0 Y_k^1
-            double Wr = L[2 * cidx(k + 1, 0)], Wi = L[2 * cidx(k + 1, 0) + 1];
-            s11r = fma(-Wr, yr, fma(Wi, yi2, s11r));
-            s11i = fma(-Wr, yi2, fma(-Wi, yr, s11i));
-          }
+      // Y_k^m = (yr, yi2); contributions of the +m and -m terms
+      double w = m == 0 ? 1.0 : 2.0;
+      double Lr = L[2 * cidx(k, m)], Li = L[2 * cidx(k, m) + 1];
+      s00 = fma(w, fma(Lr, yr, Li * yi2), s00);
+      if (k + 1 <= p) {
+        double Ur = L[2 * cidx(k + 1, m)], Ui = L[2 * cidx(k + 1, m) + 1];
+        s10 = fma(w, fma(Ur, yr, Ui * yi2), s10);
+        // + L_{k+1}^{m+1} conj(Y_k^m)
+        double Vr = L[2 * cidx(k + 1, m + 1)], Vi = L[2 * cidx(k + 1, m + 1) + 1];
+        s11r = fma(Vr, yr, fma(Vi, yi2, s11r));
+        s11i = fma(Vi, yr, fma(-Vr, yi2, s11i));
+        if (m >= 2) {  // the -m term: -conj(L_{k+1}^{m-1}) Y_k^m
+          double Wr = L[2 * cidx(k + 1, m - 1)], Wi = L[2 * cidx(k + 1, m - 1) + 1];
+          s11r = fma(-Wr, yr, fma(-Wi, yi2, s11r));
+          s11i = fma(-Wr, yi2, fma(Wi, yr, s11i));
+        } else if (m == 1) {  // the -1 term: -L_{k+1}^0 Y_k^1
+          double Wr = L[2 * cidx(k + 1, 0)], Wi = L[2 * cidx(k + 1, 0) + 1];
+          s11r = fma(-Wr, yr, fma(Wi, yi2, s11r));
+          s11i = fma(-Wr, yi2, fma(-Wi, yr, s11i));
         }
       }
-    }
-    double ax = -s11r, ay = -s11i, az = s10, ph = -s00;
-    // ---- P2P
-    double nx = 0.0, ny = 0.0, nz = 0.0, np = 0.0;
-    for (int q = off[B]; q < off[B + 1]; q++) {
-      int A = srcl[q];
-      int jb = cb[A], je = ce[A];
-      for (int j = jb; j < je; j++) {
-        double dx = sx[j] - xi, dy = sy[j] - yi, dz = sz[j] - zi;
-        double d2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
-        double rinv = rsqrt_d(d2);
-        rinv = (j != i && d2 > 0.0) ? rinv : 0.0;
-        double mr = sm[j] * rinv;
-        double mr3 = mr * rinv * rinv;
-        nx = fma(mr3, dx, nx);
-        ny = fma(mr3, dy, ny);
-        nz = fma(mr3, dz, nz);
-        np -= mr;
-      }
-    }
-    if (act) {
-      int o = perm[i];
-      acc[3 * (int64_t)o] = ax + nx;
-      acc[3 * (int64_t)o + 1] = ay + ny;
-      acc[3 * (int64_t)o + 2] = az + nz;
-      pot[o] = ph + np;
     }
   }
+  double ax = -s11r, ay = -s11i, az = s10, ph = -s00;
+  // ---- P2P
+  double nx = 0.0, ny = 0.0, nz = 0.0, np = 0.0;
+  for (int q = off[B]; q < off[B + 1]; q++) {
+    int A = srcl[q];
+    int jb = cb[A], je = ce[A];
+    for (int j = jb; j < je; j++) {
+      double4 s = pm[j];
+      double dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
+      double d2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+      double rinv = rsqrt_d(d2);
+      rinv = (j != i && d2 > 0.0) ? rinv : 0.0;
+      double mr = s.w * rinv;
+      double mr3 = mr * rinv * rinv;
+      nx = fma(mr3, dx, nx);
+      ny = fma(mr3, dy, ny);
+      nz = fma(mr3, dz, nz);
+      np -= mr;
+    }
+  }
+  int o = perm[i];
+  acc[3 * (int64_t)o] = ax + nx;
+  acc[3 * (int64_t)o + 1] = ay + ny;
+  acc[3 * (int64_t)o + 2] = az + nz;
+  pot[o] = ph + np;
 }
 
-void launch_leaf_eval(Ctx& c, const int* leaves, double* acc, double* pot) {
-  unsigned grid = 8u * (unsigned)((c.nleaf + 7) / 8);
-  hipLaunchKernelGGL(k_leaf_eval, dim3(grid), dim3(64), 0, c.stream, c.p, leaves, (int)c.nleaf,
-                     c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.c_cx.p, c.c_cy.p, c.c_cz.p,
-                     c.loc.p, c.sx.p, c.sy.p, c.sz.p, c.sm.p, c.idx[0].p, c.eps_soft * c.eps_soft, acc,
-                     pot);
+void launch_leaf_eval(Ctx& c, double* acc, double* pot) {
+  hipLaunchKernelGGL(k_leaf_eval, dim3((unsigned)ceil_div(c.n, 256)), dim3(256), 0, c.stream, c.p,
+                     (int)c.n, c.leaf_of.p, c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.c_cx.p,
+                     c.c_cy.p, c.c_cz.p, c.loc.p, c.pm.p, c.idx[0].p, c.eps_soft * c.eps_soft, acc, pot);
   HIPCHK(hipGetLastError());
 }
 

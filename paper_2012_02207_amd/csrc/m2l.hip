@@ -30,7 +30,8 @@ namespace fmm {
 constexpr int swoff(int n) { return n * (4 * n * n - 1) / 3; }
 constexpr int SWAP_DOUBLES = swoff(FMM_GPU_PMAX + 1);
 
-static __constant__ double c_swap[SWAP_DOUBLES];
+static __constant__ double c_cswap[8192];
+static __constant__ double c_fact_m2l[2 * FMM_GPU_PMAX + 2];
 static bool g_m2l_tables = false;
 
 template <int I, int E, class F>
@@ -55,24 +56,57 @@ constexpr bool swap_nz(int n, int i, int j) {
 }
 
 // v (order-n slice, 2n+1 values) <- W_n v
+// Compacted swap table: only the structural non-zeros, row by row, order by
+// order, so that each row's coefficients are contiguous.
+constexpr int swap_nnz_row(int n, int i) {
+  int c = 0;
+  for (int j = 0; j < 2 * n + 1; j++) c += swap_nz(n, i, j) ? 1 : 0;
+  return c;
+}
+constexpr int swap_nnz(int n) {
+  int c = 0;
+  for (int i = 0; i < 2 * n + 1; i++) c += swap_nnz_row(n, i);
+  return c;
+}
+constexpr int cswoff(int n) {  // offset of order n in the compacted table
+  int c = 0;
+  for (int k = 0; k < n; k++) c += swap_nnz(k);
+  return c;
+}
+constexpr int crowoff(int n, int i) {
+  int c = cswoff(n);
+  for (int r = 0; r < i; r++) c += swap_nnz_row(n, r);
+  return c;
+}
+constexpr int CSWAP_DOUBLES = cswoff(FMM_GPU_PMAX + 1);
+
+constexpr int crank(int n, int i, int j) {
+  int c = 0;
+  for (int t = 0; t < j; t++) c += swap_nz(n, i, t) ? 1 : 0;
+  return c;
+}
+
+// LDS pointer type (reads through it are ds_read)
+typedef __attribute__((address_space(3))) double ldouble;
+
+// v (order-n slice, 2n+1 values) <- W_n v, coefficients from the compacted
+// table in LDS (wave-uniform addresses: broadcast reads)
 template <int N, class T>
-__device__ __forceinline__ void swap_apply(T* v) {
+__device__ __forceinline__ void swap_apply(T* v, const ldouble* sw) {
   constexpr int D = 2 * N + 1;
   T out[D];
   static_for<0, D>([&](auto ic) {
     constexpr int i = ic;
     T s = 0;
-    bool first = true;
     static_for<0, D>([&](auto jc) {
       constexpr int j = jc;
       if constexpr (swap_nz(N, i, j)) {
-        T w = (T)c_swap[swoff(N) + i * D + j];
-        if (first) {
+        constexpr int q = crowoff(N, i) + crank(N, i, j);
+        T w = (T)sw[q];
+        if constexpr (crank(N, i, j) == 0)
           s = w * v[j];
-          first = false;
-        } else {
+        else
           s = fma(w, v[j], s);
-        }
       }
     });
     out[i] = s;
@@ -80,40 +114,94 @@ __device__ __forceinline__ void swap_apply(T* v) {
   static_for<0, D>([&](auto ic) { v[ic] = out[ic]; });
 }
 
-// rotation about z: (C, S)_m <- (C cos m a - S sin m a, C sin m a + S cos m a)
+// rotation about z: (C, S)_m <- (C cos m a - S sin m a, C sin m a + S cos m a);
+// cos m a, sin m a by the angle-addition recurrence from (c1, s1)
 template <int N, class T>
-__device__ __forceinline__ void zrot(T* v, const T* cm, const T* sm, T sgn) {
+__device__ __forceinline__ void zrot(T* v, T c1, T s1) {
+  T cm = c1, sm = s1;
   static_for<1, N + 1>([&](auto mc) {
     constexpr int m = mc;
+    if constexpr (m > 1) {
+      T c2 = fma(cm, c1, -sm * s1);
+      sm = fma(sm, c1, cm * s1);
+      cm = c2;
+    }
     T C = v[2 * m - 1], S = v[2 * m];
-    T s = sgn * sm[m];
-    v[2 * m - 1] = fma(C, cm[m], -S * s);
-    v[2 * m] = fma(C, s, S * cm[m]);
+    v[2 * m - 1] = fma(C, cm, -S * sm);
+    v[2 * m] = fma(C, sm, S * cm);
   });
 }
 
+// Two-stage reduction of D values per lane over the 64 lanes of the wave
+// through LDS; lane j (< D) receives the total of value j.
+// red: RED_ROWS * 65 doubles, RED_ROWS > D (the last row holds stage-2 partials).
+template <int D, int RED_ROWS>
+__device__ __forceinline__ void reduce_order(const double* v, double* red, double* acc_slot,
+                                             int lane, bool act) {
+  static_assert(D < RED_ROWS, "reduction buffer too small");
+  constexpr int S = (64 / D) < 8 ? (64 / D) : 8;   // segments per value
+  constexpr int G = (64 + S - 1) / S;              // lanes per segment
+  // red layout: value j of lane l at j * 65 + l (pad 65 breaks bank conflicts).
+  // Branch-free: every lane runs the same instructions on clamped indices and
+  // masks its result with a select.
+#pragma unroll
+  for (int j = 0; j < D; j++) red[j * 65 + lane] = act ? v[j] : 0.0;
+  __builtin_amdgcn_wave_barrier();
+  int j = lane / S, sg = lane % S;
+  int jr = j < D ? j : D - 1;
+  int l0 = sg * G;
+  double part = 0.0;
+#pragma unroll
+  for (int t = 0; t < G; t++) {
+    int l = l0 + t;
+    double x = red[jr * 65 + (l < 64 ? l : 63)];
+    part += (l < 64) ? x : 0.0;
+  }
+  part = j < D ? part : 0.0;
+  __builtin_amdgcn_wave_barrier();
+  red[(RED_ROWS - 1) * 65 + lane] = part;
+  __builtin_amdgcn_wave_barrier();
+  int lr = lane < D ? lane : D - 1;
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < S; t++) s += red[(RED_ROWS - 1) * 65 + lr * S + t];
+  *acc_slot += lane < D ? s : 0.0;
+  __builtin_amdgcn_wave_barrier();
+}
+
+constexpr int M2L_WAVES = 4;  // sinks per workgroup (one per wavefront)
+
 template <int P>
-__global__ void __launch_bounds__(64) k_m2l_fp64(int ncell, const int* __restrict__ off,
-                                                 const int* __restrict__ src,
-                                                 const double* __restrict__ cx,
-                                                 const double* __restrict__ cy,
-                                                 const double* __restrict__ cz,
-                                                 const double* __restrict__ mult,
-                                                 double* __restrict__ loc) {
+__global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l_fp64(int ncell, const int* __restrict__ off,
+                                                             const int* __restrict__ src,
+                                                             const double* __restrict__ cx,
+                                                             const double* __restrict__ cy,
+                                                             const double* __restrict__ cz,
+                                                             const double* __restrict__ mult,
+                                                             double* __restrict__ loc) {
   constexpr int NC = ncoef(P);
-  constexpr int NR = (P + 1) * (P + 1);      // real-basis length
-  constexpr int NSLOT = (NR + 63) / 64;
+  constexpr int RED_ROWS = 2 * P + 2;
+  constexpr int NSW = cswoff(P + 1);
+  __shared__ double swt[NSW];
+  __shared__ double red_all[M2L_WAVES][RED_ROWS * 65];
+  for (int t = threadIdx.x; t < NSW; t += 64 * M2L_WAVES) swt[t] = c_cswap[t];
+  __syncthreads();
   // XCD-aware mapping: consecutive workgroups land on different XCDs, so give
   // each XCD a contiguous range of sinks (neighbouring sinks share sources)
-  int per = (ncell + 7) >> 3;
-  int B = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (B >= ncell) return;
+  int nblk = (ncell + M2L_WAVES - 1) / M2L_WAVES;
+  int per = (nblk + 7) >> 3;
+  int blk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  int wv = threadIdx.x >> 6;
+  int B = blk * M2L_WAVES + wv;
+  if (blk >= nblk || B >= ncell) return;
   int b = off[B], e = off[B + 1];
   if (b == e) return;
-  int lane = threadIdx.x;
-  double accum[NSLOT];
+  int lane = threadIdx.x & 63;
+  double* red = red_all[wv];
+  // lane-major accumulator: lane j holds coefficient j of order n in acc[n]
+  double acc[P + 1];
 #pragma unroll
-  for (int t = 0; t < NSLOT; t++) accum[t] = 0.0;
+  for (int t = 0; t <= P; t++) acc[t] = 0.0;
   double bx = cx[B], by = cy[B], bz = cz[B];
 
   for (int base = b; base < e; base += 64) {
@@ -135,18 +223,6 @@ __global__ void __launch_bounds__(64) k_m2l_fp64(int ncell, const int* __restric
       sa = 1.0;
     }
     double cb = Rz * rinv, sb = -rho * rinv;
-    double cam[P + 1], sam[P + 1], cbm[P + 1], sbm[P + 1];
-    cam[0] = 1.0;
-    sam[0] = 0.0;
-    cbm[0] = 1.0;
-    sbm[0] = 0.0;
-#pragma unroll
-    for (int m = 1; m <= P; m++) {
-      cam[m] = fma(cam[m - 1], ca, -sam[m - 1] * sa);
-      sam[m] = fma(sam[m - 1], ca, cam[m - 1] * sa);
-      cbm[m] = fma(cbm[m - 1], cb, -sbm[m - 1] * sb);
-      sbm[m] = fma(sbm[m - 1], cb, cbm[m - 1] * sb);
-    }
     // translation factors g_j = j! / r^{j+1}
     double g[P + 1];
     {
@@ -157,32 +233,93 @@ __global__ void __launch_bounds__(64) k_m2l_fp64(int ncell, const int* __restric
         rp *= rinv;
       }
     }
-    // forward rotation of the source moments, order by order
-    double Mp[NR];
     const double* M = mult + (size_t)A * NC * 2;
-    static_for<0, P + 1>([&](auto nc) {
+    // An opaque view of the LDS swap table per iteration: without it the
+    // compiler hoists every (loop-invariant) coefficient read out of the
+    // source loop and spills them.
+    const ldouble* sw_it = (const ldouble*)swt;
+    // Source orders k >= K0 reach only output orders n <= P - k < K0: rotate
+    // them first and fold them at once into a partial local expansion Lp
+    // (orders 0..P-K0), so that only the low orders of the rotated multipole
+    // stay live.  Same terms, summed in a different order.
+    constexpr int K0 = (P + 2) / 2;
+    constexpr int NLP = (P - K0 + 1) * (P - K0 + 1);
+    double Lp[NLP];
+#pragma unroll
+    for (int t = 0; t < NLP; t++) Lp[t] = 0.0;
+    static_for<K0, P + 1>([&](auto kc) {
+      constexpr int kk = kc;
+      __builtin_amdgcn_sched_barrier(0);
+      // fresh coefficient reads per order block: shared reads between blocks
+      // would keep the coefficients live (and spilled) in between
+      const ldouble* sw = sw_it;
+      asm volatile("" : "+v"(sw));
+      double v[2 * kk + 1];
+      // an opaque per-order pointer keeps the loads of this order from being
+      // merged with (and hoisted along with) those of other orders
+      const double* Mo = M + 2 * cidx(kk, 0);
+      asm volatile("" : "+v"(Mo));
+      v[0] = Mo[0];
+      static_for<1, kk + 1>([&](auto mc) {
+        constexpr int m = mc;
+        v[2 * m - 1] = Mo[2 * m];
+        v[2 * m] = Mo[2 * m + 1];
+      });
+      zrot<kk>(v, ca, sa);
+      swap_apply<kk>(v, sw);
+      zrot<kk>(v, cb, sb);
+      swap_apply<kk>(v, sw);
+      static_for<0, P - kk + 1>([&](auto nc) {
+        constexpr int n = nc;
+        static_for<0, (n < kk ? n : kk) + 1>([&](auto mc) {
+          constexpr int m = mc;
+          if constexpr (m == 0) {
+            Lp[n * n] = fma(v[0], g[n + kk], Lp[n * n]);
+          } else {
+            Lp[n * n + 2 * m - 1] = fma(v[2 * m - 1], g[n + kk], Lp[n * n + 2 * m - 1]);
+            Lp[n * n + 2 * m] = fma(v[2 * m], g[n + kk], Lp[n * n + 2 * m]);
+          }
+        });
+      });
+    });
+    // low source orders: rotate and keep
+    double Mp[K0 * K0];
+    static_for<0, K0>([&](auto nc) {
       constexpr int n = nc;
+      __builtin_amdgcn_sched_barrier(0);
+      const ldouble* sw = sw_it;
+      asm volatile("" : "+v"(sw));
       double* v = Mp + n * n;
-      v[0] = M[2 * cidx(n, 0)];
+      const double* Mo = M + 2 * cidx(n, 0);
+      asm volatile("" : "+v"(Mo));
+      v[0] = Mo[0];
       static_for<1, n + 1>([&](auto mc) {
         constexpr int m = mc;
-        v[2 * m - 1] = M[2 * cidx(n, m)];
-        v[2 * m] = M[2 * cidx(n, m) + 1];
+        v[2 * m - 1] = Mo[2 * m];
+        v[2 * m] = Mo[2 * m + 1];
       });
-      zrot<n>(v, cam, sam, 1.0);
-      swap_apply<n>(v);
-      zrot<n>(v, cbm, sbm, 1.0);
-      swap_apply<n>(v);
+      zrot<n>(v, ca, sa);
+      swap_apply<n>(v, sw);
+      zrot<n>(v, cb, sb);
+      swap_apply<n>(v, sw);
     });
-    // translate along z, rotate back and reduce, one output order at a time
+    // complete the translation, rotate back and reduce, one output order at a time
     static_for<0, P + 1>([&](auto nc) {
       constexpr int n = nc;
+      __builtin_amdgcn_sched_barrier(0);
+      const ldouble* sw = sw_it;
+      asm volatile("" : "+v"(sw));
       double w[2 * n + 1];
       static_for<0, n + 1>([&](auto mc) {
         constexpr int m = mc;
         if constexpr (m <= P - n) {
           double sC = 0.0, sS = 0.0;
-          static_for<m, P - n + 1>([&](auto kc) {
+          if constexpr (n <= P - K0) {
+            sC = Lp[n * n + (m == 0 ? 0 : 2 * m - 1)];
+            if constexpr (m > 0) sS = Lp[n * n + 2 * m];
+          }
+          constexpr int KMAX = (P - n) < (K0 - 1) ? (P - n) : (K0 - 1);
+          static_for<m, KMAX + 1>([&](auto kc) {
             constexpr int kk = kc;
             sC = fma(Mp[kk * kk + (m == 0 ? 0 : 2 * m - 1)], g[n + kk], sC);
             if constexpr (m > 0) sS = fma(Mp[kk * kk + 2 * m], g[n + kk], sS);
@@ -199,47 +336,34 @@ __global__ void __launch_bounds__(64) k_m2l_fp64(int ncell, const int* __restric
           w[2 * m] = 0.0;
         }
       });
-      swap_apply<n>(w);
-      zrot<n>(w, cbm, sbm, -1.0);
-      swap_apply<n>(w);
-      zrot<n>(w, cam, sam, -1.0);
-      static_for<0, 2 * n + 1>([&](auto jc) {
-        constexpr int j = jc;
-        constexpr int idx = n * n + j;
-        double tot = wave_sum(act ? w[j] : 0.0);
-        if (lane == (idx & 63)) accum[idx >> 6] += tot;
-      });
+      swap_apply<n>(w, sw);
+      zrot<n>(w, cb, -sb);
+      swap_apply<n>(w, sw);
+      zrot<n>(w, ca, -sa);
+      reduce_order<2 * n + 1, RED_ROWS>(w, red, &acc[n], lane, act);
     });
   }
-  // back to the unscaled basis: L_n^m = (n-m)!(n+m)! Lhat_n^m
+  // back to the unscaled basis: L_n^m = (n-m)!(n+m)! Lhat_n^m; lane j owns
+  // real-basis entry j of every order
   double* out = loc + (size_t)B * NC * 2;
-  static_for<0, P + 1>([&](auto nc) {
-    constexpr int n = nc;
-    static_for<0, 2 * n + 1>([&](auto jc) {
-      constexpr int j = jc;
-      constexpr int idx = n * n + j;
-      constexpr int m = rb_m(j);
-      constexpr double f = cfact(n - m) * cfact(n + m);
-      if (lane == (idx & 63)) {
-        double v = accum[idx >> 6] * f;
-        if constexpr (j == 0) {
-          out[2 * cidx(n, 0)] = v;
-          out[2 * cidx(n, 0) + 1] = 0.0;
-        } else if constexpr (rb_re(j)) {
-          out[2 * cidx(n, m)] = v;
-        } else {
-          out[2 * cidx(n, m) + 1] = v;
-        }
-      }
-    });
-  });
+  int m = (lane + 1) >> 1;
+  bool im = lane > 0 && !(lane & 1);
+#pragma unroll
+  for (int n = 0; n <= P; n++) {
+    if (lane < 2 * n + 1) {
+      double f = c_fact_m2l[n - m] * c_fact_m2l[n + m];
+      out[2 * cidx(n, m) + (im ? 1 : 0)] = acc[n] * f;
+      if (lane == 0) out[2 * cidx(n, 0) + 1] = 0.0;
+    }
+  }
 }
 
 template <int P>
 static void launch_p(Ctx& c) {
   int nc = (int)c.ncell;
-  unsigned grid = 8u * (unsigned)((nc + 7) / 8);
-  hipLaunchKernelGGL(k_m2l_fp64<P>, dim3(grid), dim3(64), 0, c.stream, nc, c.m2l.off.p, c.m2l.src.p,
+  int nblk = (nc + M2L_WAVES - 1) / M2L_WAVES;
+  unsigned grid = 8u * (unsigned)((nblk + 7) / 8);
+  hipLaunchKernelGGL(k_m2l_fp64<P>, dim3(grid), dim3(64 * M2L_WAVES), 0, c.stream, nc, c.m2l.off.p, c.m2l.src.p,
                      c.c_cx.p, c.c_cy.p, c.c_cz.p, c.mult.p, c.loc.p);
 }
 
@@ -258,7 +382,15 @@ static bool dispatch(Ctx& c) {
 
 void launch_m2l_fp64(Ctx& c) {
   if (!g_m2l_tables) {
-    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_swap), fmm_swap_table, sizeof(double) * SWAP_DOUBLES));
+    // compact the dense tables to their structural non-zeros (row-major)
+    static_assert(CSWAP_DOUBLES <= 8192, "compacted swap table");
+    std::vector<double> cs;
+    for (int n = 0; n <= FMM_GPU_PMAX; n++)
+      for (int i = 0; i < 2 * n + 1; i++)
+        for (int j = 0; j < 2 * n + 1; j++)
+          if (swap_nz(n, i, j)) cs.push_back(fmm_swap_table[swoff(n) + i * (2 * n + 1) + j]);
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_cswap), cs.data(), sizeof(double) * cs.size()));
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_fact_m2l), fmm_fact_table, sizeof(double) * (2 * FMM_GPU_PMAX + 2)));
     g_m2l_tables = true;
   }
   if (!dispatch<1>(c)) throw hip_error{hipErrorInvalidValue, "M2L order not compiled"};

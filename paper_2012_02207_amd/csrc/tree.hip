@@ -155,25 +155,40 @@ __global__ void __launch_bounds__(BB_T) k_bbox_partial(const double* pos, int64_
 }
 
 // lo = min, L = largest extent (1 if zero), s = 2^21 / L  (rootbox = lo[3], L, s)
-__global__ void k_bbox_final(const double* part, int nb, double* rootbox) {
-  if (threadIdx.x != 0) return;
+__global__ void __launch_bounds__(BB_T) k_bbox_final(const double* part, int nb, double* rootbox) {
+  __shared__ double sh[6][BB_T];
+  int t = threadIdx.x;
   double lo[3], hi[3];
   for (int d = 0; d < 3; d++) {
     lo[d] = part[d];
     hi[d] = part[3 + d];
   }
-  for (int b = 1; b < nb; b++)
+  for (int b = t; b < nb; b += BB_T)
     for (int d = 0; d < 3; d++) {
       if (part[6 * b + d] < lo[d]) lo[d] = part[6 * b + d];
       if (part[6 * b + 3 + d] > hi[d]) hi[d] = part[6 * b + 3 + d];
     }
-  double L = hi[0] - lo[0];
-  if (hi[1] - lo[1] > L) L = hi[1] - lo[1];
-  if (hi[2] - lo[2] > L) L = hi[2] - lo[2];
+  for (int d = 0; d < 3; d++) {
+    sh[d][t] = lo[d];
+    sh[3 + d][t] = hi[d];
+  }
+  __syncthreads();
+  for (int o = BB_T / 2; o > 0; o >>= 1) {
+    if (t < o)
+      for (int d = 0; d < 3; d++) {
+        if (sh[d][t + o] < sh[d][t]) sh[d][t] = sh[d][t + o];
+        if (sh[3 + d][t + o] > sh[3 + d][t]) sh[3 + d][t] = sh[3 + d][t + o];
+      }
+    __syncthreads();
+  }
+  if (t != 0) return;
+  double L = sh[3][0] - sh[0][0];
+  if (sh[4][0] - sh[1][0] > L) L = sh[4][0] - sh[1][0];
+  if (sh[5][0] - sh[2][0] > L) L = sh[5][0] - sh[2][0];
   if (L == 0.0) L = 1.0;
-  rootbox[0] = lo[0];
-  rootbox[1] = lo[1];
-  rootbox[2] = lo[2];
+  rootbox[0] = sh[0][0];
+  rootbox[1] = sh[1][0];
+  rootbox[2] = sh[2][0];
   rootbox[3] = L;
   rootbox[4] = 2097152.0 / L;
 }
@@ -235,6 +250,7 @@ __global__ void __launch_bounds__(RS_T) k_rs_hist(const uint64_t* key, int64_t n
   hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
+template <bool VAL>
 __global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t* kin, const int* vin,
                                                      uint64_t* kout, int* vout, int64_t n,
                                                      int shift, const int* offs, int nblocks) {
@@ -253,7 +269,7 @@ __global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t* kin, const 
     int64_t j = base + (int64_t)c * 64 + lane;
     bool valid = j < n;
     k[c] = valid ? kin[j] : 0;
-    v[c] = valid ? vin[j] : 0;
+    if (VAL) v[c] = valid ? vin[j] : 0;
     int d = (int)((k[c] >> shift) & 255);
     uint64_t peers = ballot(valid);
     for (int b = 0; b < 8; b++) {
@@ -285,42 +301,59 @@ __global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t* kin, const 
     int64_t dst = (int64_t)goff[d] + wcnt[w][d] + rank[c];
     if (dst < n) {  // always true when the ranks are consistent with the histogram
       kout[dst] = k[c];
-      vout[dst] = v[c];
+      if (VAL) vout[dst] = v[c];
     }
   }
 }
 
-// sorts c.key[0]/c.idx[0] (n entries) over bits [0, nbits); result in key[0]/idx[0]
-void radix_sort_keys(Ctx& c, int64_t n, int nbits) {
+// Stable LSD sort of n keys over bits [0, nbits) (8 bits per pass), with an
+// optional int payload.  Data ping-pongs between (k0, v0) and (k1, v1); the
+// return value tells which buffer holds the result (0 or 1).
+int radix_sort(Ctx& c, uint64_t* k0, int* v0, uint64_t* k1, int* v1, int64_t n, int nbits) {
+  if (n <= 0) return 0;
   int nb = (int)ceil_div(n, RS_TILE);
   ensure(c.ws, c.sort_hist, (size_t)256 * nb * 2 + 64);
   int* hist = c.sort_hist.p;
   int* offs = hist + (size_t)256 * nb;
   int src = 0;
+  uint64_t* kk[2] = {k0, k1};
+  int* vv[2] = {v0, v1};
   for (int shift = 0; shift < nbits; shift += 8) {
-    hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_T), 0, c.stream, c.key[src].p, n, shift, hist, nb);
+    hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_T), 0, c.stream, kk[src], n, shift, hist, nb);
     HIPCHK(hipGetLastError());
     exclusive_scan(c, hist, offs, (int64_t)256 * nb, nullptr);
-    hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(RS_T), 0, c.stream, c.key[src].p, c.idx[src].p,
-                       c.key[1 - src].p, c.idx[1 - src].p, n, shift, offs, nb);
+    if (v0)
+      hipLaunchKernelGGL(k_rs_scatter<true>, dim3(nb), dim3(RS_T), 0, c.stream, kk[src], vv[src],
+                         kk[1 - src], vv[1 - src], n, shift, offs, nb);
+    else
+      hipLaunchKernelGGL(k_rs_scatter<false>, dim3(nb), dim3(RS_T), 0, c.stream, kk[src], nullptr,
+                         kk[1 - src], nullptr, n, shift, offs, nb);
     HIPCHK(hipGetLastError());
     src = 1 - src;
   }
-  if (src != 0) {
+  return src;
+}
+
+// sorts c.key[0]/c.idx[0] (n entries) over bits [0, nbits); result in key[0]/idx[0]
+void radix_sort_keys(Ctx& c, int64_t n, int nbits) {
+  int r = radix_sort(c, c.key[0].p, c.idx[0].p, c.key[1].p, c.idx[1].p, n, nbits);
+  if (r != 0) {
     std::swap(c.key[0], c.key[1]);
     std::swap(c.idx[0], c.idx[1]);
   }
 }
 
 __global__ void k_gather(const double* pos, const double* mass, const int* idx, int64_t n, double* sx,
-                         double* sy, double* sz, double* sm) {
+                         double* sy, double* sz, double* sm, double4* pm) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int o = idx[i];
-  sx[i] = pos[3 * (int64_t)o];
-  sy[i] = pos[3 * (int64_t)o + 1];
-  sz[i] = pos[3 * (int64_t)o + 2];
-  sm[i] = mass[o];
+  double x = pos[3 * (int64_t)o], y = pos[3 * (int64_t)o + 1], z = pos[3 * (int64_t)o + 2], m = mass[o];
+  sx[i] = x;
+  sy[i] = y;
+  sz[i] = z;
+  sm[i] = m;
+  pm[i] = make_double4(x, y, z, m);
 }
 
 // ===================================================================== cells
@@ -513,12 +546,13 @@ void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
   int nbb = (int)std::min<int64_t>(1024, ceil_div(n, BB_T));
   ensure(c.ws, c.bbox_part, (size_t)6 * nbb);
   hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(BB_T), 0, s, pos, n, c.bbox_part.p);
-  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, c.bbox_part.p, nbb, c.rootbox.p);
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(BB_T), 0, s, c.bbox_part.p, nbb, c.rootbox.p);
   hipLaunchKernelGGL(k_keys, grid1(n), dim3(256), 0, s, pos, n, c.rootbox.p, c.key[0].p, c.idx[0].p);
   HIPCHK(hipGetLastError());
   radix_sort_keys(c, n, 64);
+  ensure(c.ws, c.pm, n);
   hipLaunchKernelGGL(k_gather, grid1(n), dim3(256), 0, s, pos, mass, c.idx[0].p, n, c.sx.p, c.sy.p,
-                     c.sz.p, c.sm.p);
+                     c.sz.p, c.sm.p, c.pm.p);
   HIPCHK(hipGetLastError());
 
   // breadth-first levels

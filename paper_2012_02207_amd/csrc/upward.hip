@@ -18,6 +18,7 @@
 namespace fmm {
 
 static __constant__ double c_fact[2 * FMM_TABLE_PMAX + 2];
+static __constant__ double c_binom[FMM_TABLE_PMAX + 1][FMM_TABLE_PMAX + 1];
 static bool g_up_tables = false;
 
 constexpr int UP_LDS_DOUBLES = 7680;  // 60 KB of LDS per workgroup
@@ -92,11 +93,14 @@ __global__ void __launch_bounds__(64) k_m2m(int p, int first, int count, const i
   int k0 = c0[c], kn = nch[c];
   double* yre = lds;             // child j at stride 8
   double* yim = lds + nc * 8;
+  double* mch = lds + 2 * nc * 8;  // children's moments, contiguous ids -> contiguous rows
   int lane = threadIdx.x;
   if (lane < kn) {
     int ch = k0 + lane;
     regular_exact(p, cx[ch] - cx[c], cy[ch] - cy[c], cz[ch] - cz[c], yre + lane, yim + lane, 8);
   }
+  const double* src = mult + (size_t)k0 * nc * 2;
+  for (int t = lane; t < kn * nc * 2; t += 64) mch[t] = src[t];
   __syncthreads();
   double* out = mult + (size_t)c * nc * 2;
   for (int t = lane; t < nc; t += 64) {
@@ -106,11 +110,13 @@ __global__ void __launch_bounds__(64) k_m2m(int p, int first, int count, const i
     int m = t - cidx(n, 0);
     double sr = 0.0, si = 0.0;
     for (int j = 0; j < kn; j++) {
-      const double* cm = mult + (size_t)(k0 + j) * nc * 2;
-      for (int k = 0; k <= n; k++)
-        for (int l = -k; l <= k; l++) {
-          int jj = n - k, q = m - l;
-          if (q > jj || q < -jj) continue;
+      const double* cm = mch + j * nc * 2;
+      for (int k = 0; k <= n; k++) {
+        int jj = n - k;
+        // l ranges over |l| <= k with |m - l| <= jj
+        int lo = max(-k, m - jj), hi = min(k, m + jj);
+        for (int l = lo; l <= hi; l++) {
+          int q = m - l;
           double ar, ai;
           cget(yre + j, yim + j, 8, k, l, ar, ai);
           double br, bi;
@@ -127,14 +133,16 @@ __global__ void __launch_bounds__(64) k_m2m(int p, int first, int count, const i
           sr = sr + tr;
           si = si + ti;
         }
+      }
     }
     out[2 * t] = sr;
     out[2 * t + 1] = si;
   }
 }
 
-// P_k = sqrt( (k!)^2 |M_k^0|^2 + sum_{m=1..k} 2 (k-m)!(k+m)! |M_k^m|^2 )
-__global__ void k_pk(int p, int ncell, const double* mult, double* pk) {
+// P_k = sqrt( (k!)^2 |M_k^0|^2 + sum_{m=1..k} 2 (k-m)!(k+m)! |M_k^m|^2 ), and the
+// product C(p, k) P_k used by the acceptance test
+__global__ void k_pk(int p, int ncell, const double* mult, double* pk, double* pkb) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)ncell * (p + 1)) return;
   int c = (int)(t / (p + 1)), k = (int)(t % (p + 1));
@@ -145,7 +153,9 @@ __global__ void k_pk(int p, int ncell, const double* mult, double* pk) {
     double w = (m == 0) ? (c_fact[k] * c_fact[k]) : (2.0 * (c_fact[k - m] * c_fact[k + m]));
     acc = acc + w * (re * re + im * im);
   }
-  pk[t] = sqrt(acc);
+  double P = sqrt(acc);
+  pk[t] = P;
+  pkb[t] = c_binom[p][k] * P;
 }
 
 __global__ void k_list_leaves(const int* nch, int ncell, int* flag) {
@@ -161,6 +171,7 @@ __global__ void k_compact_leaves(const int* flag, const int* off, int ncell, int
 void upward_pass(Ctx& c) {
   if (!g_up_tables) {
     HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_fact), fmm_fact_table, sizeof(fmm_fact_table)));
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_binom), fmm_binom_table, sizeof(fmm_binom_table)));
     g_up_tables = true;
   }
   hipStream_t s = c.stream;
@@ -188,7 +199,9 @@ void upward_pass(Ctx& c) {
     HIPCHK(hipGetLastError());
   }
   int64_t npk = (int64_t)nc * (p + 1);
-  hipLaunchKernelGGL(k_pk, dim3((unsigned)ceil_div(npk, 256)), dim3(256), 0, s, p, nc, c.mult.p, c.pk.p);
+  ensure(c.ws, c.pkb, (size_t)npk);
+  hipLaunchKernelGGL(k_pk, dim3((unsigned)ceil_div(npk, 256)), dim3(256), 0, s, p, nc, c.mult.p, c.pk.p,
+                     c.pkb.p);
   HIPCHK(hipGetLastError());
 }
 

@@ -23,12 +23,10 @@
 
 namespace fmm {
 
-static __constant__ double c_binom[FMM_TABLE_PMAX + 1][FMM_TABLE_PMAX + 1];
-static bool g_walk_tables = false;
 
 struct CellView {
   const int *nch, *c0;
-  const double *rad, *cx, *cy, *cz, *mass, *pk, *fmin;
+  const double *rad, *cx, *cy, *cz, *mass, *pkb, *fmin;
   int p;
   double theta, err_tol;
   int geometric;
@@ -41,39 +39,47 @@ __device__ __forceinline__ double com_r2(const CellView& v, int a, int b) {
   return (dx * dx + dy * dy) + dz * dz;
 }
 
-// E_{A->B} M_A / r^2 with M_A cancelled; sums in the order the definition lists
+// E_{A->B} M_A / r^2 with M_A cancelled; sums in the order the definition
+// lists (k ascending), each term (C(p,k) P_{k,A}) r_B^{p-k}, with C(p,k) P_{k,A}
+// formed once per cell by the upward pass
+template <int P>
 __device__ double mac_lhs(const CellView& v, int A, int B, double r, double r2) {
-  int p = v.p;
   double rA = v.rad[A], rB = v.rad[B];
   double rp = r;
-  for (int i = 2; i <= p; i++) rp = rp * r;
+#pragma unroll
+  for (int i = 2; i <= P; i++) rp = rp * r;
   double mx = rA > rB ? rA : rB;
   double pref = (8.0 * mx) / (rA + rB);
-  double pw[FMM_TABLE_PMAX + 1];
+  double pw[P + 1];
   pw[0] = 1.0;
   double powB = 1.0;
-  for (int j = 1; j <= p; j++) {
+#pragma unroll
+  for (int j = 1; j <= P; j++) {
     powB = powB * rB;
     pw[j] = powB;
   }
-  const double* PA = v.pk + (size_t)A * (p + 1);
+  const double* PA = v.pkb + (size_t)A * (P + 1);
   double SA = 0.0;
-  for (int k = 0; k <= p; k++) SA = SA + (c_binom[p][k] * PA[k]) * pw[p - k];
+#pragma unroll
+  for (int k = 0; k <= P; k++) SA = SA + PA[k] * pw[P - k];
   return (pref * (SA / rp)) / r2;
 }
 
-template <int KIND>
+template <int KIND, int P>
 __device__ bool accept(const CellView& v, int A, int B) {
   double r2 = com_r2(v, A, B);
   double r = sqrt(r2);
   double rA = v.rad[A], rB = v.rad[B];
-  if (KIND == 0) return (rA + rB) < v.theta * r;
-  if (!((rA + rB) < v.theta * r)) return false;
-  if (v.geometric) return true;
-  if (rA + rB == 0.0) return true;
-  double lab = mac_lhs(v, A, B, r, r2);
-  double lba = mac_lhs(v, B, A, r, r2);
-  return (lab < v.err_tol * v.fmin[B]) && (lba < v.err_tol * v.fmin[A]);
+  if constexpr (KIND == 0) {
+    return (rA + rB) < v.theta * r;
+  } else {
+    if (!((rA + rB) < v.theta * r)) return false;
+    if (v.geometric) return true;
+    if (rA + rB == 0.0) return true;
+    double lab = mac_lhs<P>(v, A, B, r, r2);
+    double lba = mac_lhs<P>(v, B, A, r, r2);
+    return (lab < v.err_tol * v.fmin[B]) && (lba < v.err_tol * v.fmin[A]);
+  }
 }
 
 __device__ __forceinline__ int wave_incl_scan(int x) {
@@ -98,10 +104,10 @@ __device__ __forceinline__ long long wave_alloc(int cnt, int* ctr, int& excl) {
 }
 
 // ctr[0]: next frontier, ctr[1]: accepted pairs, ctr[2]: near-field leaf pairs
-template <int KIND>
+template <int KIND, int P>
 __global__ void __launch_bounds__(256) k_walk(CellView v, const int2* fin, int nin, int2* fout,
-                                              int fcap, int* ctr, int2* acc_list, int acap,
-                                              int2* near_list, int ncap) {
+                                              int fcap, int* ctr, uint64_t* acc_list, int acap,
+                                              uint64_t* near_list, int ncap, int bits) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   bool live = t < nin;
   int A = 0, B = 0, nkids = 0, nacc = 0, nnear = 0, mode = 0;
@@ -118,7 +124,7 @@ __global__ void __launch_bounds__(256) k_walk(CellView v, const int2* fin, int n
         mode = 1;
         nkids = kA * (kA + 1) / 2;
       }
-    } else if (accept<KIND>(v, A, B)) {
+    } else if (accept<KIND, P>(v, A, B)) {
       nacc = 2;
     } else if (kA == 0 && kB == 0) {
       nnear = 2;
@@ -148,20 +154,22 @@ __global__ void __launch_bounds__(256) k_walk(CellView v, const int2* fin, int n
     for (int j = 0; j < nkids; j++, o++)
       if (o < fcap) fout[o] = make_int2(A, c0 + j);
   }
+  // list entries: (sink << bits) | source
+  uint64_t kab = ((uint64_t)B << bits) | (uint64_t)A, kba = ((uint64_t)A << bits) | (uint64_t)B;
   if (nacc) {
     long long q = ba + ea;
     if (q + 1 < acap) {
-      acc_list[q] = make_int2(B, A);  // (sink, source)
-      acc_list[q + 1] = make_int2(A, B);
+      acc_list[q] = kab;
+      acc_list[q + 1] = kba;
     }
   }
   if (nnear) {
     long long q = bn + en;
     if (nnear == 1) {
-      if (q < ncap) near_list[q] = make_int2(A, A);
+      if (q < ncap) near_list[q] = kab;
     } else if (q + 1 < ncap) {
-      near_list[q] = make_int2(B, A);
-      near_list[q + 1] = make_int2(A, B);
+      near_list[q] = kab;
+      near_list[q + 1] = kba;
     }
   }
 }
@@ -169,86 +177,54 @@ __global__ void __launch_bounds__(256) k_walk(CellView v, const int2* fin, int n
 __global__ void k_seed(int2* f) { f[0] = make_int2(0, 0); }
 
 // ---- grouping by sink, sorted by source ----------------------------------
-__global__ void k_count_sinks(const int2* raw, int64_t cnt, int* hist) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < cnt) atomicAdd(&hist[raw[i].x], 1);
-}
-
-__global__ void k_scatter_sinks(const int2* raw, int64_t cnt, const int* off, int* cursor, int* src) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cnt) return;
-  int2 pr = raw[i];
-  int slot = atomicAdd(&cursor[pr.x], 1);
-  src[off[pr.x] + slot] = pr.y;
-}
-
-constexpr int SEG_T = 512, SEG_CAP = 8192;
-
-// sorts each sink's sources ascending: bitonic sort in LDS; longer segments
-// fall back to a rank sort in global memory (entries within a segment are distinct)
-__global__ void __launch_bounds__(SEG_T) k_sort_segments(const int* off, int nseg, int* src,
-                                                         int* tmp) {
-  __shared__ int sh[SEG_CAP];
-  int s = blockIdx.x;
-  if (s >= nseg) return;
-  int b = off[s], e = off[s + 1], len = e - b;
-  if (len <= 1) return;
-  if (len <= SEG_CAP) {
-    int P = 1;
-    while (P < len) P <<= 1;
-    for (int i = threadIdx.x; i < P; i += SEG_T) sh[i] = i < len ? src[b + i] : 0x7fffffff;
-    __syncthreads();
-    for (int k = 2; k <= P; k <<= 1)
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int i = threadIdx.x; i < P; i += SEG_T) {
-          int ix = i ^ j;
-          if (ix > i) {
-            int a = sh[i], c = sh[ix];
-            bool up = (i & k) == 0;
-            if ((a > c) == up) {
-              sh[i] = c;
-              sh[ix] = a;
-            }
-          }
-        }
-        __syncthreads();
-      }
-    for (int i = threadIdx.x; i < len; i += SEG_T) src[b + i] = sh[i];
-  } else {
-    for (int i = threadIdx.x; i < len; i += SEG_T) {
-      int v = src[b + i], r = 0;
-      for (int j = 0; j < len; j++) r += src[b + j] < v;
-      tmp[b + r] = v;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < len; i += SEG_T) src[b + i] = tmp[b + i];
+// The keys (sink << bits | source) are radix-sorted; CSR offsets come from a
+// lower bound per sink and the sources are the low bits.
+__global__ void k_csr_off(const uint64_t* keys, int64_t cnt, int nseg, int bits, int* off) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s > nseg) return;
+  uint64_t t = (uint64_t)s << bits;
+  int64_t lo = 0, hi = cnt;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (keys[mid] < t)
+      lo = mid + 1;
+    else
+      hi = mid;
   }
+  off[s] = (int)lo;
+}
+
+__global__ void k_extract_src(const uint64_t* keys, int64_t cnt, uint64_t mask, int* src) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) src[i] = (int)(keys[i] & mask);
+}
+
+static int list_bits(int64_t ncell) {
+  int b = 1;
+  while (((int64_t)1 << b) < ncell) b++;
+  return b;
 }
 
 static void group_by_sink(Ctx& c, CellList& L) {
   hipStream_t s = c.stream;
   int nc = (int)c.ncell;
+  int bits = list_bits(c.ncell);
   ensure(c.ws, L.off, (size_t)nc + 1);
-  ensure(c.ws, L.cursor, (size_t)nc + 1);
   ensure(c.ws, L.src, (size_t)std::max<int64_t>(L.count, 1));
-  int* hist = L.cursor.p;
-  HIPCHK(hipMemsetAsync(hist, 0, sizeof(int) * (nc + 1), s));
-  if (L.count)
-    hipLaunchKernelGGL(k_count_sinks, dim3((unsigned)ceil_div(L.count, 256)), dim3(256), 0, s,
-                       L.raw.p, L.count, hist);
-  exclusive_scan(c, hist, L.off.p, nc + 1, nullptr);
-  HIPCHK(hipMemsetAsync(hist, 0, sizeof(int) * (nc + 1), s));
+  ensure(c.ws, L.tmp, (size_t)std::max<int64_t>(L.count, 1));
+  const uint64_t* sorted = L.raw.p;
   if (L.count) {
-    hipLaunchKernelGGL(k_scatter_sinks, dim3((unsigned)ceil_div(L.count, 256)), dim3(256), 0, s,
-                       L.raw.p, L.count, L.off.p, hist, L.src.p);
-    // rank-sort scratch reuses the raw pair buffer (count ints fit in count int2)
-    hipLaunchKernelGGL(k_sort_segments, dim3(nc), dim3(SEG_T), 0, s, L.off.p, nc, L.src.p,
-                       (int*)L.raw.p);
+    int r = radix_sort(c, L.raw.p, nullptr, L.tmp.p, nullptr, L.count, 2 * bits);
+    sorted = r == 0 ? L.raw.p : L.tmp.p;
+    hipLaunchKernelGGL(k_extract_src, dim3((unsigned)ceil_div(L.count, 256)), dim3(256), 0, s, sorted,
+                       L.count, ((uint64_t)1 << bits) - 1, L.src.p);
   }
+  hipLaunchKernelGGL(k_csr_off, dim3((unsigned)ceil_div(nc + 1, 256)), dim3(256), 0, s, sorted, L.count,
+                     nc, bits, L.off.p);
   HIPCHK(hipGetLastError());
 }
 
-template <int KIND>
+template <int KIND, int P>
 static void run_walk(Ctx& c, CellList& acc, CellList& nearl) {
   hipStream_t s = c.stream;
   CellView v{};
@@ -259,7 +235,7 @@ static void run_walk(Ctx& c, CellList& acc, CellList& nearl) {
   v.cy = c.c_cy.p;
   v.cz = c.c_cz.p;
   v.mass = c.c_mass.p;
-  v.pk = c.pk.p;
+  v.pkb = c.pkb.p;
   v.fmin = c.fmin.p;
   v.p = c.p;
   v.theta = KIND == 0 ? c.prm.theta_est : c.prm.theta;
@@ -272,6 +248,7 @@ static void run_walk(Ctx& c, CellList& acc, CellList& nearl) {
   ensure(c.ws, nearl.raw, std::max<size_t>(nearl.raw.cap, (size_t)c.ncell * 8 + 64));
   ensure(c.ws, c.counters, 64);
   int* ctr = c.counters.p + 16;
+  int bits = list_bits(c.ncell);
   int* h = (int*)c.hbuf;
   hipLaunchKernelGGL(k_seed, dim3(1), dim3(1), 0, s, c.front[0].p);
   int nin = 1, cur = 0;
@@ -280,9 +257,9 @@ static void run_walk(Ctx& c, CellList& acc, CellList& nearl) {
     for (;;) {
       int init[4] = {0, nacc, nnear, 0};
       HIPCHK(hipMemcpyAsync(ctr, init, sizeof(init), hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL(k_walk<KIND>, dim3((unsigned)ceil_div(nin, 256)), dim3(256), 0, s, v,
+      hipLaunchKernelGGL((k_walk<KIND, P>), dim3((unsigned)ceil_div(nin, 256)), dim3(256), 0, s, v,
                          c.front[cur].p, nin, c.front[1 - cur].p, (int)c.front[1 - cur].cap, ctr,
-                         acc.raw.p, (int)acc.raw.cap, nearl.raw.p, (int)nearl.raw.cap);
+                         acc.raw.p, (int)acc.raw.cap, nearl.raw.p, (int)nearl.raw.cap, bits);
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(h, ctr, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
@@ -330,15 +307,16 @@ __global__ void k_fcell(int ncell, const int* off, const int* src, const double*
 }
 
 // f_i = (F summed from the root down to the leaf) + sum_{j near, j != i} m_j / d^2,
-// partners in ascending id, bodies in sorted order
-__global__ void __launch_bounds__(64) k_near_f(const int* leaves, int nleaves, const int* cb,
-                                               const int* ce, const int* parent, const int* off,
-                                               const int* src, const double* F, const double* sx,
-                                               const double* sy, const double* sz, const double* sm,
-                                               double* f) {
-  int li = blockIdx.x;
-  if (li >= nleaves) return;
-  int B = leaves[li];
+// partners in ascending id, bodies in sorted order; one thread per body
+__global__ void __launch_bounds__(256) k_near_f(int n, const int* __restrict__ leaf_of,
+                                                const int* __restrict__ cb, const int* __restrict__ ce,
+                                                const int* __restrict__ parent,
+                                                const int* __restrict__ off, const int* __restrict__ src,
+                                                const double* __restrict__ F,
+                                                const double4* __restrict__ pm, double* f) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int B = leaf_of[i];
   double far = 0.0;
   {
     int path[FMM_MAX_LEVEL + 2];
@@ -346,22 +324,18 @@ __global__ void __launch_bounds__(64) k_near_f(const int* leaves, int nleaves, c
     for (int q = B; q >= 0; q = parent[q]) path[len++] = q;
     for (int t = len - 1; t >= 0; t--) far = far + F[path[t]];
   }
-  int b = cb[B], e = ce[B];
-  for (int i0 = b; i0 < e; i0 += 64) {
-    int i = i0 + threadIdx.x;
-    bool act = i < e;
-    double xi = act ? sx[i] : 0.0, yi = act ? sy[i] : 0.0, zi = act ? sz[i] : 0.0;
-    double near = 0.0;
-    for (int k = off[B]; k < off[B + 1]; k++) {
-      int A = src[k];
-      for (int j = cb[A]; j < ce[A]; j++) {
-        double dx = sx[j] - xi, dy = sy[j] - yi, dz = sz[j] - zi;
-        double d2 = (dx * dx + dy * dy) + dz * dz;
-        if (j != i && d2 > 0.0) near = near + sm[j] / d2;
-      }
+  double4 me = pm[i];
+  double near = 0.0;
+  for (int k = off[B]; k < off[B + 1]; k++) {
+    int A = src[k];
+    for (int j = cb[A]; j < ce[A]; j++) {
+      double4 q = pm[j];
+      double dx = q.x - me.x, dy = q.y - me.y, dz = q.z - me.z;
+      double d2 = (dx * dx + dy * dy) + dz * dz;
+      if (j != i && d2 > 0.0) near = near + q.w / d2;
     }
-    if (act) f[i] = far + near;
   }
+  f[i] = far + near;
 }
 
 __global__ void k_fmin(int first, int count, const int* cb, const int* ce, const int* c0,
@@ -383,23 +357,17 @@ __global__ void k_fmin(int first, int count, const int* cb, const int* ce, const
 }
 
 void estimate_walk(Ctx& c) {
-  if (!g_walk_tables) {
-    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_binom), fmm_binom_table, sizeof(fmm_binom_table)));
-    g_walk_tables = true;
-  }
   hipStream_t s = c.stream;
   int nc = (int)c.ncell;
   ensure(c.ws, c.fcell, nc);
   ensure(c.ws, c.fmin, nc);
   ensure(c.ws, c.fpart, (size_t)c.n);
-  run_walk<0>(c, c.est_far, c.est_near);
+  run_walk<0, 0>(c, c.est_far, c.est_near);
   hipLaunchKernelGGL(k_fcell, dim3((nc + 255) / 256), dim3(256), 0, s, nc, c.est_far.off.p,
                      c.est_far.src.p, c.c_mass.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.fcell.p);
-  // leaves list was built by the upward pass in c_split (flag | off | leaves)
-  const int* leaves = c.c_split.p + 2 * (nc + 32);
-  hipLaunchKernelGGL(k_near_f, dim3((unsigned)c.nleaf), dim3(64), 0, s, leaves, (int)c.nleaf,
-                     c.c_begin.p, c.c_end.p, c.c_parent.p, c.est_near.off.p, c.est_near.src.p,
-                     c.fcell.p, c.sx.p, c.sy.p, c.sz.p, c.sm.p, c.fpart.p);
+  hipLaunchKernelGGL(k_near_f, dim3((unsigned)ceil_div(c.n, 256)), dim3(256), 0, s, (int)c.n,
+                     c.leaf_of.p, c.c_begin.p, c.c_end.p, c.c_parent.p, c.est_near.off.p,
+                     c.est_near.src.p, c.fcell.p, c.pm.p, c.fpart.p);
   for (int level = c.depth; level >= 0; level--) {
     int first = c.lvl_first[level], count = c.lvl_count[level];
     hipLaunchKernelGGL(k_fmin, dim3((count + 127) / 128), dim3(128), 0, s, first, count, c.c_begin.p,
@@ -408,6 +376,21 @@ void estimate_walk(Ctx& c) {
   HIPCHK(hipGetLastError());
 }
 
-void mac_walk(Ctx& c) { run_walk<1>(c, c.m2l, c.p2p); }
+template <int P>
+static bool mac_dispatch(Ctx& c) {
+  if constexpr (P > FMM_GPU_PMAX) {
+    return false;
+  } else {
+    if (c.p == P) {
+      run_walk<1, P>(c, c.m2l, c.p2p);
+      return true;
+    }
+    return mac_dispatch<P + 1>(c);
+  }
+}
+
+void mac_walk(Ctx& c) {
+  if (!mac_dispatch<1>(c)) throw hip_error{hipErrorInvalidValue, "walk order not compiled"};
+}
 
 }  // namespace fmm
