@@ -95,12 +95,15 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plummer_1m", choices=["plummer_1m", "plummer_4k", "kroupa_4m"])
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precisions", default="fp64,mixed",
+                    help="comma list; the last one is the reported value")
+    ap.add_argument("--root-levels", type=int, default=3)
     ap.add_argument("--n-leaf", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frac", type=float, default=1.0 / 64)
     ap.add_argument("--err-sinks", type=int, default=4096)
     args = ap.parse_args()
+    args.precisions = [x for x in args.precisions.split(",") if x]
     if args.gpus != 1:
         print(json.dumps({"error": "this build evaluates one force pass on one GPU; "
                                    "multi-GPU runs are not part of it (--gpus 1)"}))
@@ -118,39 +121,50 @@ def main():
     dev = torch.device("cuda:0")
     dpos = torch.from_numpy(pos).to(dev)
     dmass = torch.from_numpy(mass).to(dev)
-    f = fmm.FMM(p=p, err_tol=err_tol, n_leaf=args.n_leaf, precision=args.precision)
-    acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
-    pot = torch.empty((n,), dtype=torch.float64, device=dev)
-    for _ in range(args.warmup):
-        f.forces(dpos, dmass, out=(acc, pot))
-    torch.cuda.synchronize()
-    stage_ms = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        f.forces(dpos, dmass, out=(acc, pot))
-        stage_ms.append(f.stats())      # per-call HIP-event stage times (syncs the stream)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    st = stage_ms[-1]
-    ms_step = 1e3 * dt / args.steps
-
-    # force error on seeded sinks against the compensated direct sum
     rng = np.random.default_rng(cfg["seed"] + 99)
     sinks = np.sort(rng.choice(n, min(args.err_sinks, n), replace=False)).astype(np.int32)
-    ad, _ = fmm.direct(dpos, dmass, sinks=torch.from_numpy(sinks).to(dev))
-    a = acc[torch.from_numpy(sinks).long().to(dev)]
-    rel = (torch.linalg.norm(a - ad, dim=1) / torch.linalg.norm(ad, dim=1)).cpu().numpy()
+    dsinks = torch.from_numpy(sinks).to(dev)
+    ad, _ = fmm.direct(dpos, dmass, sinks=dsinks)
+
+    def run(precision):
+        f = fmm.FMM(p=p, err_tol=err_tol, n_leaf=args.n_leaf, precision=precision,
+                    root_levels=args.root_levels)
+        acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        pot = torch.empty((n,), dtype=torch.float64, device=dev)
+        for _ in range(args.warmup):
+            f.forces(dpos, dmass, out=(acc, pot))
+        torch.cuda.synchronize()
+        stage_ms = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            f.forces(dpos, dmass, out=(acc, pot))
+            stage_ms.append(f.stats())      # per-call HIP-event stage times (syncs the stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        a = acc[dsinks.long()]
+        rel = (torch.linalg.norm(a - ad, dim=1) / torch.linalg.norm(ad, dim=1)).cpu().numpy()
+        f.close()
+        return {"ms": 1e3 * dt / args.steps, "stages": stage_ms, "acc": acc, "rel": rel}
+
+    res = {pr: run(pr) for pr in args.precisions}
+    main_pr = args.precisions[-1]
+    R = res[main_pr]
+    st = R["stages"][-1]
+    ms_step = R["ms"]
+    rel = R["rel"]
 
     # dominant kernel roofline (algorithmic FLOPs / average event time)
-    m2l_ms = np.mean([s["ms_m2l"] for s in stage_ms])
-    p2p_ms = np.mean([s["ms_p2p"] for s in stage_ms])
+    m2l_ms = np.mean([s["ms_m2l"] for s in R["stages"]])
+    p2p_ms = np.mean([s["ms_p2p"] for s in R["stages"]])
     f_m2l = m2l_flops(p) * st["n_m2l"]
     f_leaf = P2P_FLOPS * st["n_p2p_pairs"] + l2p_flops(p) * n
-    peak = PEAK_FP64 if args.precision == "fp64" else PEAK_FP32
+    peak = PEAK_FP64 if main_pr == "fp64" else PEAK_FP32
+    kname = "k_m2l_fp64" if main_pr == "fp64" else "k_m2l_fp32 (+ k_m2l_fp64 for root-level pairs)"
     if p2p_ms >= m2l_ms:
-        dom = {"kernel": "k_leaf_eval (L2P + P2P)", "flop": f_leaf, "ms": p2p_ms}
+        dom = {"kernel": "k_leaf_eval (L2P + P2P)" if main_pr == "fp64" else "k_leaf_eval_mixed",
+               "flop": f_leaf, "ms": p2p_ms}
     else:
-        dom = {"kernel": "k_m2l_fp64", "flop": f_m2l, "ms": m2l_ms}
+        dom = {"kernel": kname, "flop": f_m2l, "ms": m2l_ms}
     achieved = dom["flop"] / (dom["ms"] * 1e-3)
     # the dominant stages are vector-ALU bound (no dense contraction on this path)
     roof = {"bound": "alu", "kernel": dom["kernel"],
@@ -158,6 +172,17 @@ def main():
             "frac": achieved / peak, "traffic": None}
     other = {"m2l": {"ms": m2l_ms, "tflops": f_m2l / (m2l_ms * 1e-3) / 1e12},
              "leaf_eval": {"ms": p2p_ms, "tflops": f_leaf / (p2p_ms * 1e-3) / 1e12}}
+    forms = {}
+    for pr, r in res.items():
+        forms[pr] = {"evals_per_s": 1e3 / r["ms"], "ms_per_eval": r["ms"],
+                     "median_err_vs_direct": float(np.median(r["rel"])),
+                     "p99_err_vs_direct": float(np.percentile(r["rel"], 99))}
+    if "fp64" in res and "mixed" in res:
+        a64, amx = res["fp64"]["acc"], res["mixed"]["acc"]
+        d = (torch.linalg.norm(amx - a64, dim=1) / torch.linalg.norm(a64, dim=1)).cpu().numpy()
+        forms["mixed_vs_fp64"] = {"median": float(np.median(d)), "p99": float(np.percentile(d, 99)),
+                                  "max": float(d.max())}
+        forms["speedup_mixed_over_fp64"] = res["fp64"]["ms"] / res["mixed"]["ms"]
 
     out = {
         "metric": "force evals/sec at N=2^20, 1e-7 median rel. force err; mixed vs FP64 GPU",
@@ -166,15 +191,17 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": "f64" if main_pr == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: Plummer N={n}, Henon units, p={p}, eps={err_tol}, "
-                               f"n_leaf={args.n_leaf}, precision={args.precision}",
-                   "n": n, "p": p, "err_tol": err_tol, "n_leaf": args.n_leaf, "precision": args.precision},
+        "config": {"workload": f"{args.workload}: N={n}, Henon units, p={p}, eps={err_tol}, "
+                               f"n_leaf={args.n_leaf}, precision={main_pr}",
+                   "n": n, "p": p, "err_tol": err_tol, "n_leaf": args.n_leaf, "precision": main_pr,
+                   "root_levels": args.root_levels},
         "direct_interactions_per_s": n * (n - 1) / (ms_step * 1e-3),
         "force_error": {"median": float(np.median(rel)), "p99": float(np.percentile(rel, 99)),
                         "max": float(rel.max()), "sinks": int(len(sinks))},
-        "stages_ms": {k: round(float(np.mean([s[k] for s in stage_ms])), 4)
+        "forms": forms,
+        "stages_ms": {k: round(float(np.mean([s[k] for s in R["stages"]])), 4)
                       for k in ("ms_tree", "ms_upward", "ms_estimate", "ms_walk", "ms_m2l",
                                 "ms_local", "ms_p2p", "ms_total")},
         "counts": {k: int(st[k]) for k in ("ncell", "nleaf", "depth", "n_m2l", "n_p2p_cells",

@@ -61,12 +61,11 @@ void evaluate(Ctx& c, double* acc, double* pot) {
   size_t nl = (size_t)nc * ncoef(c.p) * 2;
   ensure(c.ws, c.loc, nl);
   if (c.have_events) HIPCHK(hipEventRecord(c.ev[4], s));
+  HIPCHK(hipMemsetAsync(c.loc.p, 0, nl * sizeof(double), s));
   if (c.prm.precision == FMM_MIXED)
     launch_m2l_mixed(c);
-  else {
-    HIPCHK(hipMemsetAsync(c.loc.p, 0, nl * sizeof(double), s));
+  else
     launch_m2l_fp64(c);
-  }
   if (c.have_events) HIPCHK(hipEventRecord(c.ev[5], s));
   launch_l2l(c);
   if (c.have_events) HIPCHK(hipEventRecord(c.ev[6], s));
@@ -392,7 +391,7 @@ void fmm_destroy(fmm_ctx* ctx) {
     rel(c.idx[k]);
     rel(c.front[k]);
   }
-  rel(c.sx); rel(c.sy); rel(c.sz); rel(c.sm); rel(c.pm); rel(c.pkb); rel(c.fpart); rel(c.leaf_of); rel(c.sort_hist);
+  rel(c.sx); rel(c.sy); rel(c.sz); rel(c.sm); rel(c.pm); rel(c.pkb); rel(c.scale); rel(c.nmult); rel(c.fpart); rel(c.leaf_of); rel(c.sort_hist);
   rel(c.bbox_part); rel(c.rootbox); rel(c.c_level); rel(c.c_begin); rel(c.c_end); rel(c.c_parent);
   rel(c.c_child0); rel(c.c_nchild); rel(c.c_split); rel(c.c_mass); rel(c.c_sx); rel(c.c_sy);
   rel(c.c_sz); rel(c.c_cx); rel(c.c_cy); rel(c.c_cz); rel(c.c_rad); rel(c.c_rad2bits); rel(c.mult);

@@ -104,4 +104,11 @@ __device__ __forceinline__ void cget(const double* re, const double* im, int str
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// n! in FP64 by repeated multiplication (evaluation-side normalisations only)
+__device__ __forceinline__ double fmm_fact_dev(int n) {
+  double r = 1.0;
+  for (int i = 2; i <= n; i++) r *= (double)i;
+  return r;
+}
+
 }  // namespace fmm

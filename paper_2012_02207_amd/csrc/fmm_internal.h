@@ -126,6 +126,8 @@ struct Ctx {
   dbuf<double> pkb;   // ncell x (p+1): C(p, k) * P_k, as the acceptance test forms it
   dbuf<double> fcell, fmin;
   dbuf<double> loc;   // ncell x ncoef x 2
+  dbuf<double> scale; // mixed precision: expansion scale per cell
+  dbuf<float> nmult;  // mixed precision: normalised FP32 moments, (p+1)^2 per cell
 
   // walks
   dbuf<int2> front[2];
@@ -162,6 +164,7 @@ bool check_inputs_dev(Ctx& c, const double* pos, const double* mass, int64_t n);
 
 // M2L launchers (one per compiled order)
 void launch_m2l_fp64(Ctx& c);
+void launch_m2l_fp64_range(Ctx& c, int first_lo);
 void launch_m2l_mixed(Ctx& c);
 bool mixed_supported(int p);
 

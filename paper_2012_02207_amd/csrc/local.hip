@@ -96,28 +96,10 @@ __device__ __forceinline__ double rsqrt_d(double x) {
   return y;
 }
 
-// One thread per sink body (bodies in sorted order, so a wavefront covers one
-// or a few neighbouring leaves and its loads are mostly broadcasts).  Far field
-// by L2P: the leaf's local expansion shifted to the body (Phi = -Re L'_0^0,
-// a = (-Re L'_1^1, -Im L'_1^1, Re L'_1^0)); near field by direct summation over
-// the leaf's P2P sources (ascending), FP64.
-__global__ void __launch_bounds__(256) k_leaf_eval(int p, int n, const int* __restrict__ leaf_of,
-                                                   const int* __restrict__ cb, const int* __restrict__ ce,
-                                                   const int* __restrict__ off, const int* __restrict__ srcl,
-                                                   const double* __restrict__ cx, const double* __restrict__ cy,
-                                                   const double* __restrict__ cz, const double* __restrict__ loc,
-                                                   const double4* __restrict__ pm,
-                                                   const int* __restrict__ perm, double eps2, double* acc,
-                                                   double* pot) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int B = leaf_of[i];
-  int nc = ncoef(p);
-  const double* L = loc + (size_t)B * nc * 2;
-  double4 me = pm[i];
-  double xi = me.x, yi = me.y, zi = me.z;
-  // ---- L2P: harmonics of X = x_i - z_B column by column, each used once
-  double X = xi - cx[B], Y = yi - cy[B], Z = zi - cz[B];
+// L2P: the local expansion L shifted to offset (X, Y, Z) from its centre;
+// harmonics built column by column and each used once.
+__device__ __forceinline__ void l2p_eval(int p, const double* __restrict__ L, double X, double Y,
+                                         double Z, double& ax, double& ay, double& az, double& ph) {
   double r2 = fma(X, X, fma(Y, Y, Z * Z));
   double s00 = 0.0, s10 = 0.0, s11r = 0.0, s11i = 0.0;
   double dr = 1.0, di = 0.0;  // Y_m^m
@@ -161,7 +143,34 @@ __global__ void __launch_bounds__(256) k_leaf_eval(int p, int n, const int* __re
       }
     }
   }
-  double ax = -s11r, ay = -s11i, az = s10, ph = -s00;
+  ax = -s11r;
+  ay = -s11i;
+  az = s10;
+  ph = -s00;
+}
+
+// One thread per sink body (bodies in sorted order, so a wavefront covers one
+// or a few neighbouring leaves and its loads are mostly broadcasts).  Far field
+// by L2P: the leaf's local expansion shifted to the body (Phi = -Re L'_0^0,
+// a = (-Re L'_1^1, -Im L'_1^1, Re L'_1^0)); near field by direct summation over
+// the leaf's P2P sources (ascending), FP64.
+__global__ void __launch_bounds__(256) k_leaf_eval(int p, int n, const int* __restrict__ leaf_of,
+                                                   const int* __restrict__ cb, const int* __restrict__ ce,
+                                                   const int* __restrict__ off, const int* __restrict__ srcl,
+                                                   const double* __restrict__ cx, const double* __restrict__ cy,
+                                                   const double* __restrict__ cz, const double* __restrict__ loc,
+                                                   const double4* __restrict__ pm,
+                                                   const int* __restrict__ perm, double eps2, double* acc,
+                                                   double* pot) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int B = leaf_of[i];
+  int nc = ncoef(p);
+  const double* L = loc + (size_t)B * nc * 2;
+  double4 me = pm[i];
+  double xi = me.x, yi = me.y, zi = me.z;
+  double ax, ay, az, ph;
+  l2p_eval(p, L, xi - cx[B], yi - cy[B], zi - cz[B], ax, ay, az, ph);
   // ---- P2P
   double nx = 0.0, ny = 0.0, nz = 0.0, np = 0.0;
   for (int q = off[B]; q < off[B + 1]; q++) {
@@ -188,7 +197,65 @@ __global__ void __launch_bounds__(256) k_leaf_eval(int p, int n, const int* __re
   pot[o] = ph + np;
 }
 
+// Mixed precision: L2P in FP64; P2P pair arithmetic in FP32 on the separation
+// formed in FP64 and rounded once (relative coordinates), accumulated in FP32
+// over one source leaf at a time and carried into FP64 (blocked compensation:
+// the FP32 rounding error grows with the leaf size, not with the list length).
+__global__ void __launch_bounds__(256) k_leaf_eval_mixed(int p, int n, const int* __restrict__ leaf_of,
+                                                         const int* __restrict__ cb, const int* __restrict__ ce,
+                                                         const int* __restrict__ off, const int* __restrict__ srcl,
+                                                         const double* __restrict__ cx, const double* __restrict__ cy,
+                                                         const double* __restrict__ cz, const double* __restrict__ loc,
+                                                         const double4* __restrict__ pm,
+                                                         const int* __restrict__ perm, float eps2, double* acc,
+                                                         double* pot) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int B = leaf_of[i];
+  const double* L = loc + (size_t)B * ncoef(p) * 2;
+  double4 me = pm[i];
+  double xi = me.x, yi = me.y, zi = me.z;
+  double ax, ay, az, ph;
+  l2p_eval(p, L, xi - cx[B], yi - cy[B], zi - cz[B], ax, ay, az, ph);
+  double nx = 0.0, ny = 0.0, nz = 0.0, np = 0.0;
+  for (int q = off[B]; q < off[B + 1]; q++) {
+    int A = srcl[q];
+    int jb = cb[A], je = ce[A];
+    float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
+    for (int j = jb; j < je; j++) {
+      double4 s = pm[j];
+      float dx = (float)(s.x - xi), dy = (float)(s.y - yi), dz = (float)(s.z - zi);
+      float d2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+      float rinv = __builtin_amdgcn_rsqf(d2);
+      rinv = (j != i && d2 > 0.f) ? rinv : 0.f;
+      float mr = (float)s.w * rinv;
+      float mr3 = mr * rinv * rinv;
+      fx = fmaf(mr3, dx, fx);
+      fy = fmaf(mr3, dy, fy);
+      fz = fmaf(mr3, dz, fz);
+      fp -= mr;
+    }
+    nx += (double)fx;
+    ny += (double)fy;
+    nz += (double)fz;
+    np += (double)fp;
+  }
+  int o = perm[i];
+  acc[3 * (int64_t)o] = ax + nx;
+  acc[3 * (int64_t)o + 1] = ay + ny;
+  acc[3 * (int64_t)o + 2] = az + nz;
+  pot[o] = ph + np;
+}
+
 void launch_leaf_eval(Ctx& c, double* acc, double* pot) {
+  if (c.prm.precision == FMM_MIXED) {
+    hipLaunchKernelGGL(k_leaf_eval_mixed, dim3((unsigned)ceil_div(c.n, 256)), dim3(256), 0, c.stream, c.p,
+                       (int)c.n, c.leaf_of.p, c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.c_cx.p,
+                       c.c_cy.p, c.c_cz.p, c.loc.p, c.pm.p, c.idx[0].p, (float)(c.eps_soft * c.eps_soft),
+                       acc, pot);
+    HIPCHK(hipGetLastError());
+    return;
+  }
   hipLaunchKernelGGL(k_leaf_eval, dim3((unsigned)ceil_div(c.n, 256)), dim3(256), 0, c.stream, c.p,
                      (int)c.n, c.leaf_of.p, c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.c_cx.p,
                      c.c_cy.p, c.c_cz.p, c.loc.p, c.pm.p, c.idx[0].p, c.eps_soft * c.eps_soft, acc, pot);

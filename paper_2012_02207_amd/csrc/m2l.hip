@@ -172,7 +172,7 @@ __device__ __forceinline__ void reduce_order(const double* v, double* red, doubl
 constexpr int M2L_WAVES = 4;  // sinks per workgroup (one per wavefront)
 
 template <int P>
-__global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l_fp64(int ncell, const int* __restrict__ off,
+__global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l_fp64(int ncell, int first_lo, const int* __restrict__ off,
                                                              const int* __restrict__ src,
                                                              const double* __restrict__ cx,
                                                              const double* __restrict__ cy,
@@ -195,6 +195,19 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l_fp64(int ncell, const in
   int B = blk * M2L_WAVES + wv;
   if (blk >= nblk || B >= ncell) return;
   int b = off[B], e = off[B + 1];
+  if (B >= first_lo) {
+    // mixed precision: only the sources above the root levels (a prefix of
+    // the ascending, breadth-first list) are handled in FP64
+    int lo = b, hi = e;
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (src[mid] < first_lo)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    e = lo;
+  }
   if (b == e) return;
   int lane = threadIdx.x & 63;
   double* red = red_all[wv];
@@ -359,28 +372,32 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l_fp64(int ncell, const in
 }
 
 template <int P>
-static void launch_p(Ctx& c) {
+static void launch_p(Ctx& c, int first_lo) {
   int nc = (int)c.ncell;
   int nblk = (nc + M2L_WAVES - 1) / M2L_WAVES;
   unsigned grid = 8u * (unsigned)((nblk + 7) / 8);
-  hipLaunchKernelGGL(k_m2l_fp64<P>, dim3(grid), dim3(64 * M2L_WAVES), 0, c.stream, nc, c.m2l.off.p, c.m2l.src.p,
+  hipLaunchKernelGGL(k_m2l_fp64<P>, dim3(grid), dim3(64 * M2L_WAVES), 0, c.stream, nc, first_lo, c.m2l.off.p, c.m2l.src.p,
                      c.c_cx.p, c.c_cy.p, c.c_cz.p, c.mult.p, c.loc.p);
 }
 
 template <int P>
-static bool dispatch(Ctx& c) {
+static bool dispatch(Ctx& c, int first_lo) {
   if constexpr (P > FMM_GPU_PMAX) {
     return false;
   } else {
     if (c.p == P) {
-      launch_p<P>(c);
+      launch_p<P>(c, first_lo);
       return true;
     }
-    return dispatch<P + 1>(c);
+    return dispatch<P + 1>(c, first_lo);
   }
 }
 
-void launch_m2l_fp64(Ctx& c) {
+void launch_m2l_fp64(Ctx& c) { launch_m2l_fp64_range(c, (int)c.ncell); }
+
+// FP64 M2L for all pairs whose sink is above first_lo or whose source is
+// (first_lo = ncell: every pair); writes loc, which must be zeroed before
+void launch_m2l_fp64_range(Ctx& c, int first_lo) {
   if (!g_m2l_tables) {
     // compact the dense tables to their structural non-zeros (row-major)
     static_assert(CSWAP_DOUBLES <= 8192, "compacted swap table");
@@ -393,7 +410,7 @@ void launch_m2l_fp64(Ctx& c) {
     HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_fact_m2l), fmm_fact_table, sizeof(double) * (2 * FMM_GPU_PMAX + 2)));
     g_m2l_tables = true;
   }
-  if (!dispatch<1>(c)) throw hip_error{hipErrorInvalidValue, "M2L order not compiled"};
+  if (!dispatch<1>(c, first_lo)) throw hip_error{hipErrorInvalidValue, "M2L order not compiled"};
   HIPCHK(hipGetLastError());
 }
 

@@ -1,10 +1,436 @@
-// Mixed-precision M2L (FP32 below the root levels) -- not built yet.
+// Mixed-precision M2L on gfx950: the rotation-accelerated operator of section
+// 2.4 in FP32 for cell pairs below the root levels (the FP64 kernel handles
+// pairs that touch a cell above level root_levels).
+//
+// Range and conditioning: the FP32 operands are the moments in the
+// rotation-invariant normalised real basis, scaled by the source size,
+//   N_n^m = G_n^m M_n^m / rho_A^n,  G_n^0 = n!,  G_n^m = sqrt(2 (n-m)!(n+m)!),
+// for which ||N_n|| = P_n / rho_A^n <= M_A (the P_n of section 2.3), and in
+// which the swap matrices G W_n G^-1 are orthogonal (entries in [-1, 1]).  The
+// translation along z becomes
+//   Lt_n^m = sum_k N'_k^m T(n,k,m) (rho_B/r)^n (rho_A/r)^k / r,
+//   T(n,k,m) = (-1)^(n+m) (n+k)! G_n^m / ((n-m)!(n+m)! G_k^m),
+// with (rho_A + rho_B) < r, so every factor is O(1).  The result
+// Lt = rho_B^n G L / ((n-m)!(n+m)!) is summed per sink in FP64 and converted
+// back to the standard local coefficients in FP64.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <type_traits>
+#include <vector>
+
 #include "fmm_device.h"
+#include "fmm_tables.h"
 
 namespace fmm {
 
-bool mixed_supported(int) { return false; }
+namespace mx {
 
-void launch_m2l_mixed(Ctx&) { throw hip_error{hipErrorNotSupported, "mixed-precision M2L"}; }
+template <int I, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < E) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, E>(f);
+  }
+}
+
+constexpr double cfact(int n) {
+  double r = 1.0;
+  for (int i = 2; i <= n; i++) r *= (double)i;
+  return r;
+}
+constexpr int rb_m(int j) { return (j + 1) >> 1; }
+constexpr bool rb_re(int j) { return j == 0 || (j & 1); }
+constexpr bool swap_nz(int n, int i, int j) {
+  return rb_re(i) == rb_re(j) && (((rb_m(i) + rb_m(j) + n) & 1) == (rb_re(i) ? 0 : 1));
+}
+constexpr int swap_nnz_row(int n, int i) {
+  int c = 0;
+  for (int j = 0; j < 2 * n + 1; j++) c += swap_nz(n, i, j) ? 1 : 0;
+  return c;
+}
+constexpr int swap_nnz(int n) {
+  int c = 0;
+  for (int i = 0; i < 2 * n + 1; i++) c += swap_nnz_row(n, i);
+  return c;
+}
+constexpr int cswoff(int n) {
+  int c = 0;
+  for (int k = 0; k < n; k++) c += swap_nnz(k);
+  return c;
+}
+constexpr int crowoff(int n, int i) {
+  int c = cswoff(n);
+  for (int r = 0; r < i; r++) c += swap_nnz_row(n, r);
+  return c;
+}
+constexpr int crank(int n, int i, int j) {
+  int c = 0;
+  for (int t = 0; t < j; t++) c += swap_nz(n, i, t) ? 1 : 0;
+  return c;
+}
+constexpr int swoff(int n) { return n * (4 * n * n - 1) / 3; }
+
+// normalisation G_n^m of real-basis entry j of order n (m = rb_m(j))
+constexpr double csqrt_newton(double x) {
+  if (x <= 0) return 0;
+  double r = x > 1 ? x : 1;
+  for (int i = 0; i < 200; i++) r = 0.5 * (r + x / r);
+  return r;
+}
+constexpr double gnorm(int n, int m) {
+  return m == 0 ? cfact(n) : csqrt_newton(2.0 * cfact(n - m) * cfact(n + m));
+}
+// translation constant T(n, k, m)
+constexpr double tconst(int n, int k, int m) {
+  double s = ((n + m) & 1) ? -1.0 : 1.0;
+  return s * cfact(n + k) * gnorm(n, m) / (cfact(n - m) * cfact(n + m) * gnorm(k, m));
+}
+
+typedef __attribute__((address_space(3))) float lfloat;
+
+template <int N>
+__device__ __forceinline__ void swap_apply(float* v, const lfloat* sw) {
+  constexpr int D = 2 * N + 1;
+  float out[D];
+  static_for<0, D>([&](auto ic) {
+    constexpr int i = ic;
+    float s = 0.f;
+    static_for<0, D>([&](auto jc) {
+      constexpr int j = jc;
+      if constexpr (swap_nz(N, i, j)) {
+        constexpr int q = crowoff(N, i) + crank(N, i, j);
+        float w = sw[q];
+        if constexpr (crank(N, i, j) == 0)
+          s = w * v[j];
+        else
+          s = fmaf(w, v[j], s);
+      }
+    });
+    out[i] = s;
+  });
+  static_for<0, D>([&](auto ic) { v[ic] = out[ic]; });
+}
+
+template <int N>
+__device__ __forceinline__ void zrot(float* v, float c1, float s1) {
+  float cm = c1, sm = s1;
+  static_for<1, N + 1>([&](auto mc) {
+    constexpr int m = mc;
+    if constexpr (m > 1) {
+      float c2 = fmaf(cm, c1, -sm * s1);
+      sm = fmaf(sm, c1, cm * s1);
+      cm = c2;
+    }
+    float C = v[2 * m - 1], S = v[2 * m];
+    v[2 * m - 1] = fmaf(C, cm, -S * sm);
+    v[2 * m] = fmaf(C, sm, S * cm);
+  });
+}
+
+// branch-free two-stage wave reduction through LDS (see the FP64 kernel);
+// lane j (< D) adds the FP32 total of value j to its FP64 accumulator
+template <int D, int RED_ROWS>
+__device__ __forceinline__ void reduce_order(const float* v, float* red, double* acc_slot, int lane,
+                                             bool act) {
+  static_assert(D < RED_ROWS, "reduction buffer too small");
+  constexpr int S = (64 / D) < 8 ? (64 / D) : 8;
+  constexpr int G = (64 + S - 1) / S;
+#pragma unroll
+  for (int j = 0; j < D; j++) red[j * 65 + lane] = act ? v[j] : 0.f;
+  __builtin_amdgcn_wave_barrier();
+  int j = lane / S, sg = lane % S;
+  int jr = j < D ? j : D - 1;
+  int l0 = sg * G;
+  float part = 0.f;
+#pragma unroll
+  for (int t = 0; t < G; t++) {
+    int l = l0 + t;
+    float x = red[jr * 65 + (l < 64 ? l : 63)];
+    part += (l < 64) ? x : 0.f;
+  }
+  part = j < D ? part : 0.f;
+  __builtin_amdgcn_wave_barrier();
+  red[(RED_ROWS - 1) * 65 + lane] = part;
+  __builtin_amdgcn_wave_barrier();
+  int lr = lane < D ? lane : D - 1;
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < S; t++) s += (double)red[(RED_ROWS - 1) * 65 + lr * S + t];
+  *acc_slot += lane < D ? s : 0.0;
+  __builtin_amdgcn_wave_barrier();
+}
+
+}  // namespace mx
+
+constexpr int MX_CSWAP = mx::cswoff(FMM_GPU_PMAX + 1);
+static __constant__ float c_cswap32[MX_CSWAP];
+static bool g_mx_tables = false;
+constexpr int MX_WAVES = 4;
+
+// first source of [b, e) whose id is >= first_lo (ids are breadth first, so the
+// sources above the root levels form a prefix of the ascending list)
+__device__ __forceinline__ int split_point(const int* src, int b, int e, int first_lo) {
+  int lo = b, hi = e;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (src[mid] < first_lo)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <int P>
+__global__ void __launch_bounds__(64 * MX_WAVES) k_m2l_fp32(int ncell, int first_lo,
+                                                            const int* __restrict__ off,
+                                                            const int* __restrict__ src,
+                                                            const double* __restrict__ cx,
+                                                            const double* __restrict__ cy,
+                                                            const double* __restrict__ cz,
+                                                            const double* __restrict__ scale,
+                                                            const float* __restrict__ nmult,
+                                                            double* __restrict__ loc) {
+  using namespace mx;
+  constexpr int NC = ncoef(P);
+  constexpr int NR = (P + 1) * (P + 1);
+  constexpr int RED_ROWS = 2 * P + 2;
+  constexpr int NSW = cswoff(P + 1);
+  __shared__ float swt[NSW];
+  __shared__ float red_all[MX_WAVES][RED_ROWS * 65];
+  for (int t = threadIdx.x; t < NSW; t += 64 * MX_WAVES) swt[t] = c_cswap32[t];
+  __syncthreads();
+  int nlo = ncell - first_lo;  // sinks below the root levels
+  int nblk = (nlo + MX_WAVES - 1) / MX_WAVES;
+  int per = (nblk + 7) >> 3;
+  int blk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  int wv = threadIdx.x >> 6;
+  int B = first_lo + blk * MX_WAVES + wv;
+  if (blk >= nblk || B >= ncell) return;
+  int e = off[B + 1];
+  int b = split_point(src, off[B], e, first_lo);
+  if (b == e) return;
+  int lane = threadIdx.x & 63;
+  float* red = red_all[wv];
+  double acc[P + 1];
+#pragma unroll
+  for (int t = 0; t <= P; t++) acc[t] = 0.0;
+  double bx = cx[B], by = cy[B], bz = cz[B], sB = scale[B];
+  const lfloat* sw_it = (const lfloat*)swt;
+
+  for (int base = b; base < e; base += 64) {
+    int k = base + lane;
+    bool act = k < e;
+    int A = act ? src[k] : src[b];
+    // geometry in FP64, rounded once
+    double Rx = bx - cx[A], Ry = by - cy[A], Rz = bz - cz[A];
+    double rho2 = Rx * Rx + Ry * Ry;
+    double r = sqrt(rho2 + Rz * Rz);
+    double rho = sqrt(rho2);
+    double rinv = 1.0 / r;
+    float ca, sa;
+    if (rho > 0.0) {
+      double ri = 1.0 / rho;
+      ca = (float)(Ry * ri);
+      sa = (float)(Rx * ri);
+    } else {
+      ca = 0.f;
+      sa = 1.f;
+    }
+    float cb = (float)(Rz * rinv), sb = (float)(-rho * rinv);
+    float tA = (float)(scale[A] * rinv), tB = (float)(sB * rinv), fr = (float)rinv;
+    float pA[P + 1], pB[P + 1];
+    pA[0] = 1.f;
+    pB[0] = fr;
+#pragma unroll
+    for (int j = 1; j <= P; j++) {
+      pA[j] = pA[j - 1] * tA;
+      pB[j] = pB[j - 1] * tB;
+    }
+    const float* Mv = nmult + (size_t)A * NR;
+    constexpr int K0 = (P + 2) / 2;
+    constexpr int NLP = (P - K0 + 1) * (P - K0 + 1);
+    float Lp[NLP];
+#pragma unroll
+    for (int t = 0; t < NLP; t++) Lp[t] = 0.f;
+    static_for<K0, P + 1>([&](auto kc) {
+      constexpr int kk = kc;
+      __builtin_amdgcn_sched_barrier(0);
+      const lfloat* sw = sw_it;
+      asm volatile("" : "+v"(sw));
+      const float* Mo = Mv + kk * kk;
+      asm volatile("" : "+v"(Mo));
+      float v[2 * kk + 1];
+      static_for<0, 2 * kk + 1>([&](auto jc) { v[jc] = Mo[jc]; });
+      zrot<kk>(v, ca, sa);
+      swap_apply<kk>(v, sw);
+      zrot<kk>(v, cb, sb);
+      swap_apply<kk>(v, sw);
+      // fold into the partial local expansion: orders n <= P - kk
+      static_for<0, 2 * kk + 1>([&](auto jc) { v[jc] *= pA[kk]; });
+      static_for<0, P - kk + 1>([&](auto nc) {
+        constexpr int n = nc;
+        static_for<0, (n < kk ? n : kk) + 1>([&](auto mc) {
+          constexpr int m = mc;
+          constexpr float T = (float)tconst(n, kk, m);
+          if constexpr (m == 0) {
+            Lp[n * n] = fmaf(v[0], T, Lp[n * n]);
+          } else {
+            Lp[n * n + 2 * m - 1] = fmaf(v[2 * m - 1], T, Lp[n * n + 2 * m - 1]);
+            Lp[n * n + 2 * m] = fmaf(v[2 * m], T, Lp[n * n + 2 * m]);
+          }
+        });
+      });
+    });
+    float Mp[K0 * K0];
+    static_for<0, K0>([&](auto nc) {
+      constexpr int n = nc;
+      __builtin_amdgcn_sched_barrier(0);
+      const lfloat* sw = sw_it;
+      asm volatile("" : "+v"(sw));
+      const float* Mo = Mv + n * n;
+      asm volatile("" : "+v"(Mo));
+      float* v = Mp + n * n;
+      static_for<0, 2 * n + 1>([&](auto jc) { v[jc] = Mo[jc]; });
+      zrot<n>(v, ca, sa);
+      swap_apply<n>(v, sw);
+      zrot<n>(v, cb, sb);
+      swap_apply<n>(v, sw);
+      static_for<0, 2 * n + 1>([&](auto jc) { v[jc] *= pA[n]; });
+    });
+    static_for<0, P + 1>([&](auto nc) {
+      constexpr int n = nc;
+      __builtin_amdgcn_sched_barrier(0);
+      const lfloat* sw = sw_it;
+      asm volatile("" : "+v"(sw));
+      float w[2 * n + 1];
+      static_for<0, n + 1>([&](auto mc) {
+        constexpr int m = mc;
+        if constexpr (m <= P - n) {
+          float sC = 0.f, sS = 0.f;
+          if constexpr (n <= P - K0) {
+            sC = Lp[n * n + (m == 0 ? 0 : 2 * m - 1)];
+            if constexpr (m > 0) sS = Lp[n * n + 2 * m];
+          }
+          constexpr int KMAX = (P - n) < (K0 - 1) ? (P - n) : (K0 - 1);
+          static_for<m, KMAX + 1>([&](auto kc) {
+            constexpr int kk = kc;
+            constexpr float T = (float)tconst(n, kk, m);
+            sC = fmaf(Mp[kk * kk + (m == 0 ? 0 : 2 * m - 1)], T, sC);
+            if constexpr (m > 0) sS = fmaf(Mp[kk * kk + 2 * m], T, sS);
+          });
+          if constexpr (m == 0) {
+            w[0] = sC * pB[n];
+          } else {
+            w[2 * m - 1] = sC * pB[n];
+            w[2 * m] = sS * pB[n];
+          }
+        } else {
+          w[2 * m - 1] = 0.f;
+          w[2 * m] = 0.f;
+        }
+      });
+      swap_apply<n>(w, sw);
+      zrot<n>(w, cb, -sb);
+      swap_apply<n>(w, sw);
+      zrot<n>(w, ca, -sa);
+      reduce_order<2 * n + 1, RED_ROWS>(w, red, &acc[n], lane, act);
+    });
+  }
+  // back to standard coefficients: L_n^0 += Lt n! / rho_B^n,
+  // L_n^m += Lt sqrt((n-m)!(n+m)!/2) / rho_B^n; lane j owns real-basis entry j
+  double* out = loc + (size_t)B * NC * 2;
+  int m = (lane + 1) >> 1;
+  bool im = lane > 0 && !(lane & 1);
+  double isB = 1.0 / sB, pw = 1.0;
+#pragma unroll
+  for (int n = 0; n <= P; n++) {
+    if (lane < 2 * n + 1) {
+      double f = (m == 0 ? 1.0 : sqrt(0.5)) * sqrt(fmm_fact_dev(n - m) * fmm_fact_dev(n + m)) * pw;
+      out[2 * cidx(n, m) + (im ? 1 : 0)] += acc[n] * f;
+    }
+    pw *= isB;
+  }
+}
+
+// normalised, size-scaled FP32 moments of every cell (real basis, (P+1)^2 per cell)
+__global__ void k_normalize32(int p, int ncell, const double* mult, const double* scale, float* nmult) {
+  int nr = (p + 1) * (p + 1);
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)ncell * nr) return;
+  int c = (int)(t / nr), j = (int)(t % nr);
+  int n = 0;
+  while ((n + 1) * (n + 1) <= j) n++;
+  int jj = j - n * n, m = (jj + 1) >> 1;
+  bool im = jj > 0 && !(jj & 1);
+  double g = m == 0 ? fmm_fact_dev(n) : sqrt(2.0 * fmm_fact_dev(n - m) * fmm_fact_dev(n + m));
+  double v = mult[(size_t)c * ncoef(p) * 2 + 2 * cidx(n, m) + (im ? 1 : 0)];
+  nmult[t] = (float)(v * g * pow(scale[c], -(double)n));
+}
+
+// expansion scale per cell: its radius, or 1 for a point-like cell
+__global__ void k_scale(int ncell, const double* rad, double* scale) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncell) scale[c] = rad[c] > 0.0 ? rad[c] : 1.0;
+}
+
+template <int P>
+static void launch_p32(Ctx& c, int first_lo) {
+  int nc = (int)c.ncell;
+  int nlo = nc - first_lo;
+  if (nlo <= 0) return;
+  int nblk = (nlo + MX_WAVES - 1) / MX_WAVES;
+  unsigned grid = 8u * (unsigned)((nblk + 7) / 8);
+  hipLaunchKernelGGL(k_m2l_fp32<P>, dim3(grid), dim3(64 * MX_WAVES), 0, c.stream, nc, first_lo,
+                     c.m2l.off.p, c.m2l.src.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.scale.p, c.nmult.p, c.loc.p);
+}
+
+template <int P>
+static bool dispatch32(Ctx& c, int first_lo) {
+  if constexpr (P > FMM_GPU_PMAX) {
+    return false;
+  } else {
+    if (c.p == P) {
+      launch_p32<P>(c, first_lo);
+      return true;
+    }
+    return dispatch32<P + 1>(c, first_lo);
+  }
+}
+
+bool mixed_supported(int p) { return p >= 1 && p <= FMM_GPU_PMAX; }
+
+void launch_m2l_fp64_range(Ctx& c, int first_lo);
+
+void launch_m2l_mixed(Ctx& c) {
+  if (!g_mx_tables) {
+    // orthogonal swap matrices G W_n G^-1 in FP32, structural non-zeros only
+    std::vector<float> cs;
+    for (int n = 0; n <= FMM_GPU_PMAX; n++)
+      for (int i = 0; i < 2 * n + 1; i++)
+        for (int j = 0; j < 2 * n + 1; j++)
+          if (mx::swap_nz(n, i, j)) {
+            double w = fmm_swap_table[mx::swoff(n) + i * (2 * n + 1) + j];
+            cs.push_back((float)(w * mx::gnorm(n, mx::rb_m(i)) / mx::gnorm(n, mx::rb_m(j))));
+          }
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_cswap32), cs.data(), sizeof(float) * cs.size()));
+    g_mx_tables = true;
+  }
+  int nc = (int)c.ncell;
+  int K = c.prm.root_levels;
+  int first_lo = K <= c.depth ? c.lvl_first[K] : nc;
+  // FP64 for every pair touching a root-level cell (overwrites loc)
+  launch_m2l_fp64_range(c, first_lo);
+  if (first_lo >= nc) return;
+  ensure(c.ws, c.scale, (size_t)nc);
+  ensure(c.ws, c.nmult, (size_t)nc * (c.p + 1) * (c.p + 1));
+  hipLaunchKernelGGL(k_scale, dim3((nc + 255) / 256), dim3(256), 0, c.stream, nc, c.c_rad.p, c.scale.p);
+  int64_t tot = (int64_t)nc * (c.p + 1) * (c.p + 1);
+  hipLaunchKernelGGL(k_normalize32, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, c.stream, c.p, nc,
+                     c.mult.p, c.scale.p, c.nmult.p);
+  if (!dispatch32<1>(c, first_lo)) throw hip_error{hipErrorInvalidValue, "M2L order not compiled"};
+  HIPCHK(hipGetLastError());
+}
 
 }  // namespace fmm

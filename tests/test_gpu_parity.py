@@ -195,3 +195,64 @@ def test_errors(fmm):
     g.set_workspace_limit(0)
     acc, pot = g.forces(_dev(pos), _dev(mass))
     assert torch.isfinite(acc).all()
+
+
+# ---------------------------------------------------------------- mixed precision
+# Mixed precision keeps keys, tree, P2M/M2M, the estimate and the acceptance test
+# in FP64, so its interaction lists equal the FP64 ones.  Its forces are compared
+# with the FP64 oracle against a stated bound: median relative difference
+# <= 1e-6 (FP32 round-off of ~6e-8 per operation, amplified by the O(10)
+# operations per M2L coefficient and the cancellation in the force sum), and
+# the median error against the direct sum must stay below epsilon.
+MIXED_MEDIAN_BOUND = 1e-6
+
+
+@pytest.mark.parametrize("root_levels", [0, 3])
+def test_mixed_precision_bounded_difference(fmm, root_levels):
+    cfg = W.CONFIGS["plummer_4k"]
+    pos, _, mass = W.plummer(cfg["n"], cfg["seed"])
+    print(f"[gpu] mixed N={cfg['n']} root_levels={root_levels}", flush=True)
+    f = fmm.FMM(p=cfg["p"], err_tol=cfg["err_tol"], n_leaf=64, precision="mixed",
+                root_levels=root_levels)
+    acc, pot = f.forces(_dev(pos), _dev(mass))
+    acc, pot = acc.cpu().numpy(), pot.cpu().numpy()
+    o = oracle.Oracle()
+    oacc, opot = o.run(pos, mass, p=cfg["p"], err_tol=cfg["err_tol"], n_leaf=64)
+    assert np.array_equal(_sorted_pairs(f.export("m2l")), _sorted_pairs(o.get("m2l")))
+    assert np.array_equal(_sorted_pairs(f.export("p2p")), _sorted_pairs(o.get("p2p")))
+    rel = np.linalg.norm(acc - oacc, axis=1) / np.linalg.norm(oacc, axis=1)
+    relp = np.abs(pot - opot) / np.abs(opot)
+    print(f"mixed vs FP64 oracle: median {np.median(rel):.2e} p99 {np.percentile(rel, 99):.2e}")
+    assert np.median(rel) <= MIXED_MEDIAN_BOUND and np.percentile(rel, 99) <= 20 * MIXED_MEDIAN_BOUND
+    assert np.median(relp) <= MIXED_MEDIAN_BOUND
+    ad, _ = oracle.direct(pos, mass)
+    err = np.linalg.norm(acc - ad, axis=1) / np.linalg.norm(ad, axis=1)
+    assert np.median(err) < cfg["err_tol"]
+
+
+@pytest.mark.parametrize("p", [4, 8, 12])
+def test_mixed_orders(fmm, p):
+    pos, _, mass = W.plummer(3000, 200 + p)
+    print(f"[gpu] mixed p={p}", flush=True)
+    f = fmm.FMM(p=p, err_tol=1e-6, n_leaf=32, precision="mixed", root_levels=2)
+    acc, _ = f.forces(_dev(pos), _dev(mass))
+    acc = acc.cpu().numpy()
+    o = oracle.Oracle()
+    oacc, _ = o.run(pos, mass, p=p, err_tol=1e-6, n_leaf=32)
+    rel = np.linalg.norm(acc - oacc, axis=1) / np.linalg.norm(oacc, axis=1)
+    assert np.median(rel) <= MIXED_MEDIAN_BOUND, (p, np.median(rel))
+
+
+def test_mixed_kroupa_mass_spectrum(fmm):
+    """Kroupa masses (dynamic range ~1e3) plus a central particle of 1% of
+    the mass: the size-scaled FP32 moments stay in range."""
+    pos, _, mass = W.kroupa_with_central(4096, 77)
+    print("[gpu] mixed kroupa", flush=True)
+    f = fmm.FMM(p=8, err_tol=1e-7, n_leaf=64, precision="mixed", root_levels=2)
+    acc, _ = f.forces(_dev(pos), _dev(mass))
+    acc = acc.cpu().numpy()
+    o = oracle.Oracle()
+    oacc, _ = o.run(pos, mass, p=8, err_tol=1e-7, n_leaf=64)
+    rel = np.linalg.norm(acc - oacc, axis=1) / np.linalg.norm(oacc, axis=1)
+    assert np.all(np.isfinite(acc))
+    assert np.median(rel) <= MIXED_MEDIAN_BOUND
