@@ -135,7 +135,7 @@ fmm_status fmm_create(fmm_ctx** out, const fmm_params* prm) {
   ctx->c.prm = p;
   st = guarded(ctx, [&]() {
     HIPCHK(hipGetDevice(&ctx->c.device));
-    HIPCHK(hipHostMalloc((void**)&ctx->c.hbuf, 64 * sizeof(long long), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&ctx->c.hbuf, 128 * sizeof(long long), hipHostMallocDefault));
     for (auto& e : ctx->c.ev) HIPCHK(hipEventCreate(&e));
     return FMM_OK;
   });

@@ -172,22 +172,34 @@ __global__ void __launch_bounds__(256) k_leaf_eval(int p, int n, const int* __re
   double ax, ay, az, ph;
   l2p_eval(p, L, xi - cx[B], yi - cy[B], zi - cz[B], ax, ay, az, ph);
   // ---- P2P
+  // one flattened loop over the source bodies of all P2P partners (lanes of
+  // neighbouring leaves only diverge in the short advance step)
   double nx = 0.0, ny = 0.0, nz = 0.0, np = 0.0;
-  for (int q = off[B]; q < off[B + 1]; q++) {
+  int q = off[B], qe = off[B + 1];
+  int j = 0, je = 0;
+  if (q < qe) {
     int A = srcl[q];
-    int jb = cb[A], je = ce[A];
-    for (int j = jb; j < je; j++) {
-      double4 s = pm[j];
-      double dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
-      double d2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
-      double rinv = rsqrt_d(d2);
-      rinv = (j != i && d2 > 0.0) ? rinv : 0.0;
-      double mr = s.w * rinv;
-      double mr3 = mr * rinv * rinv;
-      nx = fma(mr3, dx, nx);
-      ny = fma(mr3, dy, ny);
-      nz = fma(mr3, dz, nz);
-      np -= mr;
+    j = cb[A];
+    je = ce[A];
+  }
+  while (q < qe) {
+    double4 s = pm[j];
+    double dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
+    double d2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+    double rinv = rsqrt_d(d2);
+    rinv = (j != i && d2 > 0.0) ? rinv : 0.0;
+    double mr = s.w * rinv;
+    double mr3 = mr * rinv * rinv;
+    nx = fma(mr3, dx, nx);
+    ny = fma(mr3, dy, ny);
+    nz = fma(mr3, dz, nz);
+    np -= mr;
+    if (++j == je) {
+      if (++q < qe) {
+        int A = srcl[q];
+        j = cb[A];
+        je = ce[A];
+      }
     }
   }
   int o = perm[i];
@@ -218,27 +230,38 @@ __global__ void __launch_bounds__(256) k_leaf_eval_mixed(int p, int n, const int
   double ax, ay, az, ph;
   l2p_eval(p, L, xi - cx[B], yi - cy[B], zi - cz[B], ax, ay, az, ph);
   double nx = 0.0, ny = 0.0, nz = 0.0, np = 0.0;
-  for (int q = off[B]; q < off[B + 1]; q++) {
+  float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
+  int q = off[B], qe = off[B + 1];
+  int j = 0, je = 0;
+  if (q < qe) {
     int A = srcl[q];
-    int jb = cb[A], je = ce[A];
-    float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
-    for (int j = jb; j < je; j++) {
-      double4 s = pm[j];
-      float dx = (float)(s.x - xi), dy = (float)(s.y - yi), dz = (float)(s.z - zi);
-      float d2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
-      float rinv = __builtin_amdgcn_rsqf(d2);
-      rinv = (j != i && d2 > 0.f) ? rinv : 0.f;
-      float mr = (float)s.w * rinv;
-      float mr3 = mr * rinv * rinv;
-      fx = fmaf(mr3, dx, fx);
-      fy = fmaf(mr3, dy, fy);
-      fz = fmaf(mr3, dz, fz);
-      fp -= mr;
+    j = cb[A];
+    je = ce[A];
+  }
+  while (q < qe) {
+    double4 s = pm[j];
+    float dx = (float)(s.x - xi), dy = (float)(s.y - yi), dz = (float)(s.z - zi);
+    float d2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+    float rinv = __builtin_amdgcn_rsqf(d2);
+    rinv = (j != i && d2 > 0.f) ? rinv : 0.f;
+    float mr = (float)s.w * rinv;
+    float mr3 = mr * rinv * rinv;
+    fx = fmaf(mr3, dx, fx);
+    fy = fmaf(mr3, dy, fy);
+    fz = fmaf(mr3, dz, fz);
+    fp -= mr;
+    if (++j == je) {  // end of a source leaf: carry the FP32 block into FP64
+      nx += (double)fx;
+      ny += (double)fy;
+      nz += (double)fz;
+      np += (double)fp;
+      fx = fy = fz = fp = 0.f;
+      if (++q < qe) {
+        int A = srcl[q];
+        j = cb[A];
+        je = ce[A];
+      }
     }
-    nx += (double)fx;
-    ny += (double)fy;
-    nz += (double)fz;
-    np += (double)fp;
   }
   int o = perm[i];
   acc[3 * (int64_t)o] = ax + nx;

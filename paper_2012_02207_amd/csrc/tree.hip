@@ -571,7 +571,7 @@ void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
   c.lvl_first.assign(1, 0);
   c.lvl_count.assign(1, 1);
   int64_t total_cells = 1;
-  ensure(c.ws, c.counters, 64);
+  ensure(c.ws, c.counters, 256);
   long long* tot = (long long*)c.counters.p;
   for (int level = 0;; level++) {
     int first = c.lvl_first[level], count = c.lvl_count[level];

@@ -21,20 +21,24 @@ static __constant__ double c_fact[2 * FMM_TABLE_PMAX + 2];
 static __constant__ double c_binom[FMM_TABLE_PMAX + 1][FMM_TABLE_PMAX + 1];
 static bool g_up_tables = false;
 
-constexpr int UP_LDS_DOUBLES = 7680;  // 60 KB of LDS per workgroup
+// LDS budget per P2M workgroup (dynamic, sized from p so that several
+// workgroups share a CU)
+constexpr int P2M_LDS_DOUBLES = 2560;  // 20 KB
 
 // bodies handled per LDS batch so that 2 * ncoef * batch doubles fit
 __host__ __device__ inline int p2m_batch(int p) {
   int nc = ncoef(p), b = 64;
-  while (b > 1 && 2 * nc * b > UP_LDS_DOUBLES) b >>= 1;
+  while (b > 1 && 2 * nc * b > P2M_LDS_DOUBLES) b >>= 1;
   return b;
 }
+
+constexpr int M2M_T = 128;  // threads per M2M workgroup: one per coefficient (p <= 14)
 
 __global__ void __launch_bounds__(64) k_p2m(int p, const int* leaves, int nleaves, const int* cb,
                                             const int* ce, const double* sx, const double* sy,
                                             const double* sz, const double* sm, const double* cx,
                                             const double* cy, const double* cz, double* mult) {
-  __shared__ double lds[UP_LDS_DOUBLES];
+  extern __shared__ double lds[];
   int li = blockIdx.x;
   if (li >= nleaves) return;
   int c = leaves[li];
@@ -83,10 +87,10 @@ __global__ void __launch_bounds__(64) k_p2m(int p, const int* leaves, int nleave
   }
 }
 
-__global__ void __launch_bounds__(64) k_m2m(int p, int first, int count, const int* c0,
-                                            const int* nch, const double* cx, const double* cy,
-                                            const double* cz, double* mult) {
-  __shared__ double lds[UP_LDS_DOUBLES];
+__global__ void __launch_bounds__(M2M_T) k_m2m(int p, int first, int count, const int* c0,
+                                                const int* nch, const double* cx, const double* cy,
+                                                const double* cz, double* mult) {
+  extern __shared__ double lds[];
   int c = first + blockIdx.x;
   if (blockIdx.x >= count || nch[c] == 0) return;
   int nc = ncoef(p);
@@ -100,10 +104,10 @@ __global__ void __launch_bounds__(64) k_m2m(int p, int first, int count, const i
     regular_exact(p, cx[ch] - cx[c], cy[ch] - cy[c], cz[ch] - cz[c], yre + lane, yim + lane, 8);
   }
   const double* src = mult + (size_t)k0 * nc * 2;
-  for (int t = lane; t < kn * nc * 2; t += 64) mch[t] = src[t];
+  for (int t = lane; t < kn * nc * 2; t += M2M_T) mch[t] = src[t];
   __syncthreads();
   double* out = mult + (size_t)c * nc * 2;
-  for (int t = lane; t < nc; t += 64) {
+  for (int t = lane; t < nc; t += M2M_T) {
     // coefficient index t -> (n, m)
     int n = 0;
     while (cidx(n + 1, 0) <= t) n++;
@@ -188,13 +192,15 @@ void upward_pass(Ctx& c) {
   exclusive_scan(c, flag, off, nc, tot);
   hipLaunchKernelGGL(k_compact_leaves, dim3((nc + 255) / 256), dim3(256), 0, s, flag, off, nc, leaves);
   c.nleaf = read_total(c, tot);
-  hipLaunchKernelGGL(k_p2m, dim3((unsigned)c.nleaf), dim3(64), 0, s, p, leaves, (int)c.nleaf,
+  size_t p2m_lds = sizeof(double) * 2 * ncoef(p) * p2m_batch(p);
+  hipLaunchKernelGGL(k_p2m, dim3((unsigned)c.nleaf), dim3(64), p2m_lds, s, p, leaves, (int)c.nleaf,
                      c.c_begin.p, c.c_end.p, c.sx.p, c.sy.p, c.sz.p, c.sm.p, c.c_cx.p, c.c_cy.p,
                      c.c_cz.p, c.mult.p);
   HIPCHK(hipGetLastError());
   for (int level = c.depth - 1; level >= 0; level--) {
     int first = c.lvl_first[level], count = c.lvl_count[level];
-    hipLaunchKernelGGL(k_m2m, dim3(count), dim3(64), 0, s, p, first, count, c.c_child0.p,
+    size_t m2m_lds = sizeof(double) * 32 * ncoef(p);  // harmonics of 8 children + their moments
+    hipLaunchKernelGGL(k_m2m, dim3(count), dim3(M2M_T), m2m_lds, s, p, first, count, c.c_child0.p,
                        c.c_nchild.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.mult.p);
     HIPCHK(hipGetLastError());
   }

@@ -92,20 +92,35 @@ __device__ __forceinline__ int wave_incl_scan(int x) {
   return x;
 }
 
-// one wave-aggregated allocation of `cnt` slots from counter *ctr
-__device__ __forceinline__ long long wave_alloc(int cnt, int* ctr, int& excl) {
+constexpr int WALK_T = 512;  // threads per workgroup of the walk kernels
+
+// One workgroup-aggregated allocation of `cnt` slots from counter *ctr: a
+// wave scan, the wave totals combined through LDS, one atomic per workgroup.
+__device__ __forceinline__ long long block_alloc(int cnt, int* ctr, int& excl, int* sh) {
   int incl = wave_incl_scan(cnt);
-  excl = incl - cnt;
-  int total = __shfl(incl, 63, 64);
-  int base = 0;
-  if (lane_id() == 63 && total > 0) base = atomicAdd(ctr, total);
-  base = __shfl(base, 63, 64);
+  int wv = threadIdx.x >> 6;
+  if (lane_id() == 63) sh[wv] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int w = 0; w < WALK_T / 64; w++) {
+      int t = sh[w];
+      sh[w] = run;
+      run += t;
+    }
+    sh[WALK_T / 64] = run > 0 ? atomicAdd(ctr, run) : 0;
+  }
+  __syncthreads();
+  excl = incl - cnt + sh[wv];
+  long long base = sh[WALK_T / 64];
+  __syncthreads();
   return base;
 }
 
-// ctr[0]: next frontier, ctr[1]: accepted pairs, ctr[2]: near-field leaf pairs
+// ctr[0]: next frontier, ctr[32]: accepted pairs, ctr[64]: near-field leaf
+// pairs (separate cache lines)
 template <int KIND, int P>
-__global__ void __launch_bounds__(256) k_walk(CellView v, const int2* fin, int nin, int2* fout,
+__global__ void __launch_bounds__(WALK_T) k_walk(CellView v, const int2* fin, int nin, int2* fout,
                                               int fcap, int* ctr, uint64_t* acc_list, int acap,
                                               uint64_t* near_list, int ncap, int bits) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -134,10 +149,11 @@ __global__ void __launch_bounds__(256) k_walk(CellView v, const int2* fin, int n
       nkids = splitB ? kB : kA;
     }
   }
+  __shared__ int sh[WALK_T / 64 + 1];
   int ek, ea, en;
-  long long bk = wave_alloc(nkids, &ctr[0], ek);
-  long long ba = wave_alloc(nacc, &ctr[1], ea);
-  long long bn = wave_alloc(nnear, &ctr[2], en);
+  long long bk = block_alloc(nkids, &ctr[0], ek, sh);
+  long long ba = block_alloc(nacc, &ctr[32], ea, sh);
+  long long bn = block_alloc(nnear, &ctr[64], en, sh);
   if (!live) return;
   long long o = bk + ek;
   if (mode == 1) {
@@ -247,7 +263,8 @@ static void run_walk(Ctx& c, CellList& acc, CellList& nearl) {
   ensure(c.ws, acc.raw, std::max<size_t>(acc.raw.cap, (size_t)c.ncell * 8 + 64));
   ensure(c.ws, nearl.raw, std::max<size_t>(nearl.raw.cap, (size_t)c.ncell * 8 + 64));
   ensure(c.ws, c.counters, 64);
-  int* ctr = c.counters.p + 16;
+  ensure(c.ws, c.counters, 256);
+  int* ctr = c.counters.p + 128;
   int bits = list_bits(c.ncell);
   int* h = (int*)c.hbuf;
   hipLaunchKernelGGL(k_seed, dim3(1), dim3(1), 0, s, c.front[0].p);
@@ -255,14 +272,18 @@ static void run_walk(Ctx& c, CellList& acc, CellList& nearl) {
   int nacc = 0, nnear = 0;
   while (nin > 0) {
     for (;;) {
-      int init[4] = {0, nacc, nnear, 0};
+      int init[65] = {0};
+      init[32] = nacc;
+      init[64] = nnear;
       HIPCHK(hipMemcpyAsync(ctr, init, sizeof(init), hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL((k_walk<KIND, P>), dim3((unsigned)ceil_div(nin, 256)), dim3(256), 0, s, v,
+      hipLaunchKernelGGL((k_walk<KIND, P>), dim3((unsigned)ceil_div(nin, WALK_T)), dim3(WALK_T), 0, s, v,
                          c.front[cur].p, nin, c.front[1 - cur].p, (int)c.front[1 - cur].cap, ctr,
                          acc.raw.p, (int)acc.raw.cap, nearl.raw.p, (int)nearl.raw.cap, bits);
       HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(h, ctr, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(h, ctr, 65 * sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
+      h[1] = h[32];
+      h[2] = h[64];
       bool again = false;
       if ((size_t)h[0] > c.front[1 - cur].cap) {
         ensure(c.ws, c.front[1 - cur], (size_t)h[0] * 2);
@@ -326,13 +347,25 @@ __global__ void __launch_bounds__(256) k_near_f(int n, const int* __restrict__ l
   }
   double4 me = pm[i];
   double near = 0.0;
-  for (int k = off[B]; k < off[B + 1]; k++) {
+  // one flattened loop, same order: partners ascending, bodies in sorted order
+  int k = off[B], ke = off[B + 1];
+  int j = 0, je = 0;
+  if (k < ke) {
     int A = src[k];
-    for (int j = cb[A]; j < ce[A]; j++) {
-      double4 q = pm[j];
-      double dx = q.x - me.x, dy = q.y - me.y, dz = q.z - me.z;
-      double d2 = (dx * dx + dy * dy) + dz * dz;
-      if (j != i && d2 > 0.0) near = near + q.w / d2;
+    j = cb[A];
+    je = ce[A];
+  }
+  while (k < ke) {
+    double4 q = pm[j];
+    double dx = q.x - me.x, dy = q.y - me.y, dz = q.z - me.z;
+    double d2 = (dx * dx + dy * dy) + dz * dz;
+    if (j != i && d2 > 0.0) near = near + q.w / d2;
+    if (++j == je) {
+      if (++k < ke) {
+        int A = src[k];
+        j = cb[A];
+        je = ce[A];
+      }
     }
   }
   f[i] = far + near;
