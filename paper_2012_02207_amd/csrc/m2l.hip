@@ -132,41 +132,53 @@ __device__ __forceinline__ void zrot(T* v, T c1, T s1) {
   });
 }
 
-// Two-stage reduction of D values per lane over the 64 lanes of the wave
-// through LDS; lane j (< D) receives the total of value j.
-// red: RED_ROWS * 65 doubles, RED_ROWS > D (the last row holds stage-2 partials).
-template <int D, int RED_ROWS>
-__device__ __forceinline__ void reduce_order(const double* v, double* red, double* acc_slot,
-                                             int lane, bool act) {
-  static_assert(D < RED_ROWS, "reduction buffer too small");
-  constexpr int S = (64 / D) < 8 ? (64 / D) : 8;   // segments per value
-  constexpr int G = (64 + S - 1) / S;              // lanes per segment
-  // red layout: value j of lane l at j * 65 + l (pad 65 breaks bank conflicts).
-  // Branch-free: every lane runs the same instructions on clamped indices and
-  // masks its result with a select.
-#pragma unroll
-  for (int j = 0; j < D; j++) red[j * 65 + lane] = act ? v[j] : 0.0;
-  __builtin_amdgcn_wave_barrier();
-  int j = lane / S, sg = lane % S;
-  int jr = j < D ? j : D - 1;
-  int l0 = sg * G;
-  double part = 0.0;
-#pragma unroll
-  for (int t = 0; t < G; t++) {
-    int l = l0 + t;
-    double x = red[jr * 65 + (l < 64 ? l : 63)];
-    part += (l < 64) ? x : 0.0;
-  }
-  part = j < D ? part : 0.0;
-  __builtin_amdgcn_wave_barrier();
-  red[(RED_ROWS - 1) * 65 + lane] = part;
-  __builtin_amdgcn_wave_barrier();
-  int lr = lane < D ? lane : D - 1;
-  double s = 0.0;
-#pragma unroll
-  for (int t = 0; t < S; t++) s += red[(RED_ROWS - 1) * 65 + lr * S + t];
-  *acc_slot += lane < D ? s : 0.0;
-  __builtin_amdgcn_wave_barrier();
+// Transpose-reduce of D values per lane over the 64 lanes: at each butterfly
+// step a lane keeps half of its remaining values and adds the partner's copy
+// of that half (about D + 6 shuffles instead of 6 D).  Afterwards the total of
+// value j sits in lane j * (64 / Dp) (Dp = D rounded up to a power of two),
+// which adds it to its accumulator acc_slot.
+constexpr int pow2_ceil(int d) {
+  int p = 1;
+  while (p < d) p <<= 1;
+  return p;
+}
+constexpr int ilog2(int d) {
+  int k = 0;
+  while ((1 << k) < d) k++;
+  return k;
+}
+
+template <int D>
+__device__ __forceinline__ void reduce_order(const double* v, double* acc_slot, int lane, bool act) {
+  constexpr int DP = pow2_ceil(D);
+  double x[DP];
+  static_for<0, DP>([&](auto jc) {
+    constexpr int j = jc;
+    if constexpr (j < D)
+      x[j] = act ? v[j] : 0.0;
+    else
+      x[j] = 0.0;
+  });
+  static_for<0, ilog2(DP)>([&](auto tc) {
+    constexpr int t = tc;
+    constexpr int s = 32 >> t;          // partner distance
+    constexpr int half = DP >> (t + 1);
+    bool hi = (lane & s) != 0;
+    static_for<0, half>([&](auto ic) {
+      constexpr int i = ic;
+      double keep = hi ? x[i + half] : x[i];
+      double give = hi ? x[i] : x[i + half];
+      x[i] = keep + __shfl_xor(give, s, 64);
+    });
+  });
+  static_for<ilog2(DP), 6>([&](auto tc) {
+    constexpr int s = 32 >> tc;
+    x[0] += __shfl_xor(x[0], s, 64);
+  });
+  constexpr int K = 6 - ilog2(DP);      // owner lanes: low K bits zero
+  int j = lane >> K;
+  bool own = ((lane & ((1 << K) - 1)) == 0) && j < D;
+  *acc_slot += own ? (double)x[0] : 0.0;
 }
 
 constexpr int M2L_WAVES = 4;  // sinks per workgroup (one per wavefront)
@@ -180,10 +192,8 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l_fp64(int ncell, int firs
                                                              const double* __restrict__ mult,
                                                              double* __restrict__ loc) {
   constexpr int NC = ncoef(P);
-  constexpr int RED_ROWS = 2 * P + 2;
   constexpr int NSW = cswoff(P + 1);
   __shared__ double swt[NSW];
-  __shared__ double red_all[M2L_WAVES][RED_ROWS * 65];
   for (int t = threadIdx.x; t < NSW; t += 64 * M2L_WAVES) swt[t] = c_cswap[t];
   __syncthreads();
   // XCD-aware mapping: consecutive workgroups land on different XCDs, so give
@@ -210,7 +220,6 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l_fp64(int ncell, int firs
   }
   if (b == e) return;
   int lane = threadIdx.x & 63;
-  double* red = red_all[wv];
   // lane-major accumulator: lane j holds coefficient j of order n in acc[n]
   double acc[P + 1];
 #pragma unroll
@@ -353,22 +362,24 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l_fp64(int ncell, int firs
       zrot<n>(w, cb, -sb);
       swap_apply<n>(w, sw);
       zrot<n>(w, ca, -sa);
-      reduce_order<2 * n + 1, RED_ROWS>(w, red, &acc[n], lane, act);
+      reduce_order<2 * n + 1>(w, &acc[n], lane, act);
     });
   }
-  // back to the unscaled basis: L_n^m = (n-m)!(n+m)! Lhat_n^m; lane j owns
-  // real-basis entry j of every order
+  // back to the unscaled basis: L_n^m = (n-m)!(n+m)! Lhat_n^m; real-basis
+  // entry j of order n is owned by lane j * 64 / Dp (see reduce_order)
   double* out = loc + (size_t)B * NC * 2;
-  int m = (lane + 1) >> 1;
-  bool im = lane > 0 && !(lane & 1);
-#pragma unroll
-  for (int n = 0; n <= P; n++) {
-    if (lane < 2 * n + 1) {
+  static_for<0, P + 1>([&](auto nc) {
+    constexpr int n = nc;
+    constexpr int K = 6 - ilog2(pow2_ceil(2 * n + 1));
+    int j = lane >> K;
+    if ((lane & ((1 << K) - 1)) == 0 && j < 2 * n + 1) {
+      int m = (j + 1) >> 1;
+      bool im = j > 0 && !(j & 1);
       double f = c_fact_m2l[n - m] * c_fact_m2l[n + m];
       out[2 * cidx(n, m) + (im ? 1 : 0)] = acc[n] * f;
-      if (lane == 0) out[2 * cidx(n, 0) + 1] = 0.0;
+      if (j == 0) out[2 * cidx(n, 0) + 1] = 0.0;
     }
-  }
+  });
 }
 
 template <int P>

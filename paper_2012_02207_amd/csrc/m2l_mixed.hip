@@ -128,37 +128,53 @@ __device__ __forceinline__ void zrot(float* v, float c1, float s1) {
   });
 }
 
-// branch-free two-stage wave reduction through LDS (see the FP64 kernel);
-// lane j (< D) adds the FP32 total of value j to its FP64 accumulator
-template <int D, int RED_ROWS>
-__device__ __forceinline__ void reduce_order(const float* v, float* red, double* acc_slot, int lane,
-                                             bool act) {
-  static_assert(D < RED_ROWS, "reduction buffer too small");
-  constexpr int S = (64 / D) < 8 ? (64 / D) : 8;
-  constexpr int G = (64 + S - 1) / S;
-#pragma unroll
-  for (int j = 0; j < D; j++) red[j * 65 + lane] = act ? v[j] : 0.f;
-  __builtin_amdgcn_wave_barrier();
-  int j = lane / S, sg = lane % S;
-  int jr = j < D ? j : D - 1;
-  int l0 = sg * G;
-  float part = 0.f;
-#pragma unroll
-  for (int t = 0; t < G; t++) {
-    int l = l0 + t;
-    float x = red[jr * 65 + (l < 64 ? l : 63)];
-    part += (l < 64) ? x : 0.f;
-  }
-  part = j < D ? part : 0.f;
-  __builtin_amdgcn_wave_barrier();
-  red[(RED_ROWS - 1) * 65 + lane] = part;
-  __builtin_amdgcn_wave_barrier();
-  int lr = lane < D ? lane : D - 1;
-  double s = 0.0;
-#pragma unroll
-  for (int t = 0; t < S; t++) s += (double)red[(RED_ROWS - 1) * 65 + lr * S + t];
-  *acc_slot += lane < D ? s : 0.0;
-  __builtin_amdgcn_wave_barrier();
+// Transpose-reduce of D values per lane over the 64 lanes: at each butterfly
+// step a lane keeps half of its remaining values and adds the partner's copy
+// of that half (about D + 6 shuffles instead of 6 D).  Afterwards the total of
+// value j sits in lane j * (64 / Dp) (Dp = D rounded up to a power of two),
+// which adds it to its accumulator acc_slot.
+constexpr int pow2_ceil(int d) {
+  int p = 1;
+  while (p < d) p <<= 1;
+  return p;
+}
+constexpr int ilog2(int d) {
+  int k = 0;
+  while ((1 << k) < d) k++;
+  return k;
+}
+
+template <int D>
+__device__ __forceinline__ void reduce_order(const float* v, double* acc_slot, int lane, bool act) {
+  constexpr int DP = pow2_ceil(D);
+  float x[DP];
+  static_for<0, DP>([&](auto jc) {
+    constexpr int j = jc;
+    if constexpr (j < D)
+      x[j] = act ? v[j] : 0.f;
+    else
+      x[j] = 0.f;
+  });
+  static_for<0, ilog2(DP)>([&](auto tc) {
+    constexpr int t = tc;
+    constexpr int s = 32 >> t;          // partner distance
+    constexpr int half = DP >> (t + 1);
+    bool hi = (lane & s) != 0;
+    static_for<0, half>([&](auto ic) {
+      constexpr int i = ic;
+      float keep = hi ? x[i + half] : x[i];
+      float give = hi ? x[i] : x[i + half];
+      x[i] = keep + __shfl_xor(give, s, 64);
+    });
+  });
+  static_for<ilog2(DP), 6>([&](auto tc) {
+    constexpr int s = 32 >> tc;
+    x[0] += __shfl_xor(x[0], s, 64);
+  });
+  constexpr int K = 6 - ilog2(DP);      // owner lanes: low K bits zero
+  int j = lane >> K;
+  bool own = ((lane & ((1 << K) - 1)) == 0) && j < D;
+  *acc_slot += own ? (double)x[0] : 0.0;
 }
 
 }  // namespace mx
@@ -195,10 +211,8 @@ __global__ void __launch_bounds__(64 * MX_WAVES) k_m2l_fp32(int ncell, int first
   using namespace mx;
   constexpr int NC = ncoef(P);
   constexpr int NR = (P + 1) * (P + 1);
-  constexpr int RED_ROWS = 2 * P + 2;
   constexpr int NSW = cswoff(P + 1);
   __shared__ float swt[NSW];
-  __shared__ float red_all[MX_WAVES][RED_ROWS * 65];
   for (int t = threadIdx.x; t < NSW; t += 64 * MX_WAVES) swt[t] = c_cswap32[t];
   __syncthreads();
   int nlo = ncell - first_lo;  // sinks below the root levels
@@ -212,7 +226,6 @@ __global__ void __launch_bounds__(64 * MX_WAVES) k_m2l_fp32(int ncell, int first
   int b = split_point(src, off[B], e, first_lo);
   if (b == e) return;
   int lane = threadIdx.x & 63;
-  float* red = red_all[wv];
   double acc[P + 1];
 #pragma unroll
   for (int t = 0; t <= P; t++) acc[t] = 0.0;
@@ -335,23 +348,26 @@ __global__ void __launch_bounds__(64 * MX_WAVES) k_m2l_fp32(int ncell, int first
       zrot<n>(w, cb, -sb);
       swap_apply<n>(w, sw);
       zrot<n>(w, ca, -sa);
-      reduce_order<2 * n + 1, RED_ROWS>(w, red, &acc[n], lane, act);
+      reduce_order<2 * n + 1>(w, &acc[n], lane, act);
     });
   }
   // back to standard coefficients: L_n^0 += Lt n! / rho_B^n,
-  // L_n^m += Lt sqrt((n-m)!(n+m)!/2) / rho_B^n; lane j owns real-basis entry j
+  // L_n^m += Lt sqrt((n-m)!(n+m)!/2) / rho_B^n; real-basis entry j of order n
+  // is owned by lane j * 64 / Dp (see reduce_order)
   double* out = loc + (size_t)B * NC * 2;
-  int m = (lane + 1) >> 1;
-  bool im = lane > 0 && !(lane & 1);
   double isB = 1.0 / sB, pw = 1.0;
-#pragma unroll
-  for (int n = 0; n <= P; n++) {
-    if (lane < 2 * n + 1) {
+  static_for<0, P + 1>([&](auto nc) {
+    constexpr int n = nc;
+    constexpr int K = 6 - ilog2(pow2_ceil(2 * n + 1));
+    int j = lane >> K;
+    if ((lane & ((1 << K) - 1)) == 0 && j < 2 * n + 1) {
+      int m = (j + 1) >> 1;
+      bool im = j > 0 && !(j & 1);
       double f = (m == 0 ? 1.0 : sqrt(0.5)) * sqrt(fmm_fact_dev(n - m) * fmm_fact_dev(n + m)) * pw;
       out[2 * cidx(n, m) + (im ? 1 : 0)] += acc[n] * f;
     }
     pw *= isB;
-  }
+  });
 }
 
 // normalised, size-scaled FP32 moments of every cell (real basis, (P+1)^2 per cell)
