@@ -391,7 +391,7 @@ void fmm_destroy(fmm_ctx* ctx) {
     rel(c.idx[k]);
     rel(c.front[k]);
   }
-  rel(c.sx); rel(c.sy); rel(c.sz); rel(c.sm); rel(c.pm); rel(c.pkb); rel(c.scale); rel(c.nmult); rel(c.fpart); rel(c.leaf_of); rel(c.sort_hist);
+  rel(c.sx); rel(c.sy); rel(c.sz); rel(c.sm); rel(c.pm); rel(c.pkb); rel(c.scale); rel(c.nmult); rel(c.fpart); rel(c.leaf_of); rel(c.leaves); rel(c.sort_hist);
   rel(c.bbox_part); rel(c.rootbox); rel(c.c_level); rel(c.c_begin); rel(c.c_end); rel(c.c_parent);
   rel(c.c_child0); rel(c.c_nchild); rel(c.c_split); rel(c.c_mass); rel(c.c_sx); rel(c.c_sy);
   rel(c.c_sz); rel(c.c_cx); rel(c.c_cy); rel(c.c_cz); rel(c.c_rad); rel(c.c_rad2bits); rel(c.mult);

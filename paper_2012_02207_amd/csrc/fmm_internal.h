@@ -104,6 +104,7 @@ struct Ctx {
   dbuf<double4> pm;   // packed (x, y, z, m), sorted order
   dbuf<double> fpart;
   dbuf<int> leaf_of;  // leaf id of each sorted body
+  dbuf<int> leaves;   // ids of the leaf cells, ascending (built by the upward pass)
 
   // radix sort scratch
   dbuf<int> sort_hist;

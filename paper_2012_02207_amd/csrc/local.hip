@@ -149,139 +149,142 @@ __device__ __forceinline__ void l2p_eval(int p, const double* __restrict__ L, do
   ph = -s00;
 }
 
-// One thread per sink body (bodies in sorted order, so a wavefront covers one
-// or a few neighbouring leaves and its loads are mostly broadcasts).  Far field
-// by L2P: the leaf's local expansion shifted to the body (Phi = -Re L'_0^0,
-// a = (-Re L'_1^1, -Im L'_1^1, Re L'_1^0)); near field by direct summation over
-// the leaf's P2P sources (ascending), FP64.
-__global__ void __launch_bounds__(256) k_leaf_eval(int p, int n, const int* __restrict__ leaf_of,
-                                                   const int* __restrict__ cb, const int* __restrict__ ce,
-                                                   const int* __restrict__ off, const int* __restrict__ srcl,
-                                                   const double* __restrict__ cx, const double* __restrict__ cy,
-                                                   const double* __restrict__ cz, const double* __restrict__ loc,
-                                                   const double4* __restrict__ pm,
-                                                   const int* __restrict__ perm, double eps2, double* acc,
-                                                   double* pot) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int B = leaf_of[i];
-  int nc = ncoef(p);
-  const double* L = loc + (size_t)B * nc * 2;
-  double4 me = pm[i];
-  double xi = me.x, yi = me.y, zi = me.z;
-  double ax, ay, az, ph;
-  l2p_eval(p, L, xi - cx[B], yi - cy[B], zi - cz[B], ax, ay, az, ph);
-  // ---- P2P
-  // one flattened loop over the source bodies of all P2P partners (lanes of
-  // neighbouring leaves only diverge in the short advance step)
-  double nx = 0.0, ny = 0.0, nz = 0.0, np = 0.0;
-  int q = off[B], qe = off[B + 1];
-  int j = 0, je = 0;
-  if (q < qe) {
-    int A = srcl[q];
-    j = cb[A];
-    je = ce[A];
-  }
-  while (q < qe) {
-    double4 s = pm[j];
-    double dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
-    double d2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
-    double rinv = rsqrt_d(d2);
-    rinv = (j != i && d2 > 0.0) ? rinv : 0.0;
-    double mr = s.w * rinv;
-    double mr3 = mr * rinv * rinv;
-    nx = fma(mr3, dx, nx);
-    ny = fma(mr3, dy, ny);
-    nz = fma(mr3, dz, nz);
-    np -= mr;
-    if (++j == je) {
-      if (++q < qe) {
-        int A = srcl[q];
-        j = cb[A];
-        je = ce[A];
-      }
-    }
-  }
-  int o = perm[i];
-  acc[3 * (int64_t)o] = ax + nx;
-  acc[3 * (int64_t)o + 1] = ay + ny;
-  acc[3 * (int64_t)o + 2] = az + nz;
-  pot[o] = ph + np;
-}
+// P2P + L2P, one wavefront per sink leaf.  The n_B sink bodies are replicated
+// over G = 64 / n_B lane groups, and group g takes every G-th body of each
+// source leaf, so nearly every lane works even though leaves hold ~20 bodies.
+// Each source leaf is staged once in LDS with one coalesced load and read by
+// the groups as broadcasts.  The G partial sums are combined in group order
+// (deterministic); group 0 adds the far field by L2P (the leaf's local
+// expansion shifted to the body: Phi = -Re L'_0^0,
+// a = (-Re L'_1^1, -Im L'_1^1, Re L'_1^0)) and writes the caller-order result.
+// MIXED: pair arithmetic in FP32 on the separation formed in FP64 and rounded
+// once; FP32 partial sums are carried into FP64 after every source leaf
+// (blocked compensation: the FP32 error grows with the leaf, not the list).
+constexpr int LG_WAVES = 4;
 
-// Mixed precision: L2P in FP64; P2P pair arithmetic in FP32 on the separation
-// formed in FP64 and rounded once (relative coordinates), accumulated in FP32
-// over one source leaf at a time and carried into FP64 (blocked compensation:
-// the FP32 rounding error grows with the leaf size, not with the list length).
-__global__ void __launch_bounds__(256) k_leaf_eval_mixed(int p, int n, const int* __restrict__ leaf_of,
-                                                         const int* __restrict__ cb, const int* __restrict__ ce,
-                                                         const int* __restrict__ off, const int* __restrict__ srcl,
-                                                         const double* __restrict__ cx, const double* __restrict__ cy,
-                                                         const double* __restrict__ cz, const double* __restrict__ loc,
-                                                         const double4* __restrict__ pm,
-                                                         const int* __restrict__ perm, float eps2, double* acc,
-                                                         double* pot) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int B = leaf_of[i];
-  const double* L = loc + (size_t)B * ncoef(p) * 2;
-  double4 me = pm[i];
-  double xi = me.x, yi = me.y, zi = me.z;
-  double ax, ay, az, ph;
-  l2p_eval(p, L, xi - cx[B], yi - cy[B], zi - cz[B], ax, ay, az, ph);
-  double nx = 0.0, ny = 0.0, nz = 0.0, np = 0.0;
-  float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
-  int q = off[B], qe = off[B + 1];
-  int j = 0, je = 0;
-  if (q < qe) {
-    int A = srcl[q];
-    j = cb[A];
-    je = ce[A];
-  }
-  while (q < qe) {
-    double4 s = pm[j];
-    float dx = (float)(s.x - xi), dy = (float)(s.y - yi), dz = (float)(s.z - zi);
-    float d2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
-    float rinv = __builtin_amdgcn_rsqf(d2);
-    rinv = (j != i && d2 > 0.f) ? rinv : 0.f;
-    float mr = (float)s.w * rinv;
-    float mr3 = mr * rinv * rinv;
-    fx = fmaf(mr3, dx, fx);
-    fy = fmaf(mr3, dy, fy);
-    fz = fmaf(mr3, dz, fz);
-    fp -= mr;
-    if (++j == je) {  // end of a source leaf: carry the FP32 block into FP64
-      nx += (double)fx;
-      ny += (double)fy;
-      nz += (double)fz;
-      np += (double)fp;
-      fx = fy = fz = fp = 0.f;
-      if (++q < qe) {
-        int A = srcl[q];
-        j = cb[A];
-        je = ce[A];
+template <bool MIXED>
+__global__ void __launch_bounds__(64 * LG_WAVES) k_leaf_group(int p, const int* __restrict__ leaves,
+                                                              int nleaves, const int* __restrict__ cb,
+                                                              const int* __restrict__ ce,
+                                                              const int* __restrict__ off,
+                                                              const int* __restrict__ srcl,
+                                                              const double* __restrict__ cx,
+                                                              const double* __restrict__ cy,
+                                                              const double* __restrict__ cz,
+                                                              const double* __restrict__ loc,
+                                                              const double4* __restrict__ pm,
+                                                              const int* __restrict__ perm, double eps2,
+                                                              double* acc, double* pot) {
+  __shared__ double4 sbuf[LG_WAVES][64];
+  __shared__ double rbuf[LG_WAVES][4][64];
+  int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int nblk = (nleaves + LG_WAVES - 1) / LG_WAVES;
+  int per = (nblk + 7) >> 3;
+  int blk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  int li = blk * LG_WAVES + wv;
+  if (blk >= nblk || li >= nleaves) return;
+  int B = leaves[li];
+  int b = cb[B], e = ce[B];
+  int qb = off[B], qe = off[B + 1];
+  float eps2f = (float)eps2;
+  for (int i0 = b; i0 < e; i0 += 64) {
+    int nB = min(64, e - i0);
+    int G = 64 / nB;
+    int g = lane / nB, s = lane - g * nB;
+    bool act = g < G;
+    int i = i0 + s;
+    double4 me = pm[i];
+    double nx = 0.0, ny = 0.0, nz = 0.0, np = 0.0;
+    for (int q = qb; q < qe; q++) {
+      int A = srcl[q];
+      int ja = cb[A], je = ce[A];
+      float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
+      for (int j0 = ja; j0 < je; j0 += 64) {
+        int na = min(64, je - j0);
+        __builtin_amdgcn_wave_barrier();
+        if (lane < na) sbuf[wv][lane] = pm[j0 + lane];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): staged bodies visible to the wave
+        int tmax = act ? na : 0;
+        for (int t = g; t < tmax; t += G) {
+          double4 sb = sbuf[wv][t];
+          int j = j0 + t;
+          if constexpr (MIXED) {
+            float dx = (float)(sb.x - me.x), dy = (float)(sb.y - me.y), dz = (float)(sb.z - me.z);
+            float d2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f)));
+            float rinv = __builtin_amdgcn_rsqf(d2);
+            rinv = (j != i && d2 > 0.f) ? rinv : 0.f;
+            float mr = (float)sb.w * rinv;
+            float mr3 = mr * rinv * rinv;
+            fx = fmaf(mr3, dx, fx);
+            fy = fmaf(mr3, dy, fy);
+            fz = fmaf(mr3, dz, fz);
+            fp -= mr;
+          } else {
+            double dx = sb.x - me.x, dy = sb.y - me.y, dz = sb.z - me.z;
+            double d2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+            double rinv = rsqrt_d(d2);
+            rinv = (j != i && d2 > 0.0) ? rinv : 0.0;
+            double mr = sb.w * rinv;
+            double mr3 = mr * rinv * rinv;
+            nx = fma(mr3, dx, nx);
+            ny = fma(mr3, dy, ny);
+            nz = fma(mr3, dz, nz);
+            np -= mr;
+          }
+        }
+      }
+      if constexpr (MIXED) {  // end of a source leaf: carry the FP32 block into FP64
+        nx += (double)fx;
+        ny += (double)fy;
+        nz += (double)fz;
+        np += (double)fp;
       }
     }
+    // combine the groups in order
+    __builtin_amdgcn_wave_barrier();
+    rbuf[wv][0][lane] = nx;
+    rbuf[wv][1][lane] = ny;
+    rbuf[wv][2][lane] = nz;
+    rbuf[wv][3][lane] = np;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    if (g == 0) {
+      double tx = 0.0, ty = 0.0, tz = 0.0, tp = 0.0;
+      for (int gg = 0; gg < G; gg++) {
+        int l = gg * nB + s;
+        tx += rbuf[wv][0][l];
+        ty += rbuf[wv][1][l];
+        tz += rbuf[wv][2][l];
+        tp += rbuf[wv][3][l];
+      }
+      const double* L = loc + (size_t)B * ncoef(p) * 2;
+      double ax, ay, az, ph;
+      l2p_eval(p, L, me.x - cx[B], me.y - cy[B], me.z - cz[B], ax, ay, az, ph);
+      int o = perm[i];
+      acc[3 * (int64_t)o] = ax + tx;
+      acc[3 * (int64_t)o + 1] = ay + ty;
+      acc[3 * (int64_t)o + 2] = az + tz;
+      pot[o] = ph + tp;
+    }
+    __builtin_amdgcn_wave_barrier();
   }
-  int o = perm[i];
-  acc[3 * (int64_t)o] = ax + nx;
-  acc[3 * (int64_t)o + 1] = ay + ny;
-  acc[3 * (int64_t)o + 2] = az + nz;
-  pot[o] = ph + np;
 }
 
 void launch_leaf_eval(Ctx& c, double* acc, double* pot) {
-  if (c.prm.precision == FMM_MIXED) {
-    hipLaunchKernelGGL(k_leaf_eval_mixed, dim3((unsigned)ceil_div(c.n, 256)), dim3(256), 0, c.stream, c.p,
-                       (int)c.n, c.leaf_of.p, c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.c_cx.p,
-                       c.c_cy.p, c.c_cz.p, c.loc.p, c.pm.p, c.idx[0].p, (float)(c.eps_soft * c.eps_soft),
-                       acc, pot);
-    HIPCHK(hipGetLastError());
-    return;
-  }
-  hipLaunchKernelGGL(k_leaf_eval, dim3((unsigned)ceil_div(c.n, 256)), dim3(256), 0, c.stream, c.p,
-                     (int)c.n, c.leaf_of.p, c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.c_cx.p,
-                     c.c_cy.p, c.c_cz.p, c.loc.p, c.pm.p, c.idx[0].p, c.eps_soft * c.eps_soft, acc, pot);
+  if (c.nleaf <= 0) return;
+  const int* leaves = c.leaves.p;
+  int nblk = (int)((c.nleaf + LG_WAVES - 1) / LG_WAVES);
+  unsigned grid = 8u * (unsigned)((nblk + 7) / 8);
+  double e2 = c.eps_soft * c.eps_soft;
+  if (c.prm.precision == FMM_MIXED)
+    hipLaunchKernelGGL(k_leaf_group<true>, dim3(grid), dim3(64 * LG_WAVES), 0, c.stream, c.p, leaves,
+                       (int)c.nleaf, c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.c_cx.p, c.c_cy.p,
+                       c.c_cz.p, c.loc.p, c.pm.p, c.idx[0].p, e2, acc, pot);
+  else
+    hipLaunchKernelGGL(k_leaf_group<false>, dim3(grid), dim3(64 * LG_WAVES), 0, c.stream, c.p, leaves,
+                       (int)c.nleaf, c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.c_cx.p, c.c_cy.p,
+                       c.c_cz.p, c.loc.p, c.pm.p, c.idx[0].p, e2, acc, pot);
   HIPCHK(hipGetLastError());
 }
 

@@ -183,10 +183,11 @@ void upward_pass(Ctx& c) {
   ensure(c.ws, c.mult, (size_t)nc * ncoef(p) * 2);
   ensure(c.ws, c.pk, (size_t)nc * (p + 1));
   // leaf list
-  ensure(c.ws, c.c_split, (size_t)3 * nc + 96);
+  ensure(c.ws, c.c_split, (size_t)2 * nc + 64);
+  ensure(c.ws, c.leaves, (size_t)nc);
   int* flag = c.c_split.p;
   int* off = flag + nc + 32;
-  int* leaves = off + nc + 32;
+  int* leaves = c.leaves.p;
   long long* tot = (long long*)c.counters.p;
   hipLaunchKernelGGL(k_list_leaves, dim3((nc + 255) / 256), dim3(256), 0, s, c.c_nchild.p, nc, flag);
   exclusive_scan(c, flag, off, nc, tot);
