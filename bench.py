@@ -102,11 +102,22 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frac", type=float, default=1.0 / 64)
     ap.add_argument("--err-sinks", type=int, default=4096)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-MiB device buffer 5 times (calibrates byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.ones(args.copy_probe << 18, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_per_copy": a.numel() * 4, "copies": 5}))
+        return
     args.precisions = [x for x in args.precisions.split(",") if x]
     if args.gpus != 1:
-        print(json.dumps({"error": "this build evaluates one force pass on one GPU; "
-                                   "multi-GPU runs are not part of it (--gpus 1)"}))
+        print(json.dumps({"error": "the force pass runs on one GPU; runs over several GPUs "
+                                   "are not supported (use --gpus 1)"}))
         sys.exit(2)
 
     import torch
@@ -153,15 +164,19 @@ def main():
     ms_step = R["ms"]
     rel = R["rel"]
 
-    # dominant kernel roofline (algorithmic FLOPs / average event time)
-    m2l_ms = np.mean([s["ms_m2l"] for s in R["stages"]])
+    # dominant kernel roofline: algorithmic FLOPs of one launch / its average
+    # duration between HIP events recorded around it on the library's stream
+    m2l_ms = np.mean([s["ms_m2l_kernel"] for s in R["stages"]])
+    m2l_stage_ms = np.mean([s["ms_m2l"] for s in R["stages"]])
     p2p_ms = np.mean([s["ms_p2p"] for s in R["stages"]])
-    f_m2l = m2l_flops(p) * st["n_m2l"]
+    n_m2l_main = st["n_m2l"] if main_pr == "fp64" else st["n_m2l_fp32"]
+    f_m2l = m2l_flops(p) * n_m2l_main
     f_leaf = P2P_FLOPS * st["n_p2p_pairs"] + l2p_flops(p) * n
     peak = PEAK_FP64 if main_pr == "fp64" else PEAK_FP32
-    kname = "k_m2l_fp64" if main_pr == "fp64" else "k_m2l_fp32 (+ k_m2l_fp64 for root-level pairs)"
+    kname = "k_m2l_fp64" if main_pr == "fp64" else "k_m2l_fp32"
     if p2p_ms >= m2l_ms:
-        dom = {"kernel": "k_leaf_eval (L2P + P2P)" if main_pr == "fp64" else "k_leaf_eval_mixed",
+        dom = {"kernel": "k_leaf_group<false> (L2P + P2P)" if main_pr == "fp64"
+                         else "k_leaf_group<true> (L2P + mixed P2P)",
                "flop": f_leaf, "ms": p2p_ms}
     else:
         dom = {"kernel": kname, "flop": f_m2l, "ms": m2l_ms}
@@ -169,8 +184,11 @@ def main():
     # the dominant stages are vector-ALU bound (no dense contraction on this path)
     roof = {"bound": "alu", "kernel": dom["kernel"],
             "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None}
-    other = {"m2l": {"ms": m2l_ms, "tflops": f_m2l / (m2l_ms * 1e-3) / 1e12},
+            "frac": achieved / peak, "traffic": None,
+            "flop_per_launch": dom["flop"], "ms_per_launch": dom["ms"]}
+    other = {"m2l_main": {"kernel": kname, "pairs": int(n_m2l_main), "ms": m2l_ms,
+                          "tflops": f_m2l / (m2l_ms * 1e-3) / 1e12},
+             "m2l_stage_ms": m2l_stage_ms,
              "leaf_eval": {"ms": p2p_ms, "tflops": f_leaf / (p2p_ms * 1e-3) / 1e12}}
     forms = {}
     for pr, r in res.items():

@@ -68,7 +68,8 @@ typedef struct {
   int root_levels;  /* mixed precision: M2L touching a cell above this level stays FP64 */
 } fmm_params;
 
-/* counts of the last call (filled by fmm_stats) */
+/* counts and times of the last call (filled by fmm_stats); times in ms between
+ * HIP events recorded on the call's stream */
 typedef struct {
   int64_t n;              /* bodies                                       */
   int64_t ncell;          /* cells (root = 0, breadth-first ids)          */
@@ -82,6 +83,8 @@ typedef struct {
   int64_t n_m2l_fp32;     /* M2L pairs evaluated in FP32 (mixed mode)     */
   double ms_tree, ms_upward, ms_estimate, ms_walk, ms_m2l, ms_local, ms_p2p, ms_total;
   size_t workspace_bytes; /* device memory held by the context            */
+  int64_t nsys;           /* independent systems of the call (1 for fmm_forces) */
+  double ms_m2l_kernel;   /* the main M2L kernel alone (FP32 kernel in mixed mode) */
 } fmm_stats_t;
 
 /* export selectors for fmm_export (host buffer, element counts from fmm_stats) */
@@ -108,7 +111,8 @@ typedef enum {
   FMM_X_M2L = 18,       /* int32[2*n_m2l]                                           */
   FMM_X_P2P = 19,       /* int32[2*n_p2p_cells]                                     */
   FMM_X_LOCAL = 20,     /* double[ncell*ncoef*2] local expansions after L2L         */
-  FMM_X_ROOTBOX = 21    /* double[5] lo_x, lo_y, lo_z, edge L, key scale 2^21/L    */
+  FMM_X_ROOTBOX = 21    /* double[5*nsys] per system: lo_x, lo_y, lo_z, edge L,
+                           key scale 2^21/L                                        */
 } fmm_export_what;
 
 typedef struct fmm_ctx fmm_ctx;
@@ -136,6 +140,26 @@ fmm_status fmm_build(fmm_ctx* ctx, int64_t n, const double* pos, const double* m
 fmm_status fmm_forces(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass,
                       double eps_soft, int p, double err_tol, double* acc, double* pot,
                       void* stream);
+
+/* Largest number of systems one fmm_forces_batch call accepts. */
+#define FMM_MAX_SYSTEMS 65536
+
+/* Batched evaluation of nsys independent systems (an ensemble of clusters) in
+ * one pass: system s is the bodies [offsets[s], offsets[s+1]) of pos/mass and
+ * feels only its own bodies.  The result for each system is the one
+ * fmm_forces gives for it alone (same per-system root box, Morton keys, tree,
+ * estimate and interaction lists, section 2.1 and 2.3); the systems share
+ * every launch: the sort orders bodies by (system, key), the tree is a forest
+ * with one root per system (cells 0..nsys-1), and the walks start from every
+ * (root, root) pair.  Cell ids are breadth first over the forest, so the cells
+ * of one system appear in the order of that system's own tree.
+ * offsets: HOST array of nsys + 1 values, offsets[0] = 0, strictly increasing
+ * (every system holds at least one body), offsets[nsys] = total bodies; nsys
+ * in 1..FMM_MAX_SYSTEMS, otherwise FMM_EINVAL.  Other arguments as fmm_forces;
+ * acc and pot are in the caller's order over all systems. */
+fmm_status fmm_forces_batch(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets, const double* pos,
+                            const double* mass, double eps_soft, int p, double err_tol,
+                            double* acc, double* pot, void* stream);
 
 /* Counts and per-stage times of the last call (synchronises its stream). */
 fmm_status fmm_stats(fmm_ctx* ctx, fmm_stats_t* out /* host */);

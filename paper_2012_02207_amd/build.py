@@ -22,8 +22,18 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=o
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-I" + os.path.join(HERE, "..")]
 
 
-def _compile(src):
+def _headers():
+    inc = os.path.join(HERE, "..", "include")
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    return hs + [os.path.join(inc, f) for f in os.listdir(inc) if f.endswith(".h")]
+
+
+def _compile(src, incremental=False):
     obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+    if incremental and os.path.exists(obj):
+        t = os.path.getmtime(obj)
+        if all(os.path.getmtime(f) < t for f in [os.path.join(CSRC, src)] + _headers()):
+            return obj, ""
     cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -31,10 +41,12 @@ def _compile(src):
     return obj, r.stderr
 
 
-def build(verbose=False, jobs=8):
+def build(verbose=False, jobs=8, incremental=False):
+    """Compiles every source (incremental=True skips objects newer than their
+    source and every header) and links the shared library."""
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        results = list(ex.map(_compile, SOURCES))
+        results = list(ex.map(lambda s: _compile(s, incremental), SOURCES))
     if verbose:
         for _, err in results:
             if err.strip():
@@ -47,5 +59,5 @@ def build(verbose=False, jobs=8):
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     print(LIB)

@@ -180,6 +180,8 @@ fmm_status fmm_build(fmm_ctx* ctx, int64_t n, const double* pos, const double* m
     c.err.clear();
     c.p = c.prm.p;
     c.err_tol = c.prm.err_tol;
+    c.nsys = 1;
+    c.h_sys_off.assign({0, n});
     if (c.prm.check_inputs && !check_inputs_dev(c, pos, mass, n)) return FMM_EDATA;
     c.have_events = true;
     HIPCHK(hipEventRecord(c.ev[0], c.stream));
@@ -188,8 +190,9 @@ fmm_status fmm_build(fmm_ctx* ctx, int64_t n, const double* pos, const double* m
   });
 }
 
-fmm_status fmm_forces(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass, double eps_soft,
-                      int p, double err_tol, double* acc, double* pot, void* stream) {
+static fmm_status forces_impl(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets, int64_t n,
+                              const double* pos, const double* mass, double eps_soft, int p,
+                              double err_tol, double* acc, double* pot, void* stream) {
   fmm_status st = common_checks(ctx, n, pos, mass);
   if (st != FMM_OK) return st;
   if (!acc || !pot) return FMM_EINVAL;
@@ -205,10 +208,16 @@ fmm_status fmm_forces(fmm_ctx* ctx, int64_t n, const double* pos, const double* 
     c.p = p;
     c.err_tol = err_tol;
     c.eps_soft = eps_soft;
+    c.nsys = (int)nsys;
+    c.h_sys_off.assign(offsets, offsets + nsys + 1);
     if (c.prm.check_inputs && !check_inputs_dev(c, pos, mass, n)) return FMM_EDATA;
     if (c.prm.precision == FMM_DIRECT) {
       c.have_events = false;
-      direct_sum(n, pos, mass, eps_soft * eps_soft, n, nullptr, acc, pot, c.stream);
+      for (int64_t s = 0; s < nsys; s++) {
+        int64_t b = offsets[s], m = offsets[s + 1] - b;
+        direct_sum(m, pos + 3 * b, mass + b, eps_soft * eps_soft, m, nullptr, acc + 3 * b, pot + b,
+                   c.stream);
+      }
       return FMM_OK;
     }
     c.have_events = true;
@@ -226,6 +235,23 @@ fmm_status fmm_forces(fmm_ctx* ctx, int64_t n, const double* pos, const double* 
   });
 }
 
+fmm_status fmm_forces(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass, double eps_soft,
+                      int p, double err_tol, double* acc, double* pot, void* stream) {
+  int64_t off[2] = {0, n};
+  return forces_impl(ctx, 1, off, n, pos, mass, eps_soft, p, err_tol, acc, pot, stream);
+}
+
+fmm_status fmm_forces_batch(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets, const double* pos,
+                            const double* mass, double eps_soft, int p, double err_tol, double* acc,
+                            double* pot, void* stream) {
+  if (!offsets || nsys < 1 || nsys > FMM_MAX_SYSTEMS) return FMM_EINVAL;
+  if (offsets[0] != 0) return FMM_EINVAL;
+  for (int64_t s = 0; s < nsys; s++)
+    if (offsets[s + 1] <= offsets[s]) return FMM_EINVAL;  // every system holds a body
+  return forces_impl(ctx, nsys, offsets, offsets[nsys], pos, mass, eps_soft, p, err_tol, acc, pot,
+                     stream);
+}
+
 fmm_status fmm_stats(fmm_ctx* ctx, fmm_stats_t* out) {
   if (!ctx || !out) return FMM_EINVAL;
   Ctx& c = ctx->c;
@@ -238,6 +264,7 @@ fmm_status fmm_stats(fmm_ctx* ctx, fmm_stats_t* out) {
     out->nleaf = c.nleaf;
     out->depth = c.depth;
     out->workspace_bytes = c.ws.bytes;
+    out->nsys = c.nsys;
     if (c.walked) {
       out->n_m2l = c.m2l.count;
       out->n_p2p_cells = c.p2p.count;
@@ -273,6 +300,7 @@ fmm_status fmm_stats(fmm_ctx* ctx, fmm_stats_t* out) {
         out->ms_local = el(5, 6);
         out->ms_p2p = el(6, 7);
         out->ms_total = el(0, 8);
+        out->ms_m2l_kernel = el(9, 10);
       } else {
         out->ms_total = el(0, 2);
       }
@@ -312,11 +340,20 @@ fmm_status fmm_export(fmm_ctx* ctx, int what, void* host_buf, size_t bytes) {
     case FMM_X_M2L: if (!c.walked) return FMM_ENOTBUILT; lst = &c.m2l; break;
     case FMM_X_P2P: if (!c.walked) return FMM_ENOTBUILT; lst = &c.p2p; break;
     case FMM_X_LOCAL: if (!c.evaluated) return FMM_ENOTBUILT; src = c.loc.p; need = nc * ncf * 8; break;
-    case FMM_X_ROOTBOX: src = c.rootbox.p; need = 5 * 8; break;
+    case FMM_X_ROOTBOX: break;
     default: return FMM_EINVAL;
   }
   return guarded(ctx, [&]() {
     HIPCHK(hipStreamSynchronize(c.stream));
+    if (what == FMM_X_ROOTBOX) {  // 5 values per system from the stride-8 device layout
+      if (bytes < (size_t)c.nsys * 40) return FMM_EINVAL;
+      std::vector<double> t((size_t)c.nsys * 8);
+      HIPCHK(hipMemcpy(t.data(), c.rootbox.p, t.size() * 8, hipMemcpyDeviceToHost));
+      double* o = (double*)host_buf;
+      for (int s = 0; s < c.nsys; s++)
+        for (int k = 0; k < 5; k++) o[5 * s + k] = t[8 * s + k];
+      return FMM_OK;
+    }
     if (what == FMM_X_CELL_COM) {
       if (bytes < (size_t)nc * 24) return FMM_EINVAL;
       std::vector<double> t((size_t)nc);
@@ -391,7 +428,7 @@ void fmm_destroy(fmm_ctx* ctx) {
     rel(c.idx[k]);
     rel(c.front[k]);
   }
-  rel(c.sx); rel(c.sy); rel(c.sz); rel(c.sm); rel(c.pm); rel(c.pkb); rel(c.scale); rel(c.nmult); rel(c.fpart); rel(c.leaf_of); rel(c.leaves); rel(c.sort_hist);
+  rel(c.sx); rel(c.sy); rel(c.sz); rel(c.sm); rel(c.pm); rel(c.pkb); rel(c.scale); rel(c.nmult); rel(c.fpart); rel(c.leaf_of); rel(c.leaves); rel(c.sys_off); rel(c.skey[0]); rel(c.skey[1]); rel(c.spos[0]); rel(c.spos[1]); rel(c.sort_hist);
   rel(c.bbox_part); rel(c.rootbox); rel(c.c_level); rel(c.c_begin); rel(c.c_end); rel(c.c_parent);
   rel(c.c_child0); rel(c.c_nchild); rel(c.c_split); rel(c.c_mass); rel(c.c_sx); rel(c.c_sy);
   rel(c.c_sz); rel(c.c_cx); rel(c.c_cy); rel(c.c_cz); rel(c.c_rad); rel(c.c_rad2bits); rel(c.mult);

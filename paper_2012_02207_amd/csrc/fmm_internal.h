@@ -109,9 +109,18 @@ struct Ctx {
   // radix sort scratch
   dbuf<int> sort_hist;
 
+  // independent systems evaluated together (a forest: one root per system);
+  // bodies of system s are [sys_off[s], sys_off[s+1]) in caller and sorted order
+  int nsys = 1;
+  std::vector<int64_t> h_sys_off;
+  dbuf<int> sys_off;
+  std::vector<int> sys_off_uploaded;  // host image of sys_off's current contents
+  dbuf<uint64_t> skey[2];  // second sort pass (by system), ping-pong
+  dbuf<int> spos[2];
+
   // bbox scratch: per-block min/max, then lo[3], L, s
   dbuf<double> bbox_part;
-  dbuf<double> rootbox;  // 5 doubles
+  dbuf<double> rootbox;  // per system: lo[3], L, s (stride 8 doubles)
 
   // cells (breadth-first ids)
   int64_t ncell = 0, nleaf = 0;
@@ -145,7 +154,7 @@ struct Ctx {
   long long* hbuf = nullptr;
 
   // timing
-  hipEvent_t ev[10] = {};
+  hipEvent_t ev[12] = {};  // stage boundaries 0..8; 9, 10 around the main M2L kernel
   bool have_events = false;
 };
 

@@ -195,51 +195,74 @@ __global__ void __launch_bounds__(64 * LG_WAVES) k_leaf_group(int p, const int* 
     int i = i0 + s;
     double4 me = pm[i];
     double nx = 0.0, ny = 0.0, nz = 0.0, np = 0.0;
-    for (int q = qb; q < qe; q++) {
+    float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
+    // source chunks (<= 64 bodies of one source leaf) in list order; the
+    // next chunk is fetched into registers while the current one is summed
+    int q = qb, j0 = 0, je = 0;
+    if (q < qe) {
       int A = srcl[q];
-      int ja = cb[A], je = ce[A];
-      float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
-      for (int j0 = ja; j0 < je; j0 += 64) {
-        int na = min(64, je - j0);
-        __builtin_amdgcn_wave_barrier();
-        if (lane < na) sbuf[wv][lane] = pm[j0 + lane];
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): staged bodies visible to the wave
-        int tmax = act ? na : 0;
-        for (int t = g; t < tmax; t += G) {
-          double4 sb = sbuf[wv][t];
-          int j = j0 + t;
-          if constexpr (MIXED) {
-            float dx = (float)(sb.x - me.x), dy = (float)(sb.y - me.y), dz = (float)(sb.z - me.z);
-            float d2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f)));
-            float rinv = __builtin_amdgcn_rsqf(d2);
-            rinv = (j != i && d2 > 0.f) ? rinv : 0.f;
-            float mr = (float)sb.w * rinv;
-            float mr3 = mr * rinv * rinv;
-            fx = fmaf(mr3, dx, fx);
-            fy = fmaf(mr3, dy, fy);
-            fz = fmaf(mr3, dz, fz);
-            fp -= mr;
-          } else {
-            double dx = sb.x - me.x, dy = sb.y - me.y, dz = sb.z - me.z;
-            double d2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
-            double rinv = rsqrt_d(d2);
-            rinv = (j != i && d2 > 0.0) ? rinv : 0.0;
-            double mr = sb.w * rinv;
-            double mr3 = mr * rinv * rinv;
-            nx = fma(mr3, dx, nx);
-            ny = fma(mr3, dy, ny);
-            nz = fma(mr3, dz, nz);
-            np -= mr;
-          }
+      j0 = cb[A];
+      je = ce[A];
+    }
+    double4 cur = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (q < qe && lane < je - j0) cur = pm[j0 + lane];
+    while (q < qe) {
+      int na = min(64, je - j0);
+      int nq = q, nj0 = j0 + 64, nje = je;
+      if (nj0 >= je) {
+        nq = q + 1;
+        if (nq < qe) {
+          int A = srcl[nq];
+          nj0 = cb[A];
+          nje = ce[A];
         }
       }
-      if constexpr (MIXED) {  // end of a source leaf: carry the FP32 block into FP64
-        nx += (double)fx;
-        ny += (double)fy;
-        nz += (double)fz;
-        np += (double)fp;
+      __builtin_amdgcn_wave_barrier();
+      sbuf[wv][lane] = cur;
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the staged chunk is visible to the wave
+      cur = make_double4(0.0, 0.0, 0.0, 0.0);
+      if (nq < qe && lane < nje - nj0) cur = pm[nj0 + lane];
+      int tmax = act ? na : 0;
+      for (int t = g; t < tmax; t += G) {
+        double4 sb = sbuf[wv][t];
+        int j = j0 + t;
+        if constexpr (MIXED) {
+          float dx = (float)(sb.x - me.x), dy = (float)(sb.y - me.y), dz = (float)(sb.z - me.z);
+          float d2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f)));
+          float rinv = __builtin_amdgcn_rsqf(d2);
+          rinv = (j != i && d2 > 0.f) ? rinv : 0.f;
+          float mr = (float)sb.w * rinv;
+          float mr3 = mr * rinv * rinv;
+          fx = fmaf(mr3, dx, fx);
+          fy = fmaf(mr3, dy, fy);
+          fz = fmaf(mr3, dz, fz);
+          fp -= mr;
+        } else {
+          double dx = sb.x - me.x, dy = sb.y - me.y, dz = sb.z - me.z;
+          double d2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+          double rinv = rsqrt_d(d2);
+          rinv = (j != i && d2 > 0.0) ? rinv : 0.0;
+          double mr = sb.w * rinv;
+          double mr3 = mr * rinv * rinv;
+          nx = fma(mr3, dx, nx);
+          ny = fma(mr3, dy, ny);
+          nz = fma(mr3, dz, nz);
+          np -= mr;
+        }
       }
+      if constexpr (MIXED) {
+        if (nq != q) {  // end of a source leaf: carry the FP32 block into FP64
+          nx += (double)fx;
+          ny += (double)fy;
+          nz += (double)fz;
+          np += (double)fp;
+          fx = fy = fz = fp = 0.f;
+        }
+      }
+      q = nq;
+      j0 = nj0;
+      je = nje;
     }
     // combine the groups in order
     __builtin_amdgcn_wave_barrier();

@@ -404,7 +404,11 @@ static bool dispatch(Ctx& c, int first_lo) {
   }
 }
 
-void launch_m2l_fp64(Ctx& c) { launch_m2l_fp64_range(c, (int)c.ncell); }
+void launch_m2l_fp64(Ctx& c) {
+  if (c.have_events) HIPCHK(hipEventRecord(c.ev[9], c.stream));
+  launch_m2l_fp64_range(c, (int)c.ncell);
+  if (c.have_events) HIPCHK(hipEventRecord(c.ev[10], c.stream));
+}
 
 // FP64 M2L for all pairs whose sink is above first_lo or whose source is
 // (first_lo = ncell: every pair); writes loc, which must be zeroed before

@@ -438,15 +438,23 @@ void launch_m2l_mixed(Ctx& c) {
   int first_lo = K <= c.depth ? c.lvl_first[K] : nc;
   // FP64 for every pair touching a root-level cell (overwrites loc)
   launch_m2l_fp64_range(c, first_lo);
-  if (first_lo >= nc) return;
+  if (first_lo >= nc) {
+    if (c.have_events) {  // no FP32 pairs: the main M2L kernel time is zero
+      HIPCHK(hipEventRecord(c.ev[9], c.stream));
+      HIPCHK(hipEventRecord(c.ev[10], c.stream));
+    }
+    return;
+  }
   ensure(c.ws, c.scale, (size_t)nc);
   ensure(c.ws, c.nmult, (size_t)nc * (c.p + 1) * (c.p + 1));
   hipLaunchKernelGGL(k_scale, dim3((nc + 255) / 256), dim3(256), 0, c.stream, nc, c.c_rad.p, c.scale.p);
   int64_t tot = (int64_t)nc * (c.p + 1) * (c.p + 1);
   hipLaunchKernelGGL(k_normalize32, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, c.stream, c.p, nc,
                      c.mult.p, c.scale.p, c.nmult.p);
+  if (c.have_events) HIPCHK(hipEventRecord(c.ev[9], c.stream));
   if (!dispatch32<1>(c, first_lo)) throw hip_error{hipErrorInvalidValue, "M2L order not compiled"};
   HIPCHK(hipGetLastError());
+  if (c.have_events) HIPCHK(hipEventRecord(c.ev[10], c.stream));
 }
 
 }  // namespace fmm

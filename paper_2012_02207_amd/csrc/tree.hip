@@ -193,6 +193,59 @@ __global__ void __launch_bounds__(BB_T) k_bbox_final(const double* part, int nb,
   rootbox[4] = 2097152.0 / L;
 }
 
+// one workgroup per system (the systems of a batch): the same box over the
+// bodies [off[s], off[s+1]) (min and max are exact in any order)
+__global__ void __launch_bounds__(BB_T) k_bbox_sys(const double* pos, const int* off, double* rootbox) {
+  __shared__ double sh[6][BB_T];
+  int sys = blockIdx.x, t = threadIdx.x;
+  int64_t b = off[sys], e = off[sys + 1];
+  double lo[3], hi[3];
+  for (int d = 0; d < 3; d++) lo[d] = hi[d] = pos[3 * b + d];
+  for (int64_t i = b + t; i < e; i += BB_T)
+    for (int d = 0; d < 3; d++) {
+      double v = pos[3 * i + d];
+      if (v < lo[d]) lo[d] = v;
+      if (v > hi[d]) hi[d] = v;
+    }
+  for (int d = 0; d < 3; d++) {
+    sh[d][t] = lo[d];
+    sh[3 + d][t] = hi[d];
+  }
+  __syncthreads();
+  for (int o = BB_T / 2; o > 0; o >>= 1) {
+    if (t < o)
+      for (int d = 0; d < 3; d++) {
+        if (sh[d][t + o] < sh[d][t]) sh[d][t] = sh[d][t + o];
+        if (sh[3 + d][t + o] > sh[3 + d][t]) sh[3 + d][t] = sh[3 + d][t + o];
+      }
+    __syncthreads();
+  }
+  if (t != 0) return;
+  double L = sh[3][0] - sh[0][0];
+  if (sh[4][0] - sh[1][0] > L) L = sh[4][0] - sh[1][0];
+  if (sh[5][0] - sh[2][0] > L) L = sh[5][0] - sh[2][0];
+  if (L == 0.0) L = 1.0;
+  double* rb = rootbox + 8 * sys;
+  rb[0] = sh[0][0];
+  rb[1] = sh[1][0];
+  rb[2] = sh[2][0];
+  rb[3] = L;
+  rb[4] = 2097152.0 / L;
+}
+
+// system of body i: the last s with off[s] <= i
+__device__ __forceinline__ int system_of(const int* off, int nsys, int64_t i) {
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= i)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 // ===================================================================== keys
 __device__ __forceinline__ uint64_t spread3(uint64_t x) {
   x &= 0x1fffffull;
@@ -214,9 +267,11 @@ __device__ __forceinline__ uint64_t compact3(uint64_t x) {
   return x;
 }
 
-__global__ void k_keys(const double* pos, int64_t n, const double* rootbox, uint64_t* key, int* idx) {
+__global__ void k_keys(const double* pos, int64_t n, const double* rootbox_all, const int* sys_off,
+                       int nsys, uint64_t* key, int* idx) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const double* rootbox = rootbox_all + (nsys > 1 ? 8 * system_of(sys_off, nsys, i) : 0);
   double s = rootbox[4];
   uint64_t q[3];
   for (int d = 0; d < 3; d++) {
@@ -343,6 +398,25 @@ void radix_sort_keys(Ctx& c, int64_t n, int nbits) {
   }
 }
 
+// second key of a batch: the system of each body of the key-sorted order
+// (from its caller index), payload = its position in that order
+__global__ void k_sys_keys(const int* idx, int64_t n, const int* sys_off, int nsys, uint64_t* skey,
+                           int* spos) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  skey[i] = (uint64_t)system_of(sys_off, nsys, idx[i]);
+  spos[i] = (int)i;
+}
+
+__global__ void k_apply_pos(const int* spos, int64_t n, const uint64_t* kin, const int* vin,
+                            uint64_t* kout, int* vout) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int j = spos[i];
+  kout[i] = kin[j];
+  vout[i] = vin[j];
+}
+
 __global__ void k_gather(const double* pos, const double* mass, const int* idx, int64_t n, double* sx,
                          double* sy, double* sz, double* sm, double4* pm) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -418,11 +492,15 @@ __global__ void k_emit_children(int first, int count, int level, int next_first,
   }
 }
 
-__global__ void k_root(int n, int* c_level, int* c_begin, int* c_end, int* c_parent) {
-  c_level[0] = 0;
-  c_begin[0] = 0;
-  c_end[0] = n;
-  c_parent[0] = -1;
+// one root per system: cell s holds the bodies of system s
+__global__ void k_roots(int nsys, const int* sys_off, int* c_level, int* c_begin, int* c_end,
+                        int* c_parent) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsys) return;
+  c_level[s] = 0;
+  c_begin[s] = sys_off[s];
+  c_end[s] = sys_off[s + 1];
+  c_parent[s] = -1;
 }
 
 // mass, first moments and centre of mass, one level (deepest first); leaves sum
@@ -430,7 +508,7 @@ __global__ void k_root(int n, int* c_level, int* c_begin, int* c_end, int* c_par
 __global__ void k_mass_com(int first, int count, int level, const int* cb, const int* ce,
                            const int* c0, const int* nch, const double* sx, const double* sy,
                            const double* sz, const double* sm, const uint64_t* key,
-                           const double* rootbox, double* cm, double* csx, double* csy, double* csz,
+                           const double* rootbox_all, const int* sys_off, int nsys, double* cm, double* csx, double* csy, double* csz,
                            double* cx, double* cy, double* cz) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= count) return;
@@ -461,6 +539,7 @@ __global__ void k_mass_com(int first, int count, int level, const int* cb, const
     cy[c] = Y / M;
     cz[c] = Z / M;
   } else {  // massless cell: centre of its cubic box
+    const double* rootbox = rootbox_all + (nsys > 1 ? 8 * system_of(sys_off, nsys, cb[c]) : 0);
     uint64_t k0 = key[cb[c]];
     int sh = FMM_MAX_LEVEL - level;
     double h = ldexp(rootbox[3], -level);
@@ -533,6 +612,7 @@ static inline dim3 grid1(int64_t n, int t = 256) { return dim3((unsigned)ceil_di
 void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
   hipStream_t s = c.stream;
   c.n = n;
+  int nsys = c.nsys;
   for (int k = 0; k < 2; k++) {
     ensure(c.ws, c.key[k], n);
     ensure(c.ws, c.idx[k], n);
@@ -542,21 +622,57 @@ void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
   ensure(c.ws, c.sz, n);
   ensure(c.ws, c.sm, n);
   ensure(c.ws, c.leaf_of, n);
-  ensure(c.ws, c.rootbox, 8);
-  int nbb = (int)std::min<int64_t>(1024, ceil_div(n, BB_T));
-  ensure(c.ws, c.bbox_part, (size_t)6 * nbb);
-  hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(BB_T), 0, s, pos, n, c.bbox_part.p);
-  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(BB_T), 0, s, c.bbox_part.p, nbb, c.rootbox.p);
-  hipLaunchKernelGGL(k_keys, grid1(n), dim3(256), 0, s, pos, n, c.rootbox.p, c.key[0].p, c.idx[0].p);
+  ensure(c.ws, c.rootbox, (size_t)8 * nsys);
+  {
+    int* before = c.sys_off.p;
+    ensure(c.ws, c.sys_off, (size_t)nsys + 1);
+    if (c.sys_off.p != before) c.sys_off_uploaded.clear();
+  }
+  {
+    std::vector<int> h(c.h_sys_off.begin(), c.h_sys_off.end());
+    if (h.empty()) h = {0, (int)n};
+    if (h != c.sys_off_uploaded) {  // the device copy is reused while the split is unchanged
+      HIPCHK(hipMemcpyAsync(c.sys_off.p, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
+      c.sys_off_uploaded = h;
+    }
+  }
+  if (nsys == 1) {
+    int nbb = (int)std::min<int64_t>(1024, ceil_div(n, BB_T));
+    ensure(c.ws, c.bbox_part, (size_t)6 * nbb);
+    hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(BB_T), 0, s, pos, n, c.bbox_part.p);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(BB_T), 0, s, c.bbox_part.p, nbb, c.rootbox.p);
+  } else {
+    hipLaunchKernelGGL(k_bbox_sys, dim3(nsys), dim3(BB_T), 0, s, pos, c.sys_off.p, c.rootbox.p);
+  }
+  hipLaunchKernelGGL(k_keys, grid1(n), dim3(256), 0, s, pos, n, c.rootbox.p, c.sys_off.p, nsys,
+                     c.key[0].p, c.idx[0].p);
   HIPCHK(hipGetLastError());
   radix_sort_keys(c, n, 64);
+  if (nsys > 1) {
+    // stable pass over the system id: (system, key, caller index) order
+    for (int k = 0; k < 2; k++) {
+      ensure(c.ws, c.skey[k], n);
+      ensure(c.ws, c.spos[k], n);
+    }
+    hipLaunchKernelGGL(k_sys_keys, grid1(n), dim3(256), 0, s, c.idx[0].p, n, c.sys_off.p, nsys,
+                       c.skey[0].p, c.spos[0].p);
+    int bits = 1;
+    while ((1 << bits) < nsys) bits++;
+    int r = radix_sort(c, c.skey[0].p, c.spos[0].p, c.skey[1].p, c.spos[1].p, n, bits);
+    hipLaunchKernelGGL(k_apply_pos, grid1(n), dim3(256), 0, s, c.spos[r].p, n, c.key[0].p, c.idx[0].p,
+                       c.key[1].p, c.idx[1].p);
+    HIPCHK(hipGetLastError());
+    std::swap(c.key[0], c.key[1]);
+    std::swap(c.idx[0], c.idx[1]);
+  }
   ensure(c.ws, c.pm, n);
   hipLaunchKernelGGL(k_gather, grid1(n), dim3(256), 0, s, pos, mass, c.idx[0].p, n, c.sx.p, c.sy.p,
                      c.sz.p, c.sm.p, c.pm.p);
   HIPCHK(hipGetLastError());
 
   // breadth-first levels
-  size_t cap = (size_t)std::max<int64_t>(1024, 4 * n / std::max(1, c.prm.n_leaf) + 64);
+  size_t cap = (size_t)std::max<int64_t>(1024, 4 * n / std::max(1, c.prm.n_leaf) + 64 + 2 * nsys);
   auto ensure_cells = [&](size_t need, bool keep) {
     ensure(c.ws, c.c_level, need, keep, s);
     ensure(c.ws, c.c_begin, need, keep, s);
@@ -566,11 +682,11 @@ void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
     ensure(c.ws, c.c_nchild, need, keep, s);
   };
   ensure_cells(cap, false);
-  hipLaunchKernelGGL(k_root, dim3(1), dim3(1), 0, s, (int)n, c.c_level.p, c.c_begin.p, c.c_end.p,
-                     c.c_parent.p);
+  hipLaunchKernelGGL(k_roots, grid1(nsys), dim3(256), 0, s, nsys, c.sys_off.p, c.c_level.p, c.c_begin.p,
+                     c.c_end.p, c.c_parent.p);
   c.lvl_first.assign(1, 0);
-  c.lvl_count.assign(1, 1);
-  int64_t total_cells = 1;
+  c.lvl_count.assign(1, nsys);
+  int64_t total_cells = nsys;
   ensure(c.ws, c.counters, 256);
   long long* tot = (long long*)c.counters.p;
   for (int level = 0;; level++) {
@@ -611,7 +727,7 @@ void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
     int first = c.lvl_first[level], count = c.lvl_count[level];
     hipLaunchKernelGGL(k_mass_com, grid1(count, 128), dim3(128), 0, s, first, count, level,
                        c.c_begin.p, c.c_end.p, c.c_child0.p, c.c_nchild.p, c.sx.p, c.sy.p, c.sz.p,
-                       c.sm.p, c.key[0].p, c.rootbox.p, c.c_mass.p, c.c_sx.p, c.c_sy.p, c.c_sz.p,
+                       c.sm.p, c.key[0].p, c.rootbox.p, c.sys_off.p, nsys, c.c_mass.p, c.c_sx.p, c.c_sy.p, c.c_sz.p,
                        c.c_cx.p, c.c_cy.p, c.c_cz.p);
     HIPCHK(hipGetLastError());
   }

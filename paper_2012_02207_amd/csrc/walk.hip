@@ -190,7 +190,11 @@ __global__ void __launch_bounds__(WALK_T) k_walk(CellView v, const int2* fin, in
   }
 }
 
-__global__ void k_seed(int2* f) { f[0] = make_int2(0, 0); }
+// the walks start from (root, root) of every system
+__global__ void k_seed(int2* f, int nsys) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nsys) f[s] = make_int2(s, s);
+}
 
 // ---- grouping by sink, sorted by source ----------------------------------
 // The keys (sink << bits | source) are radix-sorted; CSR offsets come from a
@@ -267,8 +271,8 @@ static void run_walk(Ctx& c, CellList& acc, CellList& nearl) {
   int* ctr = c.counters.p + 128;
   int bits = list_bits(c.ncell);
   int* h = (int*)c.hbuf;
-  hipLaunchKernelGGL(k_seed, dim3(1), dim3(1), 0, s, c.front[0].p);
-  int nin = 1, cur = 0;
+  hipLaunchKernelGGL(k_seed, dim3((unsigned)ceil_div(c.nsys, 256)), dim3(256), 0, s, c.front[0].p, c.nsys);
+  int nin = c.nsys, cur = 0;
   int nacc = 0, nnear = 0;
   while (nin > 0) {
     for (;;) {

@@ -25,7 +25,7 @@ EXPORTS = dict(keys=(0, np.uint64), perm=(1, np.int32), cell_level=(2, np.int32)
                m2l=(18, np.int32), p2p=(19, np.int32), local=(20, np.float64),
                rootbox=(21, np.float64))
 SYMBOLS = ["fmm_default_params", "fmm_create", "fmm_set_params", "fmm_build", "fmm_forces",
-           "fmm_stats", "fmm_export", "fmm_set_workspace_limit", "fmm_direct", "fmm_strerror",
+           "fmm_forces_batch", "fmm_stats", "fmm_export", "fmm_set_workspace_limit", "fmm_direct", "fmm_strerror",
            "fmm_last_error", "fmm_destroy"]
 
 
@@ -47,7 +47,8 @@ class Stats(C.Structure):
                 ("n_est_far", C.c_int64), ("n_est_near", C.c_int64), ("n_m2l_fp32", C.c_int64),
                 ("ms_tree", C.c_double), ("ms_upward", C.c_double), ("ms_estimate", C.c_double),
                 ("ms_walk", C.c_double), ("ms_m2l", C.c_double), ("ms_local", C.c_double),
-                ("ms_p2p", C.c_double), ("ms_total", C.c_double), ("workspace_bytes", C.c_size_t)]
+                ("ms_p2p", C.c_double), ("ms_total", C.c_double), ("workspace_bytes", C.c_size_t),
+                ("nsys", C.c_int64), ("ms_m2l_kernel", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -70,6 +71,8 @@ def load_library():
     lib.fmm_set_params.argtypes = [P, C.POINTER(Params)]
     lib.fmm_build.argtypes = [P, C.c_int64, P, P, P]
     lib.fmm_forces.argtypes = [P, C.c_int64, P, P, C.c_double, C.c_int, C.c_double, P, P, P]
+    lib.fmm_forces_batch.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), P, P, C.c_double, C.c_int,
+                                     C.c_double, P, P, P]
     lib.fmm_stats.argtypes = [P, C.POINTER(Stats)]
     lib.fmm_export.argtypes = [P, C.c_int, P, C.c_size_t]
     lib.fmm_set_workspace_limit.argtypes = [P, C.c_size_t]
@@ -79,7 +82,8 @@ def load_library():
     lib.fmm_last_error.argtypes = [P]
     lib.fmm_last_error.restype = C.c_char_p
     lib.fmm_destroy.argtypes = [P]
-    for f in ("fmm_create", "fmm_set_params", "fmm_build", "fmm_forces", "fmm_stats", "fmm_export",
+    for f in ("fmm_create", "fmm_set_params", "fmm_build", "fmm_forces", "fmm_forces_batch",
+              "fmm_stats", "fmm_export",
               "fmm_set_workspace_limit", "fmm_direct"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
@@ -189,6 +193,31 @@ class FMM:
         self.last_p = int(self.params.p if p is None else p)
         return acc, pot
 
+    def forces_batch(self, pos, mass, offsets, eps_soft=0.0, p=None, err_tol=None, out=None):
+        """Independent systems in one pass: system s is bodies offsets[s]:offsets[s+1]
+        (host integers, offsets[0] = 0, strictly increasing).  Returns acc, pot."""
+        torch = _torch()
+        n = mass.shape[0]
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        if off.ndim != 1 or off.size < 2 or off[-1] != n:
+            raise ValueError("offsets must be a 1-D host array ending at the body count")
+        pp = _dev_ptr(pos, torch.float64, (n, 3), "pos")
+        mp = _dev_ptr(mass, torch.float64, (n,), "mass")
+        if out is None:
+            acc = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+            pot = torch.empty((n,), dtype=torch.float64, device=pos.device)
+        else:
+            acc, pot = out
+        self._check(self._lib.fmm_forces_batch(
+            self._h, off.size - 1, off.ctypes.data_as(C.POINTER(C.c_int64)), pp, mp, float(eps_soft),
+            int(self.params.p if p is None else p),
+            float(self.params.err_tol if err_tol is None else err_tol),
+            _dev_ptr(acc, torch.float64, (n, 3), "acc"), _dev_ptr(pot, torch.float64, (n,), "pot"),
+            _stream()))
+        self.n = n
+        self.last_p = int(self.params.p if p is None else p)
+        return acc, pot
+
     def stats(self):
         s = Stats()
         self._check(self._lib.fmm_stats(self._h, C.byref(s)))
@@ -201,7 +230,7 @@ class FMM:
         p = getattr(self, "last_p", self.params.p)
         k = (p + 1) * (p + 2) // 2
         count = {"keys": n, "perm": n, "f_part": n, "cell_com": 3 * nc, "mult": nc * k * 2,
-                 "local": nc * k * 2, "pk": nc * (p + 1), "rootbox": 5,
+                 "local": nc * k * 2, "pk": nc * (p + 1), "rootbox": 5 * st["nsys"],
                  "est_far": 2 * st["n_est_far"], "est_near": 2 * st["n_est_near"],
                  "m2l": 2 * st["n_m2l"], "p2p": 2 * st["n_p2p_cells"]}.get(name, nc)
         buf = np.empty(max(int(count), 1), dtype=dt)
