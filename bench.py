@@ -59,6 +59,29 @@ def l2p_flops(p):
 
 P2P_FLOPS = 20   # per directed body pair: acc + pot, softened, rsqrt counted once
 
+# HBM bytes per launch of a kernel from rocprofv3 FETCH_SIZE and WRITE_SIZE runs,
+# each scaled by what the counter reads for a plain device copy of known size
+# (fetch x2.0, write x1.0).  Keyed by (kernel, workload, precision); valid only
+# while the kernel's source file has the recorded SHA-1 (else reported as null).
+MEASURED_TRAFFIC = {
+    ("k_m2l_fp32", "plummer_1m", "mixed"): (496.7e6, "paper_2012_02207_amd/csrc/m2l_mixed.hip",
+                                             "1b6e7c218b5a21aec1b8a256477155d025195a63"),
+}
+
+
+def measured_traffic(kernel, workload, precision):
+    import hashlib
+    rec = MEASURED_TRAFFIC.get((kernel, workload, precision))
+    if rec is None:
+        return None
+    nbytes, src, sha = rec
+    try:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            cur = hashlib.sha1(f.read()).hexdigest()
+    except OSError:
+        return None
+    return nbytes if cur == sha else None
+
 
 def cpu_baseline(pos, mass, p, err_tol, n_leaf, frac, seed=5):
     """The CPU oracle on a bounded sample: tree, upward pass, estimate and walk
@@ -184,7 +207,8 @@ def main():
     # the dominant stages are vector-ALU bound (no dense contraction on this path)
     roof = {"bound": "alu", "kernel": dom["kernel"],
             "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None,
+            "frac": achieved / peak,
+            "traffic": measured_traffic(dom["kernel"], args.workload, main_pr),
             "flop_per_launch": dom["flop"], "ms_per_launch": dom["ms"]}
     other = {"m2l_main": {"kernel": kname, "pairs": int(n_m2l_main), "ms": m2l_ms,
                           "tflops": f_m2l / (m2l_ms * 1e-3) / 1e12},
