@@ -40,17 +40,22 @@ void ws_free(Workspace& w, void* p, size_t bytes) {
 void launch_leaf_eval(Ctx& c, double* acc, double* pot);
 void launch_l2l(Ctx& c);
 
-__global__ void k_count_p2p_pairs(const int* off, const int* src, const int* cb, const int* ce,
-                                  int ncell, unsigned long long* out) {
-  int B = blockIdx.x * blockDim.x + threadIdx.x;
+
+// M2L pairs with both cells at or below first_lo (the FP32 part of mixed mode)
+__global__ void k_count_low_pairs(const int* off, const int* src, int ncell, int first_lo,
+                                  unsigned long long* out) {
+  int B = first_lo + blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long s = 0;
-  if (B < ncell) {
-    long long nb = ce[B] - cb[B];
-    for (int k = off[B]; k < off[B + 1]; k++) {
-      int A = src[k];
-      long long na = ce[A] - cb[A];
-      s += (unsigned long long)(A == B ? nb * (nb - 1) : na * nb);
+  if (B < ncell) {  // sources ascending: count those >= first_lo by a lower bound
+    int lo = off[B], hi = off[B + 1], e = hi;
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (src[mid] < first_lo)
+        lo = mid + 1;
+      else
+        hi = mid;
     }
+    s = (unsigned long long)(e - lo);
   }
   if (s) atomicAdd(out, s);
 }
@@ -268,15 +273,27 @@ fmm_status fmm_stats(fmm_ctx* ctx, fmm_stats_t* out) {
     if (c.walked) {
       out->n_m2l = c.m2l.count;
       out->n_p2p_cells = c.p2p.count;
-      out->n_m2l_fp32 = c.prm.precision == FMM_MIXED ? c.n_m2l_fp32 : 0;
+      out->n_m2l_fp32 = 0;
+      if (c.prm.precision == FMM_MIXED) {
+        int K = c.prm.root_levels;
+        int first_lo = K <= c.depth ? c.lvl_first[K] : (int)c.ncell;
+        unsigned long long* d = (unsigned long long*)(c.counters.p + 48);
+        HIPCHK(hipMemsetAsync(d, 0, 8, c.stream));
+        int cnt = (int)c.ncell - first_lo;
+        if (cnt > 0)
+          hipLaunchKernelGGL(k_count_low_pairs, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0,
+                             c.stream, c.m2l.off.p, c.m2l.src.p, (int)c.ncell, first_lo, d);
+        HIPCHK(hipMemcpyAsync(c.hbuf + 1, d, 8, hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(hipStreamSynchronize(c.stream));
+        out->n_m2l_fp32 = c.hbuf[1];
+      }
       // body-pair count of the near field
-      unsigned long long* d = (unsigned long long*)(c.counters.p + 40);
-      HIPCHK(hipMemsetAsync(d, 0, 8, c.stream));
-      hipLaunchKernelGGL(k_count_p2p_pairs, dim3((unsigned)((c.ncell + 255) / 256)), dim3(256), 0,
-                         c.stream, c.p2p.off.p, c.p2p.src.p, c.c_begin.p, c.c_end.p, (int)c.ncell, d);
-      HIPCHK(hipMemcpyAsync(c.hbuf, d, 8, hipMemcpyDeviceToHost, c.stream));
-      HIPCHK(hipStreamSynchronize(c.stream));
-      out->n_p2p_pairs = c.hbuf[0];
+      if (c.evaluated) {  // counted by the leaf kernel of the last evaluation
+        unsigned long long* d = (unsigned long long*)(c.counters.p + 40);
+        HIPCHK(hipMemcpyAsync(c.hbuf, d, 8, hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(hipStreamSynchronize(c.stream));
+        out->n_p2p_pairs = c.hbuf[0];
+      }
     }
     if (c.estimated) {
       out->n_est_far = c.est_far.count;

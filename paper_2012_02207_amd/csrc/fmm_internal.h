@@ -144,7 +144,6 @@ struct Ctx {
   dbuf<int> counters;  // device counters
   CellList est_far, est_near, m2l, p2p;
   int64_t n_p2p_pairs = 0;
-  int64_t n_m2l_fp32 = 0;
 
   // scan scratch
   dbuf<int> scan_tmp;
@@ -162,6 +161,7 @@ struct Ctx {
 void exclusive_scan(Ctx& c, const int* in, int* out, int64_t n, long long* total_dev);
 long long read_total(Ctx& c, const long long* total_dev);
 int radix_sort(Ctx& c, uint64_t* k0, int* v0, uint64_t* k1, int* v1, int64_t n, int nbits);
+uint32_t* radix_sort_narrow(Ctx& c, const uint64_t* in, uint32_t* b0, uint32_t* b1, int64_t n, int nbits);
 
 void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass);
 void upward_pass(Ctx& c);

@@ -9,81 +9,89 @@
 
 namespace fmm {
 
-// Regular harmonics with fused multiply-adds (evaluation only, not fed to the
-// acceptance test), written to LDS at stride `st`.
-__device__ inline void regular_fast(int p, double x, double y, double z, double* re, double* im,
-                                    int st) {
-  double r2 = fma(x, x, fma(y, y, z * z));
-  re[0] = 1.0;
-  im[0] = 0.0;
-  double pr = 1.0, pi = 0.0;
-  for (int n = 1; n <= p; n++) {
-    double inv = -1.0 / (double)(2 * n);
-    double tr = fma(x, pr, -y * pi), ti = fma(x, pi, y * pr);
-    pr = tr * inv;
-    pi = ti * inv;
-    re[cidx(n, n) * st] = pr;
-    im[cidx(n, n) * st] = pi;
+// L2L, one workgroup per parent: L_child(j, i) += sum_{k <= p-j} sum_{l=-k..k}
+// L_parent(j+k, i+l) conj(Y_k^l(z_child - z_parent)).  The parent expansion
+// and the conjugated harmonics of every child are laid out in LDS for both
+// signs of the order (entry n(n+1) + m, m = -n..n), which makes every sum a
+// branch-free loop; lanes evaluate harmonic columns, then (child,
+// coefficient) sums.
+constexpr int L2L_T = 256;
+
+__global__ void __launch_bounds__(L2L_T) k_l2l(int p, int first, int count, const int* c0,
+                                              const int* nch, const double* cx, const double* cy,
+                                              const double* cz, double* loc) {
+  extern __shared__ double lds[];
+  int P = first + blockIdx.x;
+  if (blockIdx.x >= count || nch[P] == 0) return;
+  int nc = ncoef(p), S = (p + 1) * (p + 1);
+  int k0 = c0[P], kn = nch[P];
+  double2* Lx = (double2*)lds;  // [S]
+  double2* Yc = Lx + S;         // [child][S]
+  int t = threadIdx.x;
+  const double* Lp = loc + (size_t)P * nc * 2;
+  for (int u = t; u < S; u += L2L_T) {
+    int n = 0;
+    while ((n + 1) * (n + 1) <= u) n++;
+    int m = u - n * n - n, am = m < 0 ? -m : m;
+    double a = Lp[2 * cidx(n, am)], b = Lp[2 * cidx(n, am) + 1];
+    if (m < 0) {
+      double sg = (am & 1) ? -1.0 : 1.0;
+      a = sg * a;
+      b = -sg * b;
+    }
+    Lx[u] = make_double2(a, b);
   }
-  for (int m = 0; m < p; m++) {
-    double ar2 = 0.0, ai2 = 0.0, ar1 = re[cidx(m, m) * st], ai1 = im[cidx(m, m) * st];
+  for (int u = t; u < kn * (p + 1); u += L2L_T) {  // column m of child j's harmonics
+    int j = u / (p + 1), m = u - j * (p + 1);
+    int ch = k0 + j;
+    double x = cx[ch] - cx[P], y = cy[ch] - cy[P], z = cz[ch] - cz[P];
+    double r2 = fma(x, x, fma(y, y, z * z));
+    double pr = 1.0, pi = 0.0;
+    for (int n = 1; n <= m; n++) {
+      double inv = -1.0 / (double)(2 * n);
+      double tr = fma(x, pr, -y * pi), ti = fma(x, pi, y * pr);
+      pr = tr * inv;
+      pi = ti * inv;
+    }
+    double2* Y = Yc + j * S;
+    double sg = (m & 1) ? -1.0 : 1.0;
+    // conj(Y_n^m) at +m; conj(Y_n^-m) = (-1)^m Y_n^m at -m
+    Y[m * m + m + m] = make_double2(pr, -pi);
+    if (m > 0) Y[m * m] = make_double2(sg * pr, sg * pi);
+    double ar2 = 0.0, ai2 = 0.0, ar1 = pr, ai1 = pi;
     for (int n = m + 1; n <= p; n++) {
       double k = (double)(2 * n - 1) * z, inv = 1.0 / (double)((n + m) * (n - m));
       double vr = fma(k, ar1, -r2 * ar2) * inv, vi = fma(k, ai1, -r2 * ai2) * inv;
-      re[cidx(n, m) * st] = vr;
-      im[cidx(n, m) * st] = vi;
+      Y[n * n + n + m] = make_double2(vr, -vi);
+      if (m > 0) Y[n * n + n - m] = make_double2(sg * vr, sg * vi);
       ar2 = ar1;
       ai2 = ai1;
       ar1 = vr;
       ai1 = vi;
     }
   }
-}
-
-// L_child(j, i) += sum_{k <= p-j} sum_l L_parent(j+k, i+l) conj(Y_k^l(z_child - z_parent))
-__global__ void __launch_bounds__(64) k_l2l(int p, int first, int count, const int* parent,
-                                            const double* cx, const double* cy, const double* cz,
-                                            double* loc) {
-  __shared__ double yre[ncoef(FMM_GPU_PMAX)], yim[ncoef(FMM_GPU_PMAX)];
-  int c = first + blockIdx.x;
-  if (blockIdx.x >= count) return;
-  int P = parent[c];
-  if (threadIdx.x == 0) regular_fast(p, cx[c] - cx[P], cy[c] - cy[P], cz[c] - cz[P], yre, yim, 1);
   __syncthreads();
-  int nc = ncoef(p);
-  const double* Lp = loc + (size_t)P * nc * 2;
-  double* Lc = loc + (size_t)c * nc * 2;
-  for (int t = threadIdx.x; t < nc; t += 64) {
-    int j = 0;
-    while (cidx(j + 1, 0) <= t) j++;
-    int i = t - cidx(j, 0);
+  for (int u = t; u < kn * nc; u += L2L_T) {
+    int j = u / nc, q = u - j * nc;
+    int jn = 0;
+    while (cidx(jn + 1, 0) <= q) jn++;
+    int i = q - cidx(jn, 0);
+    const double2* Y = Yc + j * S;
     double sr = 0.0, si = 0.0;
-    for (int k = 0; k <= p - j; k++)
-      for (int l = -k; l <= k; l++) {
-        int n = j + k, m = i + l;
-        double ar, ai;
-        if (m >= 0) {
-          ar = Lp[2 * cidx(n, m)];
-          ai = Lp[2 * cidx(n, m) + 1];
-        } else {
-          double s = (m & 1) ? -1.0 : 1.0;
-          ar = s * Lp[2 * cidx(n, -m)];
-          ai = -s * Lp[2 * cidx(n, -m) + 1];
-        }
-        double br, bi;  // conj(Y_k^l)
-        if (l >= 0) {
-          br = yre[cidx(k, l)];
-          bi = -yim[cidx(k, l)];
-        } else {
-          double s = (l & 1) ? -1.0 : 1.0;
-          br = s * yre[cidx(k, -l)];
-          bi = s * yim[cidx(k, -l)];
-        }
-        sr = fma(ar, br, fma(-ai, bi, sr));
-        si = fma(ar, bi, fma(ai, br, si));
+    for (int k = 0; k <= p - jn; k++) {
+      int n = jn + k;
+      const double2* Ln = Lx + n * n + n + i - k;
+      const double2* Yk = Y + k * k;
+#pragma unroll 4
+      for (int r = 0; r <= 2 * k; r++) {  // l = r - k
+        double2 a = Ln[r], b = Yk[r];
+        sr = fma(a.x, b.x, fma(-a.y, b.y, sr));
+        si = fma(a.x, b.y, fma(a.y, b.x, si));
       }
-    Lc[2 * t] += sr;
-    Lc[2 * t + 1] += si;
+    }
+    double* Lc = loc + (size_t)(k0 + j) * nc * 2;
+    Lc[2 * q] += sr;
+    Lc[2 * q + 1] += si;
   }
 }
 
@@ -174,7 +182,8 @@ __global__ void __launch_bounds__(64 * LG_WAVES) k_leaf_group(int p, const int* 
                                                               const double* __restrict__ loc,
                                                               const double4* __restrict__ pm,
                                                               const int* __restrict__ perm, double eps2,
-                                                              double* acc, double* pot) {
+                                                              double* acc, double* pot,
+                                                              unsigned long long* npairs) {
   __shared__ double4 sbuf[LG_WAVES][64];
   __shared__ double rbuf[LG_WAVES][4][64];
   int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -187,6 +196,7 @@ __global__ void __launch_bounds__(64 * LG_WAVES) k_leaf_group(int p, const int* 
   int b = cb[B], e = ce[B];
   int qb = off[B], qe = off[B + 1];
   float eps2f = (float)eps2;
+  long long pairs = 0;  // body pairs of this leaf (self pairs excluded), wave-uniform
   for (int i0 = b; i0 < e; i0 += 64) {
     int nB = min(64, e - i0);
     int G = 64 / nB;
@@ -208,6 +218,7 @@ __global__ void __launch_bounds__(64 * LG_WAVES) k_leaf_group(int p, const int* 
     if (q < qe && lane < je - j0) cur = pm[j0 + lane];
     while (q < qe) {
       int na = min(64, je - j0);
+      pairs += (long long)nB * na - max(0, min(i0 + nB, j0 + na) - max(i0, j0));
       int nq = q, nj0 = j0 + 64, nje = je;
       if (nj0 >= je) {
         nq = q + 1;
@@ -292,30 +303,35 @@ __global__ void __launch_bounds__(64 * LG_WAVES) k_leaf_group(int p, const int* 
     }
     __builtin_amdgcn_wave_barrier();
   }
+  if (lane == 0 && pairs > 0) atomicAdd(npairs, (unsigned long long)pairs);
 }
 
 void launch_leaf_eval(Ctx& c, double* acc, double* pot) {
   if (c.nleaf <= 0) return;
   const int* leaves = c.leaves.p;
+  // body-pair count of the near field, read by fmm_stats
+  unsigned long long* npairs = (unsigned long long*)(c.counters.p + 40);
+  HIPCHK(hipMemsetAsync(npairs, 0, sizeof(unsigned long long), c.stream));
   int nblk = (int)((c.nleaf + LG_WAVES - 1) / LG_WAVES);
   unsigned grid = 8u * (unsigned)((nblk + 7) / 8);
   double e2 = c.eps_soft * c.eps_soft;
   if (c.prm.precision == FMM_MIXED)
     hipLaunchKernelGGL(k_leaf_group<true>, dim3(grid), dim3(64 * LG_WAVES), 0, c.stream, c.p, leaves,
                        (int)c.nleaf, c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.c_cx.p, c.c_cy.p,
-                       c.c_cz.p, c.loc.p, c.pm.p, c.idx[0].p, e2, acc, pot);
+                       c.c_cz.p, c.loc.p, c.pm.p, c.idx[0].p, e2, acc, pot, npairs);
   else
     hipLaunchKernelGGL(k_leaf_group<false>, dim3(grid), dim3(64 * LG_WAVES), 0, c.stream, c.p, leaves,
                        (int)c.nleaf, c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.c_cx.p, c.c_cy.p,
-                       c.c_cz.p, c.loc.p, c.pm.p, c.idx[0].p, e2, acc, pot);
+                       c.c_cz.p, c.loc.p, c.pm.p, c.idx[0].p, e2, acc, pot, npairs);
   HIPCHK(hipGetLastError());
 }
 
 void launch_l2l(Ctx& c) {
-  for (int level = 1; level <= c.depth; level++) {
+  size_t lds = sizeof(double2) * 9 * (size_t)(c.p + 1) * (c.p + 1);
+  for (int level = 0; level < c.depth; level++) {  // parents at this level, children one below
     int first = c.lvl_first[level], count = c.lvl_count[level];
-    hipLaunchKernelGGL(k_l2l, dim3(count), dim3(64), 0, c.stream, c.p, first, count, c.c_parent.p,
-                       c.c_cx.p, c.c_cy.p, c.c_cz.p, c.loc.p);
+    hipLaunchKernelGGL(k_l2l, dim3(count), dim3(L2L_T), lds, c.stream, c.p, first, count, c.c_child0.p,
+                       c.c_nchild.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.loc.p);
   }
   HIPCHK(hipGetLastError());
 }

@@ -291,8 +291,9 @@ __global__ void k_keys(const double* pos, int64_t n, const double* rootbox_all, 
 // exclusive scan over the digit-major block histograms.
 constexpr int RS_T = 256, RS_W = RS_T / 64, RS_I = 16, RS_TILE = RS_T * RS_I;
 
-__global__ void __launch_bounds__(RS_T) k_rs_hist(const uint64_t* key, int64_t n, int shift,
-                                                  int* hist, int nblocks) {
+template <class K>
+__global__ void __launch_bounds__(RS_T) k_rs_hist(const K* key, int64_t n, int shift, int* hist,
+                                                  int nblocks) {
   __shared__ int cnt[256];
   cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -305,10 +306,9 @@ __global__ void __launch_bounds__(RS_T) k_rs_hist(const uint64_t* key, int64_t n
   hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
-template <bool VAL>
-__global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t* kin, const int* vin,
-                                                     uint64_t* kout, int* vout, int64_t n,
-                                                     int shift, const int* offs, int nblocks) {
+template <bool VAL, class KI, class KO>
+__global__ void __launch_bounds__(RS_T) k_rs_scatter(const KI* kin, const int* vin, KO* kout, int* vout,
+                                                     int64_t n, int shift, const int* offs, int nblocks) {
   __shared__ int wcnt[RS_W][256];
   __shared__ int goff[256];
   int w = threadIdx.x >> 6;
@@ -317,7 +317,7 @@ __global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t* kin, const 
   goff[threadIdx.x] = offs[(int64_t)threadIdx.x * nblocks + blockIdx.x];
   __syncthreads();
   int64_t base = (int64_t)blockIdx.x * RS_TILE + (int64_t)w * (RS_TILE / RS_W);
-  uint64_t k[RS_I];
+  KI k[RS_I];
   int v[RS_I], rank[RS_I];
   uint64_t lt = lanemask_lt();
   for (int c = 0; c < RS_I; c++) {
@@ -355,7 +355,7 @@ __global__ void __launch_bounds__(RS_T) k_rs_scatter(const uint64_t* kin, const 
     int d = (int)((k[c] >> shift) & 255);
     int64_t dst = (int64_t)goff[d] + wcnt[w][d] + rank[c];
     if (dst < n) {  // always true when the ranks are consistent with the histogram
-      kout[dst] = k[c];
+      kout[dst] = (KO)k[c];
       if (VAL) vout[dst] = v[c];
     }
   }
@@ -374,19 +374,48 @@ int radix_sort(Ctx& c, uint64_t* k0, int* v0, uint64_t* k1, int* v1, int64_t n, 
   uint64_t* kk[2] = {k0, k1};
   int* vv[2] = {v0, v1};
   for (int shift = 0; shift < nbits; shift += 8) {
-    hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_T), 0, c.stream, kk[src], n, shift, hist, nb);
+    hipLaunchKernelGGL(k_rs_hist<uint64_t>, dim3(nb), dim3(RS_T), 0, c.stream, kk[src], n, shift, hist, nb);
     HIPCHK(hipGetLastError());
     exclusive_scan(c, hist, offs, (int64_t)256 * nb, nullptr);
     if (v0)
-      hipLaunchKernelGGL(k_rs_scatter<true>, dim3(nb), dim3(RS_T), 0, c.stream, kk[src], vv[src],
-                         kk[1 - src], vv[1 - src], n, shift, offs, nb);
+      hipLaunchKernelGGL((k_rs_scatter<true, uint64_t, uint64_t>), dim3(nb), dim3(RS_T), 0, c.stream,
+                         kk[src], vv[src], kk[1 - src], vv[1 - src], n, shift, offs, nb);
     else
-      hipLaunchKernelGGL(k_rs_scatter<false>, dim3(nb), dim3(RS_T), 0, c.stream, kk[src], nullptr,
-                         kk[1 - src], nullptr, n, shift, offs, nb);
+      hipLaunchKernelGGL((k_rs_scatter<false, uint64_t, uint64_t>), dim3(nb), dim3(RS_T), 0, c.stream,
+                         kk[src], nullptr, kk[1 - src], nullptr, n, shift, offs, nb);
     HIPCHK(hipGetLastError());
     src = 1 - src;
   }
   return src;
+}
+
+// Stable LSD sort of n 64-bit keys whose values fit in nbits <= 32 bits: the
+// first pass reads the 64-bit keys and writes 32-bit ones, later passes move
+// 32-bit keys between b0 and b1.  Returns the buffer holding the result.
+uint32_t* radix_sort_narrow(Ctx& c, const uint64_t* in, uint32_t* b0, uint32_t* b1, int64_t n, int nbits) {
+  if (n <= 0) return b0;
+  int nb = (int)ceil_div(n, RS_TILE);
+  ensure(c.ws, c.sort_hist, (size_t)256 * nb * 2 + 64);
+  int* hist = c.sort_hist.p;
+  int* offs = hist + (size_t)256 * nb;
+  hipLaunchKernelGGL(k_rs_hist<uint64_t>, dim3(nb), dim3(RS_T), 0, c.stream, in, n, 0, hist, nb);
+  HIPCHK(hipGetLastError());
+  exclusive_scan(c, hist, offs, (int64_t)256 * nb, nullptr);
+  hipLaunchKernelGGL((k_rs_scatter<false, uint64_t, uint32_t>), dim3(nb), dim3(RS_T), 0, c.stream, in,
+                     nullptr, b0, nullptr, n, 0, offs, nb);
+  HIPCHK(hipGetLastError());
+  uint32_t* bb[2] = {b0, b1};
+  int src = 0;
+  for (int shift = 8; shift < nbits; shift += 8) {
+    hipLaunchKernelGGL(k_rs_hist<uint32_t>, dim3(nb), dim3(RS_T), 0, c.stream, bb[src], n, shift, hist, nb);
+    HIPCHK(hipGetLastError());
+    exclusive_scan(c, hist, offs, (int64_t)256 * nb, nullptr);
+    hipLaunchKernelGGL((k_rs_scatter<false, uint32_t, uint32_t>), dim3(nb), dim3(RS_T), 0, c.stream,
+                       bb[src], nullptr, bb[1 - src], nullptr, n, shift, offs, nb);
+    HIPCHK(hipGetLastError());
+    src = 1 - src;
+  }
+  return bb[src];
 }
 
 // sorts c.key[0]/c.idx[0] (n entries) over bits [0, nbits); result in key[0]/idx[0]

@@ -21,71 +21,121 @@ static __constant__ double c_fact[2 * FMM_TABLE_PMAX + 2];
 static __constant__ double c_binom[FMM_TABLE_PMAX + 1][FMM_TABLE_PMAX + 1];
 static bool g_up_tables = false;
 
-// LDS budget per P2M workgroup (dynamic, sized from p so that several
-// workgroups share a CU)
-constexpr int P2M_LDS_DOUBLES = 2560;  // 20 KB
-
-// bodies handled per LDS batch so that 2 * ncoef * batch doubles fit
-__host__ __device__ inline int p2m_batch(int p) {
-  int nc = ncoef(p), b = 64;
-  while (b > 1 && 2 * nc * b > P2M_LDS_DOUBLES) b >>= 1;
-  return b;
+// Column m of the regular harmonics of (x, y, z) in the exact rounding
+// sequence of the full recurrence (the same arithmetic as regular_exact): the
+// diagonal Y_1^1 .. Y_m^m, then Y_n^m for n = m+1..p.  Lanes evaluate
+// different columns (and bodies) in parallel.
+template <class Store>
+__device__ inline void regular_column_exact(int p, int m, double x, double y, double z, Store store) {
+  double r2 = (x * x + y * y) + z * z;
+  double pr = 1.0, pi = 0.0;
+  for (int n = 1; n <= m; n++) {
+    double tr = x * pr - y * pi;
+    double ti = x * pi + y * pr;
+    double den = (double)(2 * n);
+    pr = (-tr) / den;
+    pi = (-ti) / den;
+  }
+  store(m, pr, pi);
+  double ar2 = 0.0, ai2 = 0.0, ar1 = pr, ai1 = pi;
+  for (int n = m + 1; n <= p; n++) {
+    double k = (double)(2 * n - 1) * z;
+    double nr = k * ar1, ni = k * ai1;
+    if (n - 2 >= m) {
+      double br = r2 * ar2, bi = r2 * ai2;
+      nr = nr - br;
+      ni = ni - bi;
+    }
+    double den = (double)((n + m) * (n - m));
+    double vr = nr / den, vi = ni / den;
+    store(n, vr, vi);
+    ar2 = ar1;
+    ai2 = ai1;
+    ar1 = vr;
+    ai1 = vi;
+  }
 }
 
-constexpr int M2M_T = 128;  // threads per M2M workgroup: one per coefficient (p <= 14)
+// (n, m) of coefficient index t
+__device__ __forceinline__ void coef_nm(int t, int& n, int& m) {
+  n = 0;
+  while (cidx(n + 1, 0) <= t) n++;
+  m = t - cidx(n, 0);
+}
 
-__global__ void __launch_bounds__(64) k_p2m(int p, const int* leaves, int nleaves, const int* cb,
-                                            const int* ce, const double* sx, const double* sy,
-                                            const double* sz, const double* sm, const double* cx,
-                                            const double* cy, const double* cz, double* mult) {
+// P2M: one workgroup per leaf; bodies in batches of P2M_T / (p+1), lane
+// (body, column) evaluates one harmonic column into LDS, then lanes owning
+// coefficients accumulate over the batch in sorted body order.
+constexpr int P2M_T = 256;
+
+__host__ __device__ inline int p2m_batch(int p) { return P2M_T / (p + 1); }
+
+__global__ void __launch_bounds__(P2M_T) k_p2m(int p, const int* leaves, int nleaves, const int* cb,
+                                               const int* ce, const double* sx, const double* sy,
+                                               const double* sz, const double* sm, const double* cx,
+                                               const double* cy, const double* cz, double* mult) {
   extern __shared__ double lds[];
   int li = blockIdx.x;
   if (li >= nleaves) return;
   int c = leaves[li];
   int nc = ncoef(p);
   int batch = p2m_batch(p);
-  double* yre = lds;
+  double* yre = lds;  // [coef][body], stride batch
   double* yim = lds + nc * batch;
-  int lane = threadIdx.x;
+  double* msh = lds + 2 * nc * batch;  // masses of the batch
+  int t = threadIdx.x;
   double x0 = cx[c], y0 = cy[c], z0 = cz[c];
   int b = cb[c], e = ce[c];
-  // each lane keeps the running sums of coefficients lane, lane+64, ...
-  constexpr int MAXK = (ncoef(FMM_TABLE_PMAX) + 63) / 64;
+  constexpr int MAXK = (ncoef(FMM_TABLE_PMAX) + P2M_T - 1) / P2M_T;
   double acr[MAXK], aci[MAXK];
-  for (int t = 0; t < MAXK; t++) acr[t] = aci[t] = 0.0;
+  for (int u = 0; u < MAXK; u++) acr[u] = aci[u] = 0.0;
+  int hb = t / (p + 1), hm = t - hb * (p + 1);  // harmonic lane: body hb, column hm
   for (int i0 = b; i0 < e; i0 += batch) {
     int cnt = min(batch, e - i0);
-    if (lane < cnt) {
-      int i = i0 + lane;
-      regular_exact(p, sx[i] - x0, sy[i] - y0, sz[i] - z0, yre + lane, yim + lane, batch);
+    if (hb < cnt) {
+      int i = i0 + hb;
+      if (hm == 0) msh[hb] = sm[i];
+      regular_column_exact(p, hm, sx[i] - x0, sy[i] - y0, sz[i] - z0, [&](int n, double vr, double vi) {
+        yre[cidx(n, hm) * batch + hb] = vr;
+        yim[cidx(n, hm) * batch + hb] = vi;
+      });
     }
     __syncthreads();
-    for (int t = 0; t < MAXK; t++) {
-      int k = lane + 64 * t;
+    for (int u = 0; u < MAXK; u++) {
+      int k = t + P2M_T * u;
       if (k < nc) {
-        double sr = acr[t], si = aci[t];
+        double sr = acr[u], si = aci[u];
+#pragma unroll 4
         for (int j = 0; j < cnt; j++) {
-          double m = sm[i0 + j];
+          double m = msh[j];
           double tr = m * yre[k * batch + j];
           double ti = m * yim[k * batch + j];
           sr = sr + tr;
           si = si + ti;
         }
-        acr[t] = sr;
-        aci[t] = si;
+        acr[u] = sr;
+        aci[u] = si;
       }
     }
     __syncthreads();
   }
   double* out = mult + (size_t)c * nc * 2;
-  for (int t = 0; t < MAXK; t++) {
-    int k = lane + 64 * t;
+  for (int u = 0; u < MAXK; u++) {
+    int k = t + P2M_T * u;
     if (k < nc) {
-      out[2 * k] = acr[t];
-      out[2 * k + 1] = aci[t];
+      out[2 * k] = acr[u];
+      out[2 * k + 1] = aci[u];
     }
   }
 }
+
+// M2M, one workgroup per parent.  The children's harmonics Y_k^l(z_c - z_P)
+// and moments M_j^q are laid out in LDS for both signs of their order
+// (entry n(n+1) + m, m = -n..n, the negative orders from the stored ones by
+// the conjugate symmetry, exact), so that the sum of each parent coefficient
+// is a branch-free loop in the defining order: children in octant order,
+// then k, then l ascending; products rounded separately.
+constexpr int M2M_T = 128;
 
 __global__ void __launch_bounds__(M2M_T) k_m2m(int p, int first, int count, const int* c0,
                                                 const int* nch, const double* cx, const double* cy,
@@ -94,55 +144,69 @@ __global__ void __launch_bounds__(M2M_T) k_m2m(int p, int first, int count, cons
   int c = first + blockIdx.x;
   if (blockIdx.x >= count || nch[c] == 0) return;
   int nc = ncoef(p);
+  int S = (p + 1) * (p + 1);
   int k0 = c0[c], kn = nch[c];
-  double* yre = lds;             // child j at stride 8
-  double* yim = lds + nc * 8;
-  double* mch = lds + 2 * nc * 8;  // children's moments, contiguous ids -> contiguous rows
-  int lane = threadIdx.x;
-  if (lane < kn) {
-    int ch = k0 + lane;
-    regular_exact(p, cx[ch] - cx[c], cy[ch] - cy[c], cz[ch] - cz[c], yre + lane, yim + lane, 8);
+  double2* Yx = (double2*)lds;  // [child][S]
+  double2* Mx = Yx + 8 * S;     // [child][S]
+  int t = threadIdx.x;
+  for (int u = t; u < kn * (p + 1); u += M2M_T) {  // harmonics, both signs of l
+    int j = u / (p + 1), m = u - j * (p + 1);
+    int ch = k0 + j;
+    double2* Y = Yx + j * S;
+    double sg = (m & 1) ? -1.0 : 1.0;
+    regular_column_exact(p, m, cx[ch] - cx[c], cy[ch] - cy[c], cz[ch] - cz[c],
+                         [&](int n, double vr, double vi) {
+                           Y[n * n + n + m] = make_double2(vr, vi);
+                           if (m > 0) Y[n * n + n - m] = make_double2(sg * vr, -sg * vi);
+                         });
   }
   const double* src = mult + (size_t)k0 * nc * 2;
-  for (int t = lane; t < kn * nc * 2; t += M2M_T) mch[t] = src[t];
+  for (int u = t; u < kn * S; u += M2M_T) {  // moments, both signs of q
+    int j = u / S, r = u - j * S;
+    int n = 0;
+    while ((n + 1) * (n + 1) <= r) n++;
+    int q = r - n * n - n;
+    const double* cm = src + (size_t)j * nc * 2;
+    int aq = q < 0 ? -q : q;
+    double a = cm[2 * cidx(n, aq)], bb = cm[2 * cidx(n, aq) + 1];
+    if (q < 0) {
+      double sg = (aq & 1) ? -1.0 : 1.0;
+      a = sg * a;
+      bb = -sg * bb;
+    }
+    Mx[u] = make_double2(a, bb);
+  }
   __syncthreads();
   double* out = mult + (size_t)c * nc * 2;
-  for (int t = lane; t < nc; t += M2M_T) {
-    // coefficient index t -> (n, m)
-    int n = 0;
-    while (cidx(n + 1, 0) <= t) n++;
-    int m = t - cidx(n, 0);
+  for (int u = t; u < nc; u += M2M_T) {
+    int n, m;
+    coef_nm(u, n, m);
     double sr = 0.0, si = 0.0;
     for (int j = 0; j < kn; j++) {
-      const double* cm = mch + j * nc * 2;
+      const double2* Y = Yx + j * S;
+      const double2* M = Mx + j * S;
       for (int k = 0; k <= n; k++) {
         int jj = n - k;
-        // l ranges over |l| <= k with |m - l| <= jj
         int lo = max(-k, m - jj), hi = min(k, m + jj);
-        for (int l = lo; l <= hi; l++) {
-          int q = m - l;
-          double ar, ai;
-          cget(yre + j, yim + j, 8, k, l, ar, ai);
-          double br, bi;
-          if (q >= 0) {
-            br = cm[2 * cidx(jj, q)];
-            bi = cm[2 * cidx(jj, q) + 1];
-          } else {
-            double s = (q & 1) ? -1.0 : 1.0;
-            br = s * cm[2 * cidx(jj, -q)];
-            bi = -s * cm[2 * cidx(jj, -q) + 1];
-          }
-          double tr = ar * br - ai * bi;
-          double ti = ar * bi + ai * br;
+        const double2* Yk = Y + k * k + k + lo;
+        const double2* Mj = M + jj * jj + jj + m - lo;
+        int cnt = hi - lo + 1;
+#pragma unroll 4
+        for (int r = 0; r < cnt; r++) {  // l = lo + r
+          double2 a = Yk[r], bq = Mj[-r];
+          double tr = a.x * bq.x - a.y * bq.y;
+          double ti = a.x * bq.y + a.y * bq.x;
           sr = sr + tr;
           si = si + ti;
         }
       }
     }
-    out[2 * t] = sr;
-    out[2 * t + 1] = si;
+    out[2 * u] = sr;
+    out[2 * u + 1] = si;
   }
 }
+
+size_t m2m_lds_bytes(int p) { return sizeof(double2) * 2 * 8 * (size_t)(p + 1) * (p + 1); }
 
 // P_k = sqrt( (k!)^2 |M_k^0|^2 + sum_{m=1..k} 2 (k-m)!(k+m)! |M_k^m|^2 ), and the
 // product C(p, k) P_k used by the acceptance test
@@ -193,15 +257,14 @@ void upward_pass(Ctx& c) {
   exclusive_scan(c, flag, off, nc, tot);
   hipLaunchKernelGGL(k_compact_leaves, dim3((nc + 255) / 256), dim3(256), 0, s, flag, off, nc, leaves);
   c.nleaf = read_total(c, tot);
-  size_t p2m_lds = sizeof(double) * 2 * ncoef(p) * p2m_batch(p);
-  hipLaunchKernelGGL(k_p2m, dim3((unsigned)c.nleaf), dim3(64), p2m_lds, s, p, leaves, (int)c.nleaf,
+  size_t p2m_lds = sizeof(double) * (2 * ncoef(p) + 1) * p2m_batch(p);
+  hipLaunchKernelGGL(k_p2m, dim3((unsigned)c.nleaf), dim3(P2M_T), p2m_lds, s, p, leaves, (int)c.nleaf,
                      c.c_begin.p, c.c_end.p, c.sx.p, c.sy.p, c.sz.p, c.sm.p, c.c_cx.p, c.c_cy.p,
                      c.c_cz.p, c.mult.p);
   HIPCHK(hipGetLastError());
   for (int level = c.depth - 1; level >= 0; level--) {
     int first = c.lvl_first[level], count = c.lvl_count[level];
-    size_t m2m_lds = sizeof(double) * 32 * ncoef(p);  // harmonics of 8 children + their moments
-    hipLaunchKernelGGL(k_m2m, dim3(count), dim3(M2M_T), m2m_lds, s, p, first, count, c.c_child0.p,
+    hipLaunchKernelGGL(k_m2m, dim3(count), dim3(M2M_T), m2m_lds_bytes(p), s, p, first, count, c.c_child0.p,
                        c.c_nchild.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.mult.p);
     HIPCHK(hipGetLastError());
   }

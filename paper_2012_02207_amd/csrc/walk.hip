@@ -197,16 +197,18 @@ __global__ void k_seed(int2* f, int nsys) {
 }
 
 // ---- grouping by sink, sorted by source ----------------------------------
-// The keys (sink << bits | source) are radix-sorted; CSR offsets come from a
-// lower bound per sink and the sources are the low bits.
-__global__ void k_csr_off(const uint64_t* keys, int64_t cnt, int nseg, int bits, int* off) {
+// The keys (sink << bits | source) are radix-sorted (as 32-bit keys when
+// 2 bits <= 32); CSR offsets come from a lower bound per sink and the sources
+// are the low bits.
+template <class K>
+__global__ void k_csr_off(const K* keys, int64_t cnt, int nseg, int bits, int* off) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s > nseg) return;
   uint64_t t = (uint64_t)s << bits;
   int64_t lo = 0, hi = cnt;
   while (lo < hi) {
     int64_t mid = (lo + hi) >> 1;
-    if (keys[mid] < t)
+    if ((uint64_t)keys[mid] < t)
       lo = mid + 1;
     else
       hi = mid;
@@ -214,9 +216,10 @@ __global__ void k_csr_off(const uint64_t* keys, int64_t cnt, int nseg, int bits,
   off[s] = (int)lo;
 }
 
-__global__ void k_extract_src(const uint64_t* keys, int64_t cnt, uint64_t mask, int* src) {
+template <class K>
+__global__ void k_extract_src(const K* keys, int64_t cnt, uint64_t mask, int* src) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < cnt) src[i] = (int)(keys[i] & mask);
+  if (i < cnt) src[i] = (int)((uint64_t)keys[i] & mask);
 }
 
 static int list_bits(int64_t ncell) {
@@ -232,15 +235,27 @@ static void group_by_sink(Ctx& c, CellList& L) {
   ensure(c.ws, L.off, (size_t)nc + 1);
   ensure(c.ws, L.src, (size_t)std::max<int64_t>(L.count, 1));
   ensure(c.ws, L.tmp, (size_t)std::max<int64_t>(L.count, 1));
-  const uint64_t* sorted = L.raw.p;
-  if (L.count) {
-    int r = radix_sort(c, L.raw.p, nullptr, L.tmp.p, nullptr, L.count, 2 * bits);
-    sorted = r == 0 ? L.raw.p : L.tmp.p;
-    hipLaunchKernelGGL(k_extract_src, dim3((unsigned)ceil_div(L.count, 256)), dim3(256), 0, s, sorted,
-                       L.count, ((uint64_t)1 << bits) - 1, L.src.p);
+  uint64_t mask = ((uint64_t)1 << bits) - 1;
+  unsigned g = (unsigned)std::max<int64_t>(1, ceil_div(L.count, 256));
+  unsigned go = (unsigned)ceil_div(nc + 1, 256);
+  if (2 * bits <= 32) {
+    uint32_t* b0 = (uint32_t*)L.tmp.p;  // two 32-bit buffers in the 64-bit scratch
+    uint32_t* b1 = b0 + std::max<int64_t>(L.count, 1);
+    const uint32_t* sorted = b0;
+    if (L.count) {
+      sorted = radix_sort_narrow(c, L.raw.p, b0, b1, L.count, 2 * bits);
+      hipLaunchKernelGGL(k_extract_src<uint32_t>, dim3(g), dim3(256), 0, s, sorted, L.count, mask, L.src.p);
+    }
+    hipLaunchKernelGGL(k_csr_off<uint32_t>, dim3(go), dim3(256), 0, s, sorted, L.count, nc, bits, L.off.p);
+  } else {
+    const uint64_t* sorted = L.raw.p;
+    if (L.count) {
+      int r = radix_sort(c, L.raw.p, nullptr, L.tmp.p, nullptr, L.count, 2 * bits);
+      sorted = r == 0 ? L.raw.p : L.tmp.p;
+      hipLaunchKernelGGL(k_extract_src<uint64_t>, dim3(g), dim3(256), 0, s, sorted, L.count, mask, L.src.p);
+    }
+    hipLaunchKernelGGL(k_csr_off<uint64_t>, dim3(go), dim3(256), 0, s, sorted, L.count, nc, bits, L.off.p);
   }
-  hipLaunchKernelGGL(k_csr_off, dim3((unsigned)ceil_div(nc + 1, 256)), dim3(256), 0, s, sorted, L.count,
-                     nc, bits, L.off.p);
   HIPCHK(hipGetLastError());
 }
 
@@ -332,16 +347,28 @@ __global__ void k_fcell(int ncell, const int* off, const int* src, const double*
 }
 
 // f_i = (F summed from the root down to the leaf) + sum_{j near, j != i} m_j / d^2,
-// partners in ascending id, bodies in sorted order; one thread per body
-__global__ void __launch_bounds__(256) k_near_f(int n, const int* __restrict__ leaf_of,
-                                                const int* __restrict__ cb, const int* __restrict__ ce,
-                                                const int* __restrict__ parent,
-                                                const int* __restrict__ off, const int* __restrict__ src,
-                                                const double* __restrict__ F,
-                                                const double4* __restrict__ pm, double* f) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int B = leaf_of[i];
+// partners in ascending id, bodies in sorted order, one running sum per body.
+// One wavefront per sink leaf, a lane per sink body; each source leaf is
+// staged in LDS (one coalesced load, the next one fetched while the current
+// one is summed) and read by all lanes as broadcasts.
+constexpr int NF_WAVES = 4;
+
+__global__ void __launch_bounds__(64 * NF_WAVES) k_near_f(int nleaves, const int* __restrict__ leaves,
+                                                          const int* __restrict__ cb,
+                                                          const int* __restrict__ ce,
+                                                          const int* __restrict__ parent,
+                                                          const int* __restrict__ off,
+                                                          const int* __restrict__ src,
+                                                          const double* __restrict__ F,
+                                                          const double4* __restrict__ pm, double* f) {
+  __shared__ double4 sbuf[NF_WAVES][64];
+  int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int nblk = (nleaves + NF_WAVES - 1) / NF_WAVES;
+  int per = (nblk + 7) >> 3;
+  int blk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  int li = blk * NF_WAVES + wv;
+  if (blk >= nblk || li >= nleaves) return;
+  int B = leaves[li];
   double far = 0.0;
   {
     int path[FMM_MAX_LEVEL + 2];
@@ -349,30 +376,52 @@ __global__ void __launch_bounds__(256) k_near_f(int n, const int* __restrict__ l
     for (int q = B; q >= 0; q = parent[q]) path[len++] = q;
     for (int t = len - 1; t >= 0; t--) far = far + F[path[t]];
   }
-  double4 me = pm[i];
-  double near = 0.0;
-  // one flattened loop, same order: partners ascending, bodies in sorted order
-  int k = off[B], ke = off[B + 1];
-  int j = 0, je = 0;
-  if (k < ke) {
-    int A = src[k];
-    j = cb[A];
-    je = ce[A];
-  }
-  while (k < ke) {
-    double4 q = pm[j];
-    double dx = q.x - me.x, dy = q.y - me.y, dz = q.z - me.z;
-    double d2 = (dx * dx + dy * dy) + dz * dz;
-    if (j != i && d2 > 0.0) near = near + q.w / d2;
-    if (++j == je) {
-      if (++k < ke) {
-        int A = src[k];
-        j = cb[A];
-        je = ce[A];
-      }
+  int b = cb[B], e = ce[B];
+  int qb = off[B], qe = off[B + 1];
+  for (int i0 = b; i0 < e; i0 += 64) {
+    int i = i0 + lane;
+    bool act = i < e;
+    double4 me = act ? pm[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+    double near = 0.0;
+    int q = qb, j0 = 0, je = 0;
+    if (q < qe) {
+      int A = src[q];
+      j0 = cb[A];
+      je = ce[A];
     }
+    double4 cur = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (q < qe && lane < je - j0) cur = pm[j0 + lane];
+    while (q < qe) {
+      int na = min(64, je - j0);
+      int nq = q, nj0 = j0 + 64, nje = je;
+      if (nj0 >= je) {
+        nq = q + 1;
+        if (nq < qe) {
+          int A = src[nq];
+          nj0 = cb[A];
+          nje = ce[A];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      sbuf[wv][lane] = cur;
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the staged chunk is visible to the wave
+      cur = make_double4(0.0, 0.0, 0.0, 0.0);
+      if (nq < qe && lane < nje - nj0) cur = pm[nj0 + lane];
+      int tmax = act ? na : 0;
+      for (int t = 0; t < tmax; t++) {
+        double4 s = sbuf[wv][t];
+        double dx = s.x - me.x, dy = s.y - me.y, dz = s.z - me.z;
+        double d2 = (dx * dx + dy * dy) + dz * dz;
+        if (j0 + t != i && d2 > 0.0) near = near + s.w / d2;
+      }
+      q = nq;
+      j0 = nj0;
+      je = nje;
+    }
+    if (act) f[i] = far + near;
+    __builtin_amdgcn_wave_barrier();
   }
-  f[i] = far + near;
 }
 
 __global__ void k_fmin(int first, int count, const int* cb, const int* ce, const int* c0,
@@ -402,9 +451,13 @@ void estimate_walk(Ctx& c) {
   run_walk<0, 0>(c, c.est_far, c.est_near);
   hipLaunchKernelGGL(k_fcell, dim3((nc + 255) / 256), dim3(256), 0, s, nc, c.est_far.off.p,
                      c.est_far.src.p, c.c_mass.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.fcell.p);
-  hipLaunchKernelGGL(k_near_f, dim3((unsigned)ceil_div(c.n, 256)), dim3(256), 0, s, (int)c.n,
-                     c.leaf_of.p, c.c_begin.p, c.c_end.p, c.c_parent.p, c.est_near.off.p,
-                     c.est_near.src.p, c.fcell.p, c.pm.p, c.fpart.p);
+  {
+    int nblk = (int)ceil_div(c.nleaf, NF_WAVES);
+    unsigned grid = 8u * (unsigned)ceil_div(nblk, 8);
+    hipLaunchKernelGGL(k_near_f, dim3(grid), dim3(64 * NF_WAVES), 0, s, (int)c.nleaf, c.leaves.p,
+                       c.c_begin.p, c.c_end.p, c.c_parent.p, c.est_near.off.p, c.est_near.src.p,
+                       c.fcell.p, c.pm.p, c.fpart.p);
+  }
   for (int level = c.depth; level >= 0; level--) {
     int first = c.lvl_first[level], count = c.lvl_count[level];
     hipLaunchKernelGGL(k_fmin, dim3((count + 127) / 128), dim3(128), 0, s, first, count, c.c_begin.p,

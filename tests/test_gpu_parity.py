@@ -220,6 +220,11 @@ def test_mixed_precision_bounded_difference(fmm, root_levels):
     oacc, opot = o.run(pos, mass, p=cfg["p"], err_tol=cfg["err_tol"], n_leaf=64)
     assert np.array_equal(_sorted_pairs(f.export("m2l")), _sorted_pairs(o.get("m2l")))
     assert np.array_equal(_sorted_pairs(f.export("p2p")), _sorted_pairs(o.get("p2p")))
+    # pairs taken in FP32: both cells below the root levels
+    lvl = o.get("cell_level")
+    m2l = o.get("m2l")
+    low = (lvl[m2l[:, 0]] >= root_levels) & (lvl[m2l[:, 1]] >= root_levels)
+    assert f.stats()["n_m2l_fp32"] == int(low.sum())
     rel = np.linalg.norm(acc - oacc, axis=1) / np.linalg.norm(oacc, axis=1)
     relp = np.abs(pot - opot) / np.abs(opot)
     print(f"mixed vs FP64 oracle: median {np.median(rel):.2e} p99 {np.percentile(rel, 99):.2e}")
