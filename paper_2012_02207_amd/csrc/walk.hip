@@ -117,83 +117,99 @@ __device__ __forceinline__ long long block_alloc(int cnt, int* ctr, int& excl, i
   return base;
 }
 
-// ctr[0]: next frontier, ctr[32]: accepted pairs, ctr[64]: near-field leaf
-// pairs (separate cache lines)
+// Device counters of a walk (ints, each on its own cache line): three
+// rotating frontier sizes, the totals of accepted and near-field entries, and
+// the largest frontier seen.  Step k reads its frontier size from slot k % 3,
+// appends to slot (k+1) % 3 and clears slot (k+2) % 3 for the step after, so
+// consecutive steps need no host round trip.
+constexpr int WC_FRONT = 0, WC_ACC = 96, WC_NEAR = 128, WC_MAXF = 160, WC_INTS = 192;
+constexpr int WALK_BLOCKS = 1024;  // persistent grid; blocks stride over the frontier
+
 template <int KIND, int P>
-__global__ void __launch_bounds__(WALK_T) k_walk(CellView v, const int2* fin, int nin, int2* fout,
-                                              int fcap, int* ctr, uint64_t* acc_list, int acap,
-                                              uint64_t* near_list, int ncap, int bits) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  bool live = t < nin;
-  int A = 0, B = 0, nkids = 0, nacc = 0, nnear = 0, mode = 0;
-  // mode: 0 none, 1 self children, 2 split A, 3 split B
-  if (live) {
-    int2 pr = fin[t];
-    A = pr.x;
-    B = pr.y;
-    int kA = v.nch[A], kB = v.nch[B];
-    if (A == B) {
-      if (kA == 0) {
-        nnear = 1;
-      } else {
-        mode = 1;
-        nkids = kA * (kA + 1) / 2;
-      }
-    } else if (accept<KIND, P>(v, A, B)) {
-      nacc = 2;
-    } else if (kA == 0 && kB == 0) {
-      nnear = 2;
-    } else {
-      bool splitB = (kA == 0) || (v.rad[B] > v.rad[A] && kB != 0);
-      mode = splitB ? 3 : 2;
-      nkids = splitB ? kB : kA;
-    }
+__global__ void __launch_bounds__(WALK_T) k_walk(CellView v, int step, const int2* fin, int fin_cap,
+                                              int2* fout, int fcap, int* ctr, uint64_t* acc_list,
+                                              int acap, uint64_t* near_list, int ncap, int bits) {
+  int nin_all = ctr[WC_FRONT + 32 * (step % 3)];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctr[WC_FRONT + 32 * ((step + 2) % 3)] = 0;
+    atomicMax(&ctr[WC_MAXF], nin_all);
   }
+  int nin = min(nin_all, fin_cap);  // an overflowed frontier is redone by the host
+  int* fctr = &ctr[WC_FRONT + 32 * ((step + 1) % 3)];
   __shared__ int sh[WALK_T / 64 + 1];
-  int ek, ea, en;
-  long long bk = block_alloc(nkids, &ctr[0], ek, sh);
-  long long ba = block_alloc(nacc, &ctr[32], ea, sh);
-  long long bn = block_alloc(nnear, &ctr[64], en, sh);
-  if (!live) return;
-  long long o = bk + ek;
-  if (mode == 1) {
-    int c0 = v.c0[A], k = v.nch[A];
-    for (int i = 0; i < k; i++)
-      for (int j = i; j < k; j++, o++)
-        if (o < fcap) fout[o] = make_int2(c0 + i, c0 + j);
-  } else if (mode == 2) {
-    int c0 = v.c0[A];
-    for (int i = 0; i < nkids; i++, o++)
-      if (o < fcap) fout[o] = make_int2(c0 + i, B);
-  } else if (mode == 3) {
-    int c0 = v.c0[B];
-    for (int j = 0; j < nkids; j++, o++)
-      if (o < fcap) fout[o] = make_int2(A, c0 + j);
-  }
-  // list entries: (sink << bits) | source
-  uint64_t kab = ((uint64_t)B << bits) | (uint64_t)A, kba = ((uint64_t)A << bits) | (uint64_t)B;
-  if (nacc) {
-    long long q = ba + ea;
-    if (q + 1 < acap) {
-      acc_list[q] = kab;
-      acc_list[q + 1] = kba;
+  for (int base = blockIdx.x * WALK_T; base < nin; base += gridDim.x * WALK_T) {
+    int t = base + threadIdx.x;
+    bool live = t < nin;
+    int A = 0, B = 0, nkids = 0, nacc = 0, nnear = 0, mode = 0;
+    // mode: 0 none, 1 self children, 2 split A, 3 split B
+    if (live) {
+      int2 pr = fin[t];
+      A = pr.x;
+      B = pr.y;
+      int kA = v.nch[A], kB = v.nch[B];
+      if (A == B) {
+        if (kA == 0) {
+          nnear = 1;
+        } else {
+          mode = 1;
+          nkids = kA * (kA + 1) / 2;
+        }
+      } else if (accept<KIND, P>(v, A, B)) {
+        nacc = 2;
+      } else if (kA == 0 && kB == 0) {
+        nnear = 2;
+      } else {
+        bool splitB = (kA == 0) || (v.rad[B] > v.rad[A] && kB != 0);
+        mode = splitB ? 3 : 2;
+        nkids = splitB ? kB : kA;
+      }
     }
-  }
-  if (nnear) {
-    long long q = bn + en;
-    if (nnear == 1) {
-      if (q < ncap) near_list[q] = kab;
-    } else if (q + 1 < ncap) {
-      near_list[q] = kab;
-      near_list[q + 1] = kba;
+    int ek, ea, en;
+    long long bk = block_alloc(nkids, fctr, ek, sh);
+    long long ba = block_alloc(nacc, &ctr[WC_ACC], ea, sh);
+    long long bn = block_alloc(nnear, &ctr[WC_NEAR], en, sh);
+    if (!live) continue;
+    long long o = bk + ek;
+    if (mode == 1) {
+      int c0 = v.c0[A], k = v.nch[A];
+      for (int i = 0; i < k; i++)
+        for (int j = i; j < k; j++, o++)
+          if (o < fcap) fout[o] = make_int2(c0 + i, c0 + j);
+    } else if (mode == 2) {
+      int c0 = v.c0[A];
+      for (int i = 0; i < nkids; i++, o++)
+        if (o < fcap) fout[o] = make_int2(c0 + i, B);
+    } else if (mode == 3) {
+      int c0 = v.c0[B];
+      for (int j = 0; j < nkids; j++, o++)
+        if (o < fcap) fout[o] = make_int2(A, c0 + j);
+    }
+    // list entries: (sink << bits) | source
+    uint64_t kab = ((uint64_t)B << bits) | (uint64_t)A, kba = ((uint64_t)A << bits) | (uint64_t)B;
+    if (nacc) {
+      long long q = ba + ea;
+      if (q + 1 < acap) {
+        acc_list[q] = kab;
+        acc_list[q + 1] = kba;
+      }
+    }
+    if (nnear) {
+      long long q = bn + en;
+      if (nnear == 1) {
+        if (q < ncap) near_list[q] = kab;
+      } else if (q + 1 < ncap) {
+        near_list[q] = kab;
+        near_list[q + 1] = kba;
+      }
     }
   }
 }
 
-// the walks start from (root, root) of every system
-__global__ void k_seed(int2* f, int nsys) {
+// the walks start from (root, root) of every system; counters cleared
+__global__ void k_seed(int2* f, int nsys, int* ctr) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s < nsys) f[s] = make_int2(s, s);
+  if (s < WC_INTS) ctr[s] = s == WC_FRONT ? nsys : 0;
 }
 
 // ---- grouping by sink, sorted by source ----------------------------------
@@ -281,48 +297,50 @@ static void run_walk(Ctx& c, CellList& acc, CellList& nearl) {
   ensure(c.ws, c.front[1], fcap0);
   ensure(c.ws, acc.raw, std::max<size_t>(acc.raw.cap, (size_t)c.ncell * 8 + 64));
   ensure(c.ws, nearl.raw, std::max<size_t>(nearl.raw.cap, (size_t)c.ncell * 8 + 64));
-  ensure(c.ws, c.counters, 64);
-  ensure(c.ws, c.counters, 256);
-  int* ctr = c.counters.p + 128;
+  ensure(c.ws, c.counters, 512);
+  int* ctr = c.counters.p + 256;
   int bits = list_bits(c.ncell);
   int* h = (int*)c.hbuf;
-  hipLaunchKernelGGL(k_seed, dim3((unsigned)ceil_div(c.nsys, 256)), dim3(256), 0, s, c.front[0].p, c.nsys);
-  int nin = c.nsys, cur = 0;
+  // A pair's step count is at most the sum of its cells' levels plus one, so
+  // 2 depth + 2 steps drain the frontier; the host checks once at the end.
+  int steps = 2 * c.depth + 2;
   int nacc = 0, nnear = 0;
-  while (nin > 0) {
-    for (;;) {
-      int init[65] = {0};
-      init[32] = nacc;
-      init[64] = nnear;
-      HIPCHK(hipMemcpyAsync(ctr, init, sizeof(init), hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL((k_walk<KIND, P>), dim3((unsigned)ceil_div(nin, WALK_T)), dim3(WALK_T), 0, s, v,
-                         c.front[cur].p, nin, c.front[1 - cur].p, (int)c.front[1 - cur].cap, ctr,
-                         acc.raw.p, (int)acc.raw.cap, nearl.raw.p, (int)nearl.raw.cap, bits);
+  for (int attempt = 0;; attempt++) {
+    int sblocks = (int)ceil_div(std::max(c.nsys, WC_INTS), 256);
+    hipLaunchKernelGGL(k_seed, dim3((unsigned)sblocks), dim3(256), 0, s, c.front[0].p, c.nsys, ctr);
+    int step = 0;
+    bool done = false;
+    while (!done) {
+      for (int e = 0; e < steps; e++, step++)
+        hipLaunchKernelGGL((k_walk<KIND, P>), dim3(WALK_BLOCKS), dim3(WALK_T), 0, s, v, step,
+                           c.front[step & 1].p, (int)c.front[step & 1].cap, c.front[1 - (step & 1)].p,
+                           (int)c.front[1 - (step & 1)].cap, ctr, acc.raw.p, (int)acc.raw.cap,
+                           nearl.raw.p, (int)nearl.raw.cap, bits);
       HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(h, ctr, 65 * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(h, ctr, WC_INTS * sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      h[1] = h[32];
-      h[2] = h[64];
-      bool again = false;
-      if ((size_t)h[0] > c.front[1 - cur].cap) {
-        ensure(c.ws, c.front[1 - cur], (size_t)h[0] * 2);
-        again = true;
-      }
-      if ((size_t)h[1] + 2 > acc.raw.cap) {
-        ensure(c.ws, acc.raw, (size_t)h[1] * 2 + 64, true, s);
-        again = true;
-      }
-      if ((size_t)h[2] + 2 > nearl.raw.cap) {
-        ensure(c.ws, nearl.raw, (size_t)h[2] * 2 + 64, true, s);
-        again = true;
-      }
-      if (!again) break;
+      done = h[WC_FRONT + 32 * (step % 3)] == 0;  // frontier of the next step is empty
+      if (h[WC_MAXF] > (int)std::min(c.front[0].cap, c.front[1].cap)) break;  // overflowed: redo
     }
-    nacc = h[1];
-    nnear = h[2];
-    nin = h[0];
-    cur = 1 - cur;
-    if ((size_t)nin * 36 > c.front[1 - cur].cap) ensure(c.ws, c.front[1 - cur], (size_t)nin * 8 + 4096);
+    nacc = h[WC_ACC];
+    nnear = h[WC_NEAR];
+    bool again = false;
+    size_t need_f = (size_t)h[WC_MAXF];
+    if (need_f > std::min(c.front[0].cap, c.front[1].cap)) {
+      ensure(c.ws, c.front[0], need_f * 2);
+      ensure(c.ws, c.front[1], need_f * 2);
+      again = true;
+    }
+    if ((size_t)nacc + 2 > acc.raw.cap) {
+      ensure(c.ws, acc.raw, (size_t)nacc * 2 + 64);
+      again = true;
+    }
+    if ((size_t)nnear + 2 > nearl.raw.cap) {
+      ensure(c.ws, nearl.raw, (size_t)nnear * 2 + 64);
+      again = true;
+    }
+    if (!again) break;
+    if (attempt > 8) throw hip_error{hipErrorUnknown, "walk buffers did not converge"};
   }
   acc.count = nacc;
   nearl.count = nnear;
