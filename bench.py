@@ -112,17 +112,157 @@ def cpu_baseline(pos, mass, p, err_tol, n_leaf, frac, seed=5):
                       f"x{scale:.1f}; estimated {t_full:.1f} s per evaluation"}
 
 
+def run_ensemble(args):
+    """The batched ensemble: 256 Plummer clusters of log-uniform size in
+    [2^10, 2^16], p = 8, epsilon = 1e-6.  One step = one force evaluation of
+    every cluster.  The value is cluster evaluations/s of the batched mixed
+    form (fmm_forces_batch); beside it the batched FP64 form and the
+    sequential per-cluster FP64 and mixed forms (one fmm_forces call per
+    cluster), each with its median force error against the direct sum on
+    sampled sinks."""
+    import torch
+    from paper_2012_02207_amd import fmm, workloads as W
+    cfg = W.CONFIGS["ensemble_256"]
+    p, err_tol = cfg["p"], cfg["err_tol"]
+    clusters = W.ensemble(cfg["count"], cfg["seed"])
+    sizes = np.array([len(c[2]) for c in clusters], dtype=np.int64)
+    off = np.zeros(len(clusters) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    n = int(off[-1])
+    dev = torch.device("cuda:0")
+    dpos = torch.from_numpy(np.concatenate([c[0] for c in clusters])).to(dev)
+    dmass = torch.from_numpy(np.concatenate([c[2] for c in clusters])).to(dev)
+    views = [(dpos[off[i]:off[i + 1]], dmass[off[i]:off[i + 1]]) for i in range(len(clusters))]
+    # error sample: 32 clusters x up to 64 sinks each, direct sum on the GPU
+    rng = np.random.default_rng(cfg["seed"] + 99)
+    picked = np.sort(rng.choice(len(clusters), 32, replace=False))
+    ref = []
+    for ci in picked:
+        m = int(sizes[ci])
+        sk = np.sort(rng.choice(m, min(64, m), replace=False)).astype(np.int32)
+        ad, _ = fmm.direct(views[ci][0], views[ci][1], sinks=torch.from_numpy(sk).to(dev))
+        ref.append((ci, sk, ad))
+
+    def errors(acc):
+        e = []
+        for ci, sk, ad in ref:
+            a = acc[int(off[ci]) + torch.from_numpy(sk).long().to(dev)]
+            e.append((torch.linalg.norm(a - ad, dim=1) / torch.linalg.norm(ad, dim=1)).cpu().numpy())
+        e = np.concatenate(e)
+        return float(np.median(e)), float(np.percentile(e, 99))
+
+    def run(precision, batched):
+        f = fmm.FMM(p=p, err_tol=err_tol, n_leaf=args.n_leaf, precision=precision,
+                    root_levels=args.root_levels)
+        tuned = None
+        if batched and not args.no_autotune:  # the batched forms run at the autotuner's n_leaf
+            tuned = f.autotune(dpos, dmass, off)
+        acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        pot = torch.empty((n,), dtype=torch.float64, device=dev)
+        outs = [(acc[off[i]:off[i + 1]], pot[off[i]:off[i + 1]]) for i in range(len(clusters))]
+
+        def step():
+            if batched:
+                f.forces_batch(dpos, dmass, off, out=(acc, pot))
+            else:
+                for (pp, mm), o in zip(views, outs):
+                    f.forces(pp, mm, out=o)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        st = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+            if batched:
+                st.append(f.stats())
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        med, p99 = errors(acc)
+        f.close()
+        return {"ms": 1e3 * dt, "cluster_evals_per_s": len(clusters) / dt, "particle_evals_per_s": n / dt,
+                "median_err_vs_direct": med, "p99_err_vs_direct": p99,
+                "n_leaf": tuned if tuned is not None else args.n_leaf, "stats": st}
+
+    res = {"batched_mixed": run("mixed", True), "batched_fp64": run("fp64", True),
+           "sequential_fp64": run("fp64", False), "sequential_mixed": run("mixed", False)}
+    R = res["batched_mixed"]
+    st = R["stats"][-1]
+    m2l_ms = float(np.mean([s["ms_m2l_kernel"] for s in R["stats"]]))
+    p2p_ms = float(np.mean([s["ms_p2p"] for s in R["stats"]]))
+    f_m2l = m2l_flops(p) * st["n_m2l_fp32"]
+    f_leaf = P2P_FLOPS * st["n_p2p_pairs"] + l2p_flops(p) * n
+    if p2p_ms >= m2l_ms:
+        dom = {"kernel": "k_leaf_group<true> (L2P + mixed P2P)", "flop": f_leaf, "ms": p2p_ms}
+    else:
+        dom = {"kernel": "k_m2l_fp32", "flop": f_m2l, "ms": m2l_ms}
+    achieved = dom["flop"] / (dom["ms"] * 1e-3)
+    forms = {k: {kk: vv for kk, vv in v.items() if kk != "stats"} for k, v in res.items()}
+    forms["speedup_batched_mixed_over_sequential_fp64"] = res["sequential_fp64"]["ms"] / R["ms"]
+    forms["speedup_batched_fp64_over_sequential_fp64"] = (res["sequential_fp64"]["ms"]
+                                                          / res["batched_fp64"]["ms"])
+    out = {
+        "metric": "cluster force evals/sec, 256 Plummer clusters (N log-uniform in [2^10, 2^16]), p=8, "
+                  "1e-6; batched mixed vs sequential FP64 GPU",
+        "value": R["cluster_evals_per_s"], "unit": "cluster evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": R["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"ensemble_256: {len(clusters)} clusters, N={n}, p={p}, eps={err_tol}, "
+                               f"n_leaf={R['n_leaf']}, batched mixed", "clusters": len(clusters),
+                   "n": n, "p": p, "err_tol": err_tol, "n_leaf": R["n_leaf"],
+                   "root_levels": args.root_levels},
+        "particle_evals_per_s": R["particle_evals_per_s"],
+        "forms": forms,
+        "stages_ms": {k: round(float(np.mean([s[k] for s in R["stats"]])), 4)
+                      for k in ("ms_tree", "ms_upward", "ms_estimate", "ms_walk", "ms_m2l",
+                                "ms_local", "ms_p2p", "ms_total")},
+        "roofline": {"bound": "alu", "kernel": dom["kernel"], "achieved": achieved / 1e12,
+                     "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
+                     "traffic": None, "flop_per_launch": dom["flop"], "ms_per_launch": dom["ms"]},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = ensemble_cpu_baseline(clusters, p, err_tol, args.n_leaf)
+    print(json.dumps(out))
+
+
+def ensemble_cpu_baseline(clusters, p, err_tol, n_leaf, count=8, seed=7):
+    """The CPU oracle on a sample of whole clusters, scaled to all of them by
+    their share of the bodies."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    picked = rng.choice(len(clusters), count, replace=False)
+    t = 0.0
+    nb = 0
+    for ci in picked:
+        pos, _, mass = clusters[ci]
+        o = oracle.Oracle()
+        t0 = time.perf_counter()
+        o.run(pos, mass, p=p, err_tol=err_tol, n_leaf=n_leaf)
+        t += time.perf_counter() - t0
+        nb += len(mass)
+    total = sum(len(c[2]) for c in clusters)
+    t_all = t * total / nb
+    return {"value": len(clusters) / t_all, "unit": "cluster evals/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{count} random clusters ({nb} bodies) evaluated in full ({t:.1f} s), scaled by "
+                      f"the body share to all {len(clusters)} clusters ({total} bodies): "
+                      f"{t_all:.1f} s per ensemble evaluation"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="plummer_1m", choices=["plummer_1m", "plummer_4k", "kroupa_4m"])
+    ap.add_argument("--workload", default="plummer_1m",
+                    choices=["plummer_1m", "plummer_4k", "kroupa_4m", "ensemble_256"])
     ap.add_argument("--precisions", default="fp64,mixed",
                     help="comma list; the last one is the reported value")
     ap.add_argument("--root-levels", type=int, default=3)
     ap.add_argument("--n-leaf", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="ensemble: keep --n-leaf for batched forms")
     ap.add_argument("--cpu-frac", type=float, default=1.0 / 64)
     ap.add_argument("--err-sinks", type=int, default=4096)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -146,6 +286,8 @@ def main():
     import torch
     from paper_2012_02207_amd import fmm, workloads as W
 
+    if args.workload == "ensemble_256":
+        return run_ensemble(args)
     cfg = W.CONFIGS[args.workload]
     n, p, err_tol = cfg["n"], cfg["p"], cfg["err_tol"]
     if args.workload == "kroupa_4m":
@@ -227,7 +369,9 @@ def main():
         forms["speedup_mixed_over_fp64"] = res["fp64"]["ms"] / res["mixed"]["ms"]
 
     out = {
-        "metric": "force evals/sec at N=2^20, 1e-7 median rel. force err; mixed vs FP64 GPU",
+        "metric": ("force evals/sec at N=2^20, 1e-7 median rel. force err; mixed vs FP64 GPU"
+                   if args.workload == "plummer_1m" else
+                   f"force evals/sec at N={n}, {err_tol:g} median rel. force err; {main_pr}"),
         "value": 1e3 / ms_step,
         "unit": "force evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

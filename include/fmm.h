@@ -161,6 +161,20 @@ fmm_status fmm_forces_batch(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets, 
                             const double* mass, double eps_soft, int p, double err_tol,
                             double* acc, double* pot, void* stream);
 
+/* Autotuner: picks the leaf capacity n_leaf (the balance between the near
+ * field and the expansions) for this workload by timing full evaluations of
+ * the systems given as for fmm_forces_batch (nsys = 1, offsets = {0, n} for a
+ * single system) at n_leaf in {16, 24, 32, 48, 64, 96, 128}: one warm-up and
+ * two timed calls each, HIP events on the stream.  The fastest is written to
+ * *chosen_n_leaf (host) and set in the context's parameters.  Choices are
+ * cached in the process per (device, precision, p, err_tol, log2 of the body
+ * count, log2 of the mean system size); a cached workload class returns at
+ * once without running anything.  acc and pot receive the last evaluation.
+ * Errors as fmm_forces_batch; on error the parameters are unchanged. */
+fmm_status fmm_autotune(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets, const double* pos,
+                        const double* mass, double eps_soft, int p, double err_tol, double* acc,
+                        double* pot, void* stream, int* chosen_n_leaf);
+
 /* Counts and per-stage times of the last call (synchronises its stream). */
 fmm_status fmm_stats(fmm_ctx* ctx, fmm_stats_t* out /* host */);
 

@@ -5,7 +5,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 
 #include "fmm_device.h"
 
@@ -400,6 +403,88 @@ fmm_status fmm_export(fmm_ctx* ctx, int what, void* host_buf, size_t bytes) {
     HIPCHK(hipMemcpy(host_buf, src, need, hipMemcpyDeviceToHost));
     return FMM_OK;
   });
+}
+
+// ---- autotuner: n_leaf per (device, precision, p, tolerance, size class) ----
+namespace {
+using TuneKey = std::tuple<int, int, int, double, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune_cache;
+
+int size_class(int64_t v) {
+  int c = 0;
+  while (v > 1) {
+    v >>= 1;
+    c++;
+  }
+  return c;
+}
+}  // namespace
+
+fmm_status fmm_autotune(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets, const double* pos,
+                        const double* mass, double eps_soft, int p, double err_tol, double* acc,
+                        double* pot, void* stream, int* chosen_n_leaf) {
+  if (!ctx || !chosen_n_leaf || !offsets) return FMM_EINVAL;
+  if (nsys < 1 || nsys > FMM_MAX_SYSTEMS || offsets[0] != 0) return FMM_EINVAL;
+  for (int64_t s = 0; s < nsys; s++)
+    if (offsets[s + 1] <= offsets[s]) return FMM_EINVAL;
+  Ctx& c = ctx->c;
+  int64_t n = offsets[nsys];
+  TuneKey key{c.device, c.prm.precision, p, err_tol, size_class(n), size_class(n / nsys)};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      c.prm.n_leaf = it->second;
+      *chosen_n_leaf = it->second;
+      return FMM_OK;
+    }
+  }
+  static const int cand[] = {16, 24, 32, 48, 64, 96, 128};
+  fmm_params saved = c.prm;
+  int best = saved.n_leaf;
+  float best_ms = 1e30f;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  fmm_status st = guarded(ctx, [&]() {
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    return FMM_OK;
+  });
+  if (st != FMM_OK) return st;
+  for (int nl : cand) {
+    c.prm.n_leaf = nl;
+    st = forces_impl(ctx, nsys, offsets, n, pos, mass, eps_soft, p, err_tol, acc, pot, stream);  // warm-up
+    if (st != FMM_OK) break;
+    float ms = 0;
+    st = guarded(ctx, [&]() {
+      HIPCHK(hipEventRecord(e0, (hipStream_t)stream));
+      return FMM_OK;
+    });
+    if (st != FMM_OK) break;
+    for (int r = 0; r < 2 && st == FMM_OK; r++)
+      st = forces_impl(ctx, nsys, offsets, n, pos, mass, eps_soft, p, err_tol, acc, pot, stream);
+    if (st != FMM_OK) break;
+    st = guarded(ctx, [&]() {
+      HIPCHK(hipEventRecord(e1, (hipStream_t)stream));
+      HIPCHK(hipEventSynchronize(e1));
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      return FMM_OK;
+    });
+    if (st != FMM_OK) break;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = nl;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c.prm = saved;
+  if (st != FMM_OK) return st;
+  c.prm.n_leaf = best;
+  *chosen_n_leaf = best;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = best;
+  return FMM_OK;
 }
 
 fmm_status fmm_set_workspace_limit(fmm_ctx* ctx, size_t bytes) {

@@ -25,8 +25,8 @@ EXPORTS = dict(keys=(0, np.uint64), perm=(1, np.int32), cell_level=(2, np.int32)
                m2l=(18, np.int32), p2p=(19, np.int32), local=(20, np.float64),
                rootbox=(21, np.float64))
 SYMBOLS = ["fmm_default_params", "fmm_create", "fmm_set_params", "fmm_build", "fmm_forces",
-           "fmm_forces_batch", "fmm_stats", "fmm_export", "fmm_set_workspace_limit", "fmm_direct", "fmm_strerror",
-           "fmm_last_error", "fmm_destroy"]
+           "fmm_forces_batch", "fmm_autotune", "fmm_stats", "fmm_export", "fmm_set_workspace_limit",
+           "fmm_direct", "fmm_strerror", "fmm_last_error", "fmm_destroy"]
 
 
 class FmmError(RuntimeError):
@@ -73,6 +73,8 @@ def load_library():
     lib.fmm_forces.argtypes = [P, C.c_int64, P, P, C.c_double, C.c_int, C.c_double, P, P, P]
     lib.fmm_forces_batch.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), P, P, C.c_double, C.c_int,
                                      C.c_double, P, P, P]
+    lib.fmm_autotune.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), P, P, C.c_double, C.c_int,
+                                 C.c_double, P, P, P, C.POINTER(C.c_int)]
     lib.fmm_stats.argtypes = [P, C.POINTER(Stats)]
     lib.fmm_export.argtypes = [P, C.c_int, P, C.c_size_t]
     lib.fmm_set_workspace_limit.argtypes = [P, C.c_size_t]
@@ -83,8 +85,7 @@ def load_library():
     lib.fmm_last_error.restype = C.c_char_p
     lib.fmm_destroy.argtypes = [P]
     for f in ("fmm_create", "fmm_set_params", "fmm_build", "fmm_forces", "fmm_forces_batch",
-              "fmm_stats", "fmm_export",
-              "fmm_set_workspace_limit", "fmm_direct"):
+              "fmm_autotune", "fmm_stats", "fmm_export", "fmm_set_workspace_limit", "fmm_direct"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -217,6 +218,25 @@ class FMM:
         self.n = n
         self.last_p = int(self.params.p if p is None else p)
         return acc, pot
+
+    def autotune(self, pos, mass, offsets=None, eps_soft=0.0, p=None, err_tol=None):
+        """Picks n_leaf for this workload (timed on the GPU, cached per workload
+        class in the process); returns the choice, also set in the context."""
+        torch = _torch()
+        n = mass.shape[0]
+        off = np.ascontiguousarray(np.asarray([0, n] if offsets is None else offsets, dtype=np.int64))
+        acc = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        pot = torch.empty((n,), dtype=torch.float64, device=pos.device)
+        chosen = C.c_int(0)
+        self._check(self._lib.fmm_autotune(
+            self._h, off.size - 1, off.ctypes.data_as(C.POINTER(C.c_int64)),
+            _dev_ptr(pos, torch.float64, (n, 3), "pos"), _dev_ptr(mass, torch.float64, (n,), "mass"),
+            float(eps_soft), int(self.params.p if p is None else p),
+            float(self.params.err_tol if err_tol is None else err_tol),
+            _dev_ptr(acc, torch.float64, (n, 3), "acc"), _dev_ptr(pot, torch.float64, (n,), "pot"),
+            _stream(), C.byref(chosen)))
+        self.params.n_leaf = chosen.value
+        return chosen.value
 
     def stats(self):
         s = Stats()

@@ -165,3 +165,28 @@ def test_ensemble_config_batch(fmm):
             assert np.median(err) < cfg["err_tol"], (s, precision, np.median(err))
     d = np.linalg.norm(res["mixed"] - res["fp64"], axis=1) / np.linalg.norm(res["fp64"], axis=1)
     assert np.median(d) <= 1e-6 and d.max() <= 1e-3, (np.median(d), d.max())
+
+
+def test_autotune_picks_a_candidate_and_caches(fmm):
+    """The autotuner times the candidate leaf capacities, sets the fastest in
+    the context, returns the cached choice for the same workload class, and
+    the tuned context still matches the oracle run at that n_leaf."""
+    import time
+    systems = _systems()
+    pos, mass, off = _concat(systems)
+    print("[gpu] autotune on the mixed batch", flush=True)
+    f = fmm.FMM(p=6, err_tol=1e-6, n_leaf=64)
+    nl = f.autotune(_dev(pos), _dev(mass), off)
+    assert nl in (16, 24, 32, 48, 64, 96, 128)
+    t0 = time.perf_counter()
+    assert f.autotune(_dev(pos), _dev(mass), off) == nl
+    assert time.perf_counter() - t0 < 0.5
+    acc, _ = f.forces_batch(_dev(pos), _dev(mass), off)
+    acc = acc.cpu().numpy()
+    s = 5  # the 3000-body Plummer system
+    b, e = off[s], off[s + 1]
+    o = oracle.Oracle()
+    oacc, _ = o.run(systems[s][0], systems[s][1], p=6, err_tol=1e-6, n_leaf=nl)
+    rel = np.linalg.norm(acc[b:e] - oacc, axis=1) / np.linalg.norm(oacc, axis=1)
+    assert np.median(rel) <= 1e-12 and rel.max() <= 1e-9
+    f.close()
