@@ -141,6 +141,34 @@ fmm_status fmm_forces(fmm_ctx* ctx, int64_t n, const double* pos, const double* 
                       double eps_soft, int p, double err_tol, double* acc, double* pot,
                       void* stream);
 
+/* Force evaluation with the tree and interaction lists of the context's last
+ * fmm_forces call kept (frozen): the bodies are taken in the stored order,
+ * and cell centres, radii, P2M, M2M, M2L, L2L, L2P and P2P are recomputed from
+ * pos and mass, the acceptance test is not.  The result is a smooth function
+ * of pos and mass, which is what finite-difference checks of gradients need
+ * (a change of the accepted pairs would make it jump).  n must equal the last
+ * call's body count (FMM_ENOTBUILT if no evaluation was made, or another n);
+ * p, err_tol and the system split are the last call's. */
+fmm_status fmm_forces_frozen(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass,
+                             double eps_soft, double* acc, double* pot, void* stream);
+
+/* Gradient of the force pass: for a scalar L(acc, pot) given gacc = dL/dacc
+ * (n x 3) and gpot = dL/dpot (n, or NULL for zero), writes gpos = dL/dpos
+ * (n x 3) and gmass = dL/dmass (n), all device buffers in the caller's body
+ * order.  The forward pass at pos is recomputed first (tree, estimate, walk,
+ * expansions; FP64 whatever the context's precision), and its interaction
+ * lists serve the gradient too: the sink side applies the tidal tensor (the
+ * Hessian of the potential from the order-2 local coefficients, plus the
+ * softened near-field pair terms) to gacc; the source side runs a second
+ * expansion pass (P2M, M2M, M2L, L2L on the same tree) over charges gpot and
+ * dipoles -gacc.  The far field is the FMM approximation of the exact
+ * gradient, accurate at the level of the forces (err_tol), not the exact
+ * derivative of the approximate forces.  Errors as fmm_forces; p must have a
+ * compiled kernel (FMM_EUNSUPPORTED otherwise). */
+fmm_status fmm_adjoint(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass, double eps_soft,
+                       int p, double err_tol, const double* gacc, const double* gpot, double* gpos,
+                       double* gmass, void* stream);
+
 /* Largest number of systems one fmm_forces_batch call accepts. */
 #define FMM_MAX_SYSTEMS 65536
 

@@ -1,0 +1,312 @@
+// Adjoint of the force pass on gfx950: for a scalar L(acc, pot) with
+// ga_k = dL/da_k and gp_k = dL/dpot_k, the gradients dL/dx_k and dL/dm_k.
+//
+// Differentiating the defining sums a_k = sum_j m_j u / s^3, pot_k =
+// -sum_j m_j / s (u = x_j - x_k, s^2 = |u|^2 + eps^2) splits the gradient in
+// two parts:
+//   * sink side: the tidal tensor T_k = da_k/dx_k = -Hess Phi(x_k) applied to
+//     ga_k, and -gp_k a_k;
+//   * source side: body k moves the field every other body feels.  With
+//     Psi(x) = sum_i [ga_i . (x - x_i) / s^3 - gp_i / s]  (the potential of
+//     dipoles -ga_i and charges gp_i in the sign convention of the forward
+//     pass), dL/dm_k = Psi(x_k) and the source part of dL/dx_k is m_k grad Psi(x_k).
+// The far field of both uses the FMM of the forward pass on the same tree and
+// interaction lists: Hess Phi from the forward local expansions shifted to the
+// body (orders 2), and Psi by a second expansion pass whose multipoles hold
+// the charges and dipoles (P2M of a dipole d is d . grad Y_n^m, from the ladder
+// relations d/dz Y_n^m = Y_{n-1}^m, (d/dx + i d/dy) Y_n^m = Y_{n-1}^{m+1},
+// (d/dx - i d/dy) Y_n^m = -Y_{n-1}^{m-1}), followed by the same M2M, M2L
+// (FP64) and L2L.  The near field sums the softened pair terms directly.
+#include <hip/hip_runtime.h>
+
+#include "fmm_device.h"
+
+namespace fmm {
+
+// regular harmonics with fused multiply-adds into re/im at stride st
+__device__ inline void regular_fma(int p, double x, double y, double z, double* re, double* im, int st) {
+  double r2 = fma(x, x, fma(y, y, z * z));
+  re[0] = 1.0;
+  im[0] = 0.0;
+  double pr = 1.0, pi = 0.0;
+  for (int n = 1; n <= p; n++) {
+    double inv = -1.0 / (double)(2 * n);
+    double tr = fma(x, pr, -y * pi), ti = fma(x, pi, y * pr);
+    pr = tr * inv;
+    pi = ti * inv;
+    re[cidx(n, n) * st] = pr;
+    im[cidx(n, n) * st] = pi;
+  }
+  for (int m = 0; m < p; m++) {
+    double ar2 = 0.0, ai2 = 0.0, ar1 = re[cidx(m, m) * st], ai1 = im[cidx(m, m) * st];
+    for (int n = m + 1; n <= p; n++) {
+      double k = (double)(2 * n - 1) * z, inv = 1.0 / (double)((n + m) * (n - m));
+      double vr = fma(k, ar1, -r2 * ar2) * inv, vi = fma(k, ai1, -r2 * ai2) * inv;
+      re[cidx(n, m) * st] = vr;
+      im[cidx(n, m) * st] = vi;
+      ar2 = ar1;
+      ai2 = ai1;
+      ar1 = vr;
+      ai1 = vi;
+    }
+  }
+}
+
+// sorted copies: (ga, gp) and the forward acceleration
+__global__ void k_adj_gather(int64_t n, const int* perm, const double* gacc, const double* gpot,
+                             const double* acc, double4* gs, double4* as) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t o = perm[i];
+  gs[i] = make_double4(gacc[3 * o], gacc[3 * o + 1], gacc[3 * o + 2], gpot ? gpot[o] : 0.0);
+  as[i] = make_double4(acc[3 * o], acc[3 * o + 1], acc[3 * o + 2], 0.0);
+}
+
+// P2M of charges q = gp and dipoles d = -ga at the leaf's centre:
+// M_n^m = sum_i q_i Y_n^m + d_z Y_{n-1}^m + (d_x - i d_y)/2 Y_{n-1}^{m+1}
+//                         - (d_x + i d_y)/2 Y_{n-1}^{m-1}     (at x_i - z)
+constexpr int PA_T = 64, PA_LDS = 2048;  // doubles of harmonics per batch
+
+__global__ void __launch_bounds__(PA_T) k_p2m_adj(int p, const int* leaves, int nleaves, const int* cb,
+                                                  const int* ce, const double4* pm, const double4* gs,
+                                                  const double* cx, const double* cy, const double* cz,
+                                                  double* madj) {
+  __shared__ double lds[PA_LDS];
+  __shared__ double4 gsh[64];
+  int li = blockIdx.x;
+  if (li >= nleaves) return;
+  int c = leaves[li];
+  int nc = ncoef(p);
+  int batch = min(64, PA_LDS / (2 * nc));
+  double* yre = lds;
+  double* yim = lds + nc * batch;
+  int t = threadIdx.x;
+  double x0 = cx[c], y0 = cy[c], z0 = cz[c];
+  int b = cb[c], e = ce[c];
+  constexpr int MAXK = (ncoef(FMM_GPU_PMAX) + PA_T - 1) / PA_T;
+  double acr[MAXK], aci[MAXK];
+  for (int u = 0; u < MAXK; u++) acr[u] = aci[u] = 0.0;
+  for (int i0 = b; i0 < e; i0 += batch) {
+    int cnt = min(batch, e - i0);
+    if (t < cnt) {
+      double4 q = pm[i0 + t];
+      regular_fma(p, q.x - x0, q.y - y0, q.z - z0, yre + t, yim + t, batch);
+      gsh[t] = gs[i0 + t];
+    }
+    __syncthreads();
+    for (int u = 0; u < MAXK; u++) {
+      int k = t + PA_T * u;
+      if (k >= nc) continue;
+      int n = 0;
+      while (cidx(n + 1, 0) <= k) n++;
+      int m = k - cidx(n, 0);
+      double sr = acr[u], si = aci[u];
+      for (int j = 0; j < cnt; j++) {
+        double4 g = gsh[j];
+        double q = g.w, dx = -g.x, dy = -g.y, dz = -g.z;
+        sr = fma(q, yre[k * batch + j], sr);
+        si = fma(q, yim[k * batch + j], si);
+        if (n >= 1) {
+          if (m <= n - 1) {  // d_z Y_{n-1}^m
+            sr = fma(dz, yre[cidx(n - 1, m) * batch + j], sr);
+            si = fma(dz, yim[cidx(n - 1, m) * batch + j], si);
+          }
+          if (m + 1 <= n - 1) {  // (d_x - i d_y)/2 * Y_{n-1}^{m+1}
+            double ar = yre[cidx(n - 1, m + 1) * batch + j], ai = yim[cidx(n - 1, m + 1) * batch + j];
+            sr = fma(0.5 * dx, ar, fma(0.5 * dy, ai, sr));
+            si = fma(0.5 * dx, ai, fma(-0.5 * dy, ar, si));
+          }
+          if (m - 1 <= n - 1) {  // -(d_x + i d_y)/2 * Y_{n-1}^{m-1}
+            double ar, ai;
+            if (m >= 1) {
+              ar = yre[cidx(n - 1, m - 1) * batch + j];
+              ai = yim[cidx(n - 1, m - 1) * batch + j];
+            } else if (n - 1 >= 1) {  // Y^{-1} = -conj(Y^1)
+              ar = -yre[cidx(n - 1, 1) * batch + j];
+              ai = yim[cidx(n - 1, 1) * batch + j];
+            } else {
+              ar = ai = 0.0;
+            }
+            sr = fma(-0.5 * dx, ar, fma(0.5 * dy, ai, sr));
+            si = fma(-0.5 * dx, ai, fma(-0.5 * dy, ar, si));
+          }
+        }
+      }
+      acr[u] = sr;
+      aci[u] = si;
+    }
+    __syncthreads();
+  }
+  double* out = madj + (size_t)c * nc * 2;
+  for (int u = 0; u < MAXK; u++) {
+    int k = t + PA_T * u;
+    if (k < nc) {
+      out[2 * k] = acr[u];
+      out[2 * k + 1] = aci[u];
+    }
+  }
+}
+
+// coefficient (n, q) of an expansion for either sign of q
+__device__ __forceinline__ void lget(const double* L, int n, int q, double& a, double& b) {
+  if (q >= 0) {
+    a = L[2 * cidx(n, q)];
+    b = L[2 * cidx(n, q) + 1];
+  } else {
+    double s = (q & 1) ? -1.0 : 1.0;
+    a = s * L[2 * cidx(n, -q)];
+    b = -s * L[2 * cidx(n, -q) + 1];
+  }
+}
+
+// Low orders of the expansion L re-centred at offset (X, Y, Z):
+// L'_j^i = sum_{k <= p-j} sum_l L_{j+k}^{i+l} conj(Y_k^l), for j in [J0, J1],
+// i = 0..j, written to out[(j(j+1)/2 + i) - J0(J0+1)/2] (complex, re/im).
+template <int J0, int J1>
+__device__ inline void shift_low(int p, const double* L, double X, double Y, double Z, double* outr,
+                                 double* outi) {
+  constexpr int NT = (J1 + 1) * (J1 + 2) / 2 - J0 * (J0 + 1) / 2;
+  for (int t = 0; t < NT; t++) outr[t] = outi[t] = 0.0;
+  double r2 = fma(X, X, fma(Y, Y, Z * Z));
+  double dr = 1.0, di = 0.0;  // Y_m^m
+  for (int m = 0; m <= p; m++) {
+    if (m > 0) {
+      double inv = -1.0 / (double)(2 * m);
+      double tr = fma(X, dr, -Y * di), ti = fma(X, di, Y * dr);
+      dr = tr * inv;
+      di = ti * inv;
+    }
+    double yr = dr, yi = di, pr = 0.0, pi = 0.0;
+    double sg = (m & 1) ? -1.0 : 1.0;
+    for (int k = m; k <= p - J0; k++) {
+      if (k > m) {
+        double kk = (double)(2 * k - 1) * Z, inv = 1.0 / (double)((k + m) * (k - m));
+        double vr = fma(kk, yr, -r2 * pr) * inv, vi = fma(kk, yi, -r2 * pi) * inv;
+        pr = yr;
+        pi = yi;
+        yr = vr;
+        yi = vi;
+      }
+#pragma unroll
+      for (int j = J0; j <= J1; j++) {
+        if (j + k > p) continue;
+#pragma unroll
+        for (int i = 0; i <= j; i++) {
+          int t = j * (j + 1) / 2 + i - J0 * (J0 + 1) / 2;
+          double a, b;
+          // l = +m: L_{j+k}^{i+m} conj(Y_k^m)
+          lget(L, j + k, i + m, a, b);
+          outr[t] = fma(a, yr, fma(b, yi, outr[t]));
+          outi[t] = fma(b, yr, fma(-a, yi, outi[t]));
+          if (m > 0) {  // l = -m: L_{j+k}^{i-m} (-1)^m Y_k^m
+            lget(L, j + k, i - m, a, b);
+            double cr = sg * yr, ci = sg * yi;
+            outr[t] = fma(a, cr, fma(-b, ci, outr[t]));
+            outi[t] = fma(a, ci, fma(b, cr, outi[t]));
+          }
+        }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ double rsqrt_fp64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
+// one thread per body (sorted order); results in the caller's order
+__global__ void __launch_bounds__(256) k_adj_leaf(int p, int64_t n, const int* __restrict__ leaf_of,
+                                                  const int* __restrict__ cb, const int* __restrict__ ce,
+                                                  const int* __restrict__ off, const int* __restrict__ srcl,
+                                                  const double* __restrict__ cx, const double* __restrict__ cy,
+                                                  const double* __restrict__ cz,
+                                                  const double* __restrict__ lfwd,
+                                                  const double* __restrict__ ladj,
+                                                  const double4* __restrict__ pm,
+                                                  const double4* __restrict__ gs,
+                                                  const double4* __restrict__ as,
+                                                  const int* __restrict__ perm, double eps2, double* gpos,
+                                                  double* gmass) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int B = leaf_of[i];
+  int nc = ncoef(p);
+  double4 me = pm[i], g = gs[i], af = as[i];
+  double X = me.x - cx[B], Y = me.y - cy[B], Z = me.z - cz[B];
+  // far field: Hess Phi from the forward expansion (order 2), Psi and grad Psi
+  // from the adjoint expansion (orders 0, 1)
+  double hr[3], hi[3], ar[3], ai[3];
+  shift_low<2, 2>(p, lfwd + (size_t)B * nc * 2, X, Y, Z, hr, hi);
+  shift_low<0, 1>(p, ladj + (size_t)B * nc * 2, X, Y, Z, ar, ai);
+  // Phi_2 = -Re[conj(A) Y_2^0 + 2 conj(B) Y_2^1 + 2 conj(C) Y_2^2]
+  double Hxx = 0.5 * hr[0] - 0.5 * hr[2], Hyy = 0.5 * hr[0] + 0.5 * hr[2], Hzz = -hr[0];
+  double Hxy = -0.5 * hi[2], Hxz = hr[1], Hyz = hi[1];
+  double gx = -(Hxx * g.x + Hxy * g.y + Hxz * g.z);
+  double gy = -(Hxy * g.x + Hyy * g.y + Hyz * g.z);
+  double gz = -(Hxz * g.x + Hyz * g.y + Hzz * g.z);
+  double psi = -ar[0];
+  double px = ar[2], py = ai[2], pz = -ar[1];
+  // near field, softened pair terms
+  double kx = 0.0, ky = 0.0, kz = 0.0;
+  for (int q = off[B]; q < off[B + 1]; q++) {
+    int A = srcl[q];
+    for (int j = cb[A]; j < ce[A]; j++) {
+      double4 s = pm[j];
+      double ux = me.x - s.x, uy = me.y - s.y, uz = me.z - s.z;
+      double s2 = fma(ux, ux, fma(uy, uy, fma(uz, uz, eps2)));
+      if (j == i || !(s2 > 0.0)) continue;
+      double4 gj = gs[j];
+      double inv = rsqrt_fp64(s2), inv2 = inv * inv, inv3 = inv2 * inv, inv5 = inv3 * inv2;
+      double ugj = fma(ux, gj.x, fma(uy, gj.y, uz * gj.z));
+      psi = fma(ugj, inv3, fma(-gj.w, inv, psi));
+      double c1 = -3.0 * ugj * inv5, c2 = gj.w * inv3;
+      px = fma(gj.x, inv3, fma(c1 + c2, ux, px));
+      py = fma(gj.y, inv3, fma(c1 + c2, uy, py));
+      pz = fma(gj.z, inv3, fma(c1 + c2, uz, pz));
+      double ug = fma(ux, g.x, fma(uy, g.y, uz * g.z));
+      double w3 = s.w * inv3, w5 = -3.0 * s.w * ug * inv5;
+      kx = fma(w3, g.x, fma(w5, ux, kx));
+      ky = fma(w3, g.y, fma(w5, uy, ky));
+      kz = fma(w3, g.z, fma(w5, uz, kz));
+    }
+  }
+  int64_t o = perm[i];
+  gpos[3 * o] = gx - kx - g.w * af.x + me.w * px;
+  gpos[3 * o + 1] = gy - ky - g.w * af.y + me.w * py;
+  gpos[3 * o + 2] = gz - kz - g.w * af.z + me.w * pz;
+  gmass[o] = psi;
+}
+
+// the expansion pass of the adjoint sources and the leaf evaluation; the
+// forward pass (tree, lists, local expansions, acc) must be in place
+void adjoint_pass(Ctx& c, const double* gacc, const double* gpot, const double* acc_fwd, double* gpos,
+                  double* gmass) {
+  hipStream_t s = c.stream;
+  int64_t n = c.n;
+  int nc = (int)c.ncell;
+  size_t ne = (size_t)nc * ncoef(c.p) * 2;
+  ensure(c.ws, c.madj, ne);
+  ensure(c.ws, c.ladj, ne);
+  ensure(c.ws, c.gsort, (size_t)n);
+  ensure(c.ws, c.asort, (size_t)n);
+  unsigned g = (unsigned)ceil_div(n, 256);
+  hipLaunchKernelGGL(k_adj_gather, dim3(g), dim3(256), 0, s, n, c.idx[0].p, gacc, gpot, acc_fwd, c.gsort.p,
+                     c.asort.p);
+  hipLaunchKernelGGL(k_p2m_adj, dim3((unsigned)c.nleaf), dim3(PA_T), 0, s, c.p, c.leaves.p, (int)c.nleaf,
+                     c.c_begin.p, c.c_end.p, c.pm.p, c.gsort.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.madj.p);
+  HIPCHK(hipGetLastError());
+  m2m_levels(c, c.madj.p);
+  HIPCHK(hipMemsetAsync(c.ladj.p, 0, ne * sizeof(double), s));
+  launch_m2l_fp64_buffers(c, nc, c.madj.p, c.ladj.p);
+  launch_l2l_buf(c, c.ladj.p);
+  hipLaunchKernelGGL(k_adj_leaf, dim3(g), dim3(256), 0, s, c.p, n, c.leaf_of.p, c.c_begin.p, c.c_end.p,
+                     c.p2p.off.p, c.p2p.src.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.loc.p, c.ladj.p, c.pm.p,
+                     c.gsort.p, c.asort.p, c.idx[0].p, c.eps_soft * c.eps_soft, gpos, gmass);
+  HIPCHK(hipGetLastError());
+}
+
+}  // namespace fmm

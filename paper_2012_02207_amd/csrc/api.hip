@@ -405,6 +405,56 @@ fmm_status fmm_export(fmm_ctx* ctx, int what, void* host_buf, size_t bytes) {
   });
 }
 
+fmm_status fmm_forces_frozen(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass,
+                             double eps_soft, double* acc, double* pot, void* stream) {
+  fmm_status st = common_checks(ctx, n, pos, mass);
+  if (st != FMM_OK) return st;
+  if (!acc || !pot || !(eps_soft >= 0) || !std::isfinite(eps_soft)) return FMM_EINVAL;
+  Ctx& c = ctx->c;
+  if (!c.evaluated || c.n != n) return FMM_ENOTBUILT;
+  return guarded(ctx, [&]() {
+    c.stream = (hipStream_t)stream;
+    c.err.clear();
+    c.eps_soft = eps_soft;
+    c.have_events = true;
+    HIPCHK(hipEventRecord(c.ev[0], c.stream));
+    refresh_frozen(c, pos, mass);
+    HIPCHK(hipEventRecord(c.ev[1], c.stream));
+    expansions_up(c);
+    HIPCHK(hipEventRecord(c.ev[2], c.stream));
+    HIPCHK(hipEventRecord(c.ev[3], c.stream));  // no estimate, no walk
+    evaluate(c, acc, pot);
+    HIPCHK(hipEventRecord(c.ev[8], c.stream));
+    return FMM_OK;
+  });
+}
+
+fmm_status fmm_adjoint(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass, double eps_soft,
+                       int p, double err_tol, const double* gacc, const double* gpot, double* gpos,
+                       double* gmass, void* stream) {
+  if (!ctx || !gacc || !gpos || !gmass) return FMM_EINVAL;
+  Ctx& c = ctx->c;
+  if (p < 1 || p > FMM_GPU_PMAX) return p < 1 || p > 30 ? FMM_EINVAL : FMM_EUNSUPPORTED;
+  fmm_params saved = c.prm;
+  c.prm.precision = FMM_FP64;  // the gradient is formed in FP64
+  fmm_status st = guarded(ctx, [&]() {
+    ensure(c.ws, c.fwd_acc, (size_t)std::max<int64_t>(n, 1) * 3);
+    ensure(c.ws, c.fwd_pot, (size_t)std::max<int64_t>(n, 1));
+    return FMM_OK;
+  });
+  if (st == FMM_OK) {
+    int64_t off[2] = {0, n};
+    st = forces_impl(ctx, 1, off, n, pos, mass, eps_soft, p, err_tol, c.fwd_acc.p, c.fwd_pot.p, stream);
+  }
+  if (st == FMM_OK)
+    st = guarded(ctx, [&]() {
+      adjoint_pass(c, gacc, gpot, c.fwd_acc.p, gpos, gmass);
+      return FMM_OK;
+    });
+  c.prm = saved;
+  return st;
+}
+
 // ---- autotuner: n_leaf per (device, precision, p, tolerance, size class) ----
 namespace {
 using TuneKey = std::tuple<int, int, int, double, int, int>;
@@ -530,7 +580,7 @@ void fmm_destroy(fmm_ctx* ctx) {
     rel(c.idx[k]);
     rel(c.front[k]);
   }
-  rel(c.sx); rel(c.sy); rel(c.sz); rel(c.sm); rel(c.pm); rel(c.pkb); rel(c.scale); rel(c.nmult); rel(c.fpart); rel(c.leaf_of); rel(c.leaves); rel(c.sys_off); rel(c.skey[0]); rel(c.skey[1]); rel(c.spos[0]); rel(c.spos[1]); rel(c.sort_hist);
+  rel(c.sx); rel(c.sy); rel(c.sz); rel(c.sm); rel(c.pm); rel(c.pkb); rel(c.scale); rel(c.nmult); rel(c.fpart); rel(c.leaf_of); rel(c.leaves); rel(c.madj); rel(c.ladj); rel(c.fwd_acc); rel(c.fwd_pot); rel(c.gsort); rel(c.asort); rel(c.sys_off); rel(c.skey[0]); rel(c.skey[1]); rel(c.spos[0]); rel(c.spos[1]); rel(c.sort_hist);
   rel(c.bbox_part); rel(c.rootbox); rel(c.c_level); rel(c.c_begin); rel(c.c_end); rel(c.c_parent);
   rel(c.c_child0); rel(c.c_nchild); rel(c.c_split); rel(c.c_mass); rel(c.c_sx); rel(c.c_sy);
   rel(c.c_sz); rel(c.c_cx); rel(c.c_cy); rel(c.c_cz); rel(c.c_rad); rel(c.c_rad2bits); rel(c.mult);

@@ -139,6 +139,11 @@ struct Ctx {
   dbuf<double> scale; // mixed precision: expansion scale per cell
   dbuf<float> nmult;  // mixed precision: normalised FP32 moments, (p+1)^2 per cell
 
+  // adjoint pass: expansions of the adjoint sources, sorted (ga, gp) and
+  // forward acceleration, forward outputs of the recomputed pass
+  dbuf<double> madj, ladj, fwd_acc, fwd_pot;
+  dbuf<double4> gsort, asort;
+
   // walks
   dbuf<int2> front[2];
   dbuf<int> counters;  // device counters
@@ -165,6 +170,9 @@ uint32_t* radix_sort_narrow(Ctx& c, const uint64_t* in, uint32_t* b0, uint32_t* 
 
 void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass);
 void upward_pass(Ctx& c);
+void expansions_up(Ctx& c);
+void cell_moments(Ctx& c);
+void refresh_frozen(Ctx& c, const double* pos, const double* mass);
 void estimate_walk(Ctx& c);
 void mac_walk(Ctx& c);
 void evaluate(Ctx& c, double* acc, double* pot);
@@ -175,7 +183,12 @@ bool check_inputs_dev(Ctx& c, const double* pos, const double* mass, int64_t n);
 // M2L launchers (one per compiled order)
 void launch_m2l_fp64(Ctx& c);
 void launch_m2l_fp64_range(Ctx& c, int first_lo);
+void launch_m2l_fp64_buffers(Ctx& c, int first_lo, const double* mult, double* loc);
+void m2m_levels(Ctx& c, double* mult);
+void launch_l2l_buf(Ctx& c, double* loc);
 void launch_m2l_mixed(Ctx& c);
 bool mixed_supported(int p);
+void adjoint_pass(Ctx& c, const double* gacc, const double* gpot, const double* acc_fwd, double* gpos,
+                  double* gmass);
 
 }  // namespace fmm

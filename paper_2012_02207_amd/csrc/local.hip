@@ -326,12 +326,14 @@ void launch_leaf_eval(Ctx& c, double* acc, double* pot) {
   HIPCHK(hipGetLastError());
 }
 
-void launch_l2l(Ctx& c) {
+void launch_l2l(Ctx& c) { launch_l2l_buf(c, c.loc.p); }
+
+void launch_l2l_buf(Ctx& c, double* loc) {
   size_t lds = sizeof(double2) * 9 * (size_t)(c.p + 1) * (c.p + 1);
   for (int level = 0; level < c.depth; level++) {  // parents at this level, children one below
     int first = c.lvl_first[level], count = c.lvl_count[level];
     hipLaunchKernelGGL(k_l2l, dim3(count), dim3(L2L_T), lds, c.stream, c.p, first, count, c.c_child0.p,
-                       c.c_nchild.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.loc.p);
+                       c.c_nchild.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, loc);
   }
   HIPCHK(hipGetLastError());
 }

@@ -383,24 +383,24 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l_fp64(int ncell, int firs
 }
 
 template <int P>
-static void launch_p(Ctx& c, int first_lo) {
+static void launch_p(Ctx& c, int first_lo, const double* mult, double* loc) {
   int nc = (int)c.ncell;
   int nblk = (nc + M2L_WAVES - 1) / M2L_WAVES;
   unsigned grid = 8u * (unsigned)((nblk + 7) / 8);
   hipLaunchKernelGGL(k_m2l_fp64<P>, dim3(grid), dim3(64 * M2L_WAVES), 0, c.stream, nc, first_lo, c.m2l.off.p, c.m2l.src.p,
-                     c.c_cx.p, c.c_cy.p, c.c_cz.p, c.mult.p, c.loc.p);
+                     c.c_cx.p, c.c_cy.p, c.c_cz.p, mult, loc);
 }
 
 template <int P>
-static bool dispatch(Ctx& c, int first_lo) {
+static bool dispatch(Ctx& c, int first_lo, const double* mult, double* loc) {
   if constexpr (P > FMM_GPU_PMAX) {
     return false;
   } else {
     if (c.p == P) {
-      launch_p<P>(c, first_lo);
+      launch_p<P>(c, first_lo, mult, loc);
       return true;
     }
-    return dispatch<P + 1>(c, first_lo);
+    return dispatch<P + 1>(c, first_lo, mult, loc);
   }
 }
 
@@ -413,6 +413,11 @@ void launch_m2l_fp64(Ctx& c) {
 // FP64 M2L for all pairs whose sink is above first_lo or whose source is
 // (first_lo = ncell: every pair); writes loc, which must be zeroed before
 void launch_m2l_fp64_range(Ctx& c, int first_lo) {
+  launch_m2l_fp64_buffers(c, first_lo, c.mult.p, c.loc.p);
+}
+
+// the same over other expansion buffers (same tree and list)
+void launch_m2l_fp64_buffers(Ctx& c, int first_lo, const double* mult, double* loc) {
   if (!g_m2l_tables) {
     // compact the dense tables to their structural non-zeros (row-major)
     static_assert(CSWAP_DOUBLES <= 8192, "compacted swap table");
@@ -425,7 +430,7 @@ void launch_m2l_fp64_range(Ctx& c, int first_lo) {
     HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_fact_m2l), fmm_fact_table, sizeof(double) * (2 * FMM_GPU_PMAX + 2)));
     g_m2l_tables = true;
   }
-  if (!dispatch<1>(c, first_lo)) throw hip_error{hipErrorInvalidValue, "M2L order not compiled"};
+  if (!dispatch<1>(c, first_lo, mult, loc)) throw hip_error{hipErrorInvalidValue, "M2L order not compiled"};
   HIPCHK(hipGetLastError());
 }
 

@@ -638,6 +638,50 @@ __global__ void k_leaf_of(const int* cb, const int* ce, const int* nch, int ncel
 
 static inline dim3 grid1(int64_t n, int t = 256) { return dim3((unsigned)ceil_div(n, t)); }
 
+// mass, centre of mass and radius of every cell from the sorted bodies
+void cell_moments(Ctx& c) {
+  hipStream_t s = c.stream;
+  int nc = (int)c.ncell, nsys = c.nsys;
+  long long* tot = (long long*)c.counters.p;
+  ensure(c.ws, c.c_mass, nc);
+  ensure(c.ws, c.c_sx, nc);
+  ensure(c.ws, c.c_sy, nc);
+  ensure(c.ws, c.c_sz, nc);
+  ensure(c.ws, c.c_cx, nc);
+  ensure(c.ws, c.c_cy, nc);
+  ensure(c.ws, c.c_cz, nc);
+  ensure(c.ws, c.c_rad, nc);
+  ensure(c.ws, c.c_rad2bits, nc);
+  for (int level = c.depth; level >= 0; level--) {
+    int first = c.lvl_first[level], count = c.lvl_count[level];
+    hipLaunchKernelGGL(k_mass_com, grid1(count, 128), dim3(128), 0, s, first, count, level,
+                       c.c_begin.p, c.c_end.p, c.c_child0.p, c.c_nchild.p, c.sx.p, c.sy.p, c.sz.p,
+                       c.sm.p, c.key[0].p, c.rootbox.p, c.sys_off.p, nsys, c.c_mass.p, c.c_sx.p, c.c_sy.p, c.c_sz.p,
+                       c.c_cx.p, c.c_cy.p, c.c_cz.p);
+    HIPCHK(hipGetLastError());
+  }
+  // radii
+  ensure(c.ws, c.c_split, (size_t)2 * nc + 64);
+  int* nchunk = c.c_split.p;
+  int* choff = nchunk + nc + 32;
+  hipLaunchKernelGGL(k_rad_chunks, grid1(nc), dim3(256), 0, s, c.c_begin.p, c.c_end.p, nc, nchunk);
+  exclusive_scan(c, nchunk, choff, nc, tot);
+  long long nchunks = read_total(c, tot);
+  HIPCHK(hipMemsetAsync(c.c_rad2bits.p, 0, sizeof(unsigned long long) * nc, s));
+  hipLaunchKernelGGL(k_radius, dim3((unsigned)nchunks), dim3(RAD_T), 0, s, c.c_begin.p, c.c_end.p,
+                     choff, nc, c.sx.p, c.sy.p, c.sz.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.c_rad2bits.p);
+  hipLaunchKernelGGL(k_radius_final, grid1(nc), dim3(256), 0, s, c.c_rad2bits.p, nc, c.c_rad.p);
+}
+
+// Positions and masses changed, tree topology, order and lists kept: the
+// sorted bodies and the cell moments are recomputed from the stored order.
+void refresh_frozen(Ctx& c, const double* pos, const double* mass) {
+  hipLaunchKernelGGL(k_gather, grid1(c.n), dim3(256), 0, c.stream, pos, mass, c.idx[0].p, c.n, c.sx.p,
+                     c.sy.p, c.sz.p, c.sm.p, c.pm.p);
+  HIPCHK(hipGetLastError());
+  cell_moments(c);
+}
+
 void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
   hipStream_t s = c.stream;
   c.n = n;
@@ -743,34 +787,7 @@ void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
   c.depth = (int)c.lvl_first.size() - 1;
   int nc = (int)c.ncell;
 
-  ensure(c.ws, c.c_mass, nc);
-  ensure(c.ws, c.c_sx, nc);
-  ensure(c.ws, c.c_sy, nc);
-  ensure(c.ws, c.c_sz, nc);
-  ensure(c.ws, c.c_cx, nc);
-  ensure(c.ws, c.c_cy, nc);
-  ensure(c.ws, c.c_cz, nc);
-  ensure(c.ws, c.c_rad, nc);
-  ensure(c.ws, c.c_rad2bits, nc);
-  for (int level = c.depth; level >= 0; level--) {
-    int first = c.lvl_first[level], count = c.lvl_count[level];
-    hipLaunchKernelGGL(k_mass_com, grid1(count, 128), dim3(128), 0, s, first, count, level,
-                       c.c_begin.p, c.c_end.p, c.c_child0.p, c.c_nchild.p, c.sx.p, c.sy.p, c.sz.p,
-                       c.sm.p, c.key[0].p, c.rootbox.p, c.sys_off.p, nsys, c.c_mass.p, c.c_sx.p, c.c_sy.p, c.c_sz.p,
-                       c.c_cx.p, c.c_cy.p, c.c_cz.p);
-    HIPCHK(hipGetLastError());
-  }
-  // radii
-  ensure(c.ws, c.c_split, (size_t)2 * nc + 64);
-  int* nchunk = c.c_split.p;
-  int* choff = nchunk + nc + 32;
-  hipLaunchKernelGGL(k_rad_chunks, grid1(nc), dim3(256), 0, s, c.c_begin.p, c.c_end.p, nc, nchunk);
-  exclusive_scan(c, nchunk, choff, nc, tot);
-  long long nchunks = read_total(c, tot);
-  HIPCHK(hipMemsetAsync(c.c_rad2bits.p, 0, sizeof(unsigned long long) * nc, s));
-  hipLaunchKernelGGL(k_radius, dim3((unsigned)nchunks), dim3(RAD_T), 0, s, c.c_begin.p, c.c_end.p,
-                     choff, nc, c.sx.p, c.sy.p, c.sz.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.c_rad2bits.p);
-  hipLaunchKernelGGL(k_radius_final, grid1(nc), dim3(256), 0, s, c.c_rad2bits.p, nc, c.c_rad.p);
+  cell_moments(c);
   hipLaunchKernelGGL(k_leaf_of, grid1(nc), dim3(256), 0, s, c.c_begin.p, c.c_end.p, c.c_nchild.p, nc,
                      c.leaf_of.p);
   HIPCHK(hipGetLastError());

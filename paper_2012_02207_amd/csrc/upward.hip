@@ -236,6 +236,16 @@ __global__ void k_compact_leaves(const int* flag, const int* off, int ncell, int
   if (c < ncell && flag[c]) leaves[off[c]] = c;
 }
 
+// M2M from the deepest parents to the roots over the multipole buffer `mult`
+void m2m_levels(Ctx& c, double* mult) {
+  for (int level = c.depth - 1; level >= 0; level--) {
+    int first = c.lvl_first[level], count = c.lvl_count[level];
+    hipLaunchKernelGGL(k_m2m, dim3(count), dim3(M2M_T), m2m_lds_bytes(c.p), c.stream, c.p, first, count,
+                       c.c_child0.p, c.c_nchild.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, mult);
+    HIPCHK(hipGetLastError());
+  }
+}
+
 void upward_pass(Ctx& c) {
   if (!g_up_tables) {
     HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_fact), fmm_fact_table, sizeof(fmm_fact_table)));
@@ -257,17 +267,20 @@ void upward_pass(Ctx& c) {
   exclusive_scan(c, flag, off, nc, tot);
   hipLaunchKernelGGL(k_compact_leaves, dim3((nc + 255) / 256), dim3(256), 0, s, flag, off, nc, leaves);
   c.nleaf = read_total(c, tot);
+  expansions_up(c);
+}
+
+// P2M at the leaves (list built above), M2M to the roots, P_k
+void expansions_up(Ctx& c) {
+  hipStream_t s = c.stream;
+  int p = c.p, nc = (int)c.ncell;
+  const int* leaves = c.leaves.p;
   size_t p2m_lds = sizeof(double) * (2 * ncoef(p) + 1) * p2m_batch(p);
   hipLaunchKernelGGL(k_p2m, dim3((unsigned)c.nleaf), dim3(P2M_T), p2m_lds, s, p, leaves, (int)c.nleaf,
                      c.c_begin.p, c.c_end.p, c.sx.p, c.sy.p, c.sz.p, c.sm.p, c.c_cx.p, c.c_cy.p,
                      c.c_cz.p, c.mult.p);
   HIPCHK(hipGetLastError());
-  for (int level = c.depth - 1; level >= 0; level--) {
-    int first = c.lvl_first[level], count = c.lvl_count[level];
-    hipLaunchKernelGGL(k_m2m, dim3(count), dim3(M2M_T), m2m_lds_bytes(p), s, p, first, count, c.c_child0.p,
-                       c.c_nchild.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.mult.p);
-    HIPCHK(hipGetLastError());
-  }
+  m2m_levels(c, c.mult.p);
   int64_t npk = (int64_t)nc * (p + 1);
   ensure(c.ws, c.pkb, (size_t)npk);
   hipLaunchKernelGGL(k_pk, dim3((unsigned)ceil_div(npk, 256)), dim3(256), 0, s, p, nc, c.mult.p, c.pk.p,

@@ -25,7 +25,7 @@ EXPORTS = dict(keys=(0, np.uint64), perm=(1, np.int32), cell_level=(2, np.int32)
                m2l=(18, np.int32), p2p=(19, np.int32), local=(20, np.float64),
                rootbox=(21, np.float64))
 SYMBOLS = ["fmm_default_params", "fmm_create", "fmm_set_params", "fmm_build", "fmm_forces",
-           "fmm_forces_batch", "fmm_autotune", "fmm_stats", "fmm_export", "fmm_set_workspace_limit",
+           "fmm_forces_batch", "fmm_forces_frozen", "fmm_autotune", "fmm_adjoint", "fmm_stats", "fmm_export", "fmm_set_workspace_limit",
            "fmm_direct", "fmm_strerror", "fmm_last_error", "fmm_destroy"]
 
 
@@ -75,6 +75,8 @@ def load_library():
                                      C.c_double, P, P, P]
     lib.fmm_autotune.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), P, P, C.c_double, C.c_int,
                                  C.c_double, P, P, P, C.POINTER(C.c_int)]
+    lib.fmm_forces_frozen.argtypes = [P, C.c_int64, P, P, C.c_double, P, P, P]
+    lib.fmm_adjoint.argtypes = [P, C.c_int64, P, P, C.c_double, C.c_int, C.c_double, P, P, P, P, P]
     lib.fmm_stats.argtypes = [P, C.POINTER(Stats)]
     lib.fmm_export.argtypes = [P, C.c_int, P, C.c_size_t]
     lib.fmm_set_workspace_limit.argtypes = [P, C.c_size_t]
@@ -85,7 +87,8 @@ def load_library():
     lib.fmm_last_error.restype = C.c_char_p
     lib.fmm_destroy.argtypes = [P]
     for f in ("fmm_create", "fmm_set_params", "fmm_build", "fmm_forces", "fmm_forces_batch",
-              "fmm_autotune", "fmm_stats", "fmm_export", "fmm_set_workspace_limit", "fmm_direct"):
+              "fmm_forces_frozen", "fmm_autotune", "fmm_adjoint", "fmm_stats", "fmm_export", "fmm_set_workspace_limit",
+              "fmm_direct"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -237,6 +240,41 @@ class FMM:
             _stream(), C.byref(chosen)))
         self.params.n_leaf = chosen.value
         return chosen.value
+
+    def forces_frozen(self, pos, mass, eps_soft=0.0, out=None):
+        """Forces with the tree and lists of the last evaluation kept (see fmm_forces_frozen)."""
+        torch = _torch()
+        n = mass.shape[0]
+        if out is None:
+            acc = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+            pot = torch.empty((n,), dtype=torch.float64, device=pos.device)
+        else:
+            acc, pot = out
+        self._check(self._lib.fmm_forces_frozen(
+            self._h, n, _dev_ptr(pos, torch.float64, (n, 3), "pos"),
+            _dev_ptr(mass, torch.float64, (n,), "mass"), float(eps_soft),
+            _dev_ptr(acc, torch.float64, (n, 3), "acc"), _dev_ptr(pot, torch.float64, (n,), "pot"),
+            _stream()))
+        return acc, pot
+
+    def adjoint(self, pos, mass, gacc, gpot=None, eps_soft=0.0, p=None, err_tol=None):
+        """(dL/dpos, dL/dmass) for dL/dacc = gacc and dL/dpot = gpot (or zero);
+        recomputes the forward pass at pos."""
+        torch = _torch()
+        n = mass.shape[0]
+        gpos = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        gmass = torch.empty((n,), dtype=torch.float64, device=pos.device)
+        gp = None if gpot is None else _dev_ptr(gpot, torch.float64, (n,), "gpot")
+        self._check(self._lib.fmm_adjoint(
+            self._h, n, _dev_ptr(pos, torch.float64, (n, 3), "pos"),
+            _dev_ptr(mass, torch.float64, (n,), "mass"), float(eps_soft),
+            int(self.params.p if p is None else p),
+            float(self.params.err_tol if err_tol is None else err_tol),
+            _dev_ptr(gacc, torch.float64, (n, 3), "gacc"), gp,
+            _dev_ptr(gpos, torch.float64, (n, 3), "gpos"), _dev_ptr(gmass, torch.float64, (n,), "gmass"),
+            _stream()))
+        self.n = n
+        return gpos, gmass
 
     def stats(self):
         s = Stats()

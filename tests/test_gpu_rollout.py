@@ -1,0 +1,156 @@
+"""Gradients through the GPU force pass (fmm_adjoint) and through a leapfrog
+rollout built on it, against the direct-sum gradients of the oracle and
+against central finite differences.
+
+Bounds: the adjoint's far field is the FMM approximation of the exact
+gradient, so its error follows the force error of the pass (err_tol), made
+larger by the random signs of the test's dL/da (their fields cancel, so the
+relative error grows): median <= 10 err_tol and 99th percentile <= 1e3
+err_tol against the direct sum."""
+import numpy as np
+import pytest
+
+from oracle import adjoint as A
+from paper_2012_02207_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fmm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2012_02207_amd import fmm as F
+    return F
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+@pytest.mark.parametrize("eps_soft,p,tol", [(0.0, 10, 1e-7), (0.01, 8, 1e-6)])
+def test_force_adjoint_matches_direct_sum(fmm, eps_soft, p, tol):
+    pos, _, mass = W.plummer(4096, 123)
+    rng = np.random.default_rng(4)
+    ga, gp = rng.normal(size=(4096, 3)), rng.normal(size=4096)
+    print(f"[gpu] adjoint N=4096 p={p} tol={tol} eps_soft={eps_soft}", flush=True)
+    f = fmm.FMM(p=p, err_tol=tol, n_leaf=64)
+    gx, gm = f.adjoint(_dev(pos), _dev(mass), _dev(ga), _dev(gp), eps_soft=eps_soft)
+    rx, rm = A.direct_adjoint(pos, mass, ga, gp, eps_soft)
+    ex = np.linalg.norm(gx.cpu().numpy() - rx, axis=1) / np.linalg.norm(rx, axis=1)
+    em = np.abs(gm.cpu().numpy() - rm) / np.abs(rm)
+    assert np.median(ex) <= 10 * tol and np.percentile(ex, 99) <= 1e3 * tol, (np.median(ex),)
+    assert np.median(em) <= 10 * tol and np.percentile(em, 99) <= 1e3 * tol, (np.median(em),)
+    # gpot = None is zero
+    gx0, _ = f.adjoint(_dev(pos), _dev(mass), _dev(ga), None, eps_soft=eps_soft)
+    rx0, _ = A.direct_adjoint(pos, mass, ga, None, eps_soft)
+    e0 = np.linalg.norm(gx0.cpu().numpy() - rx0, axis=1) / np.linalg.norm(rx0, axis=1)
+    assert np.median(e0) <= 10 * tol
+    f.close()
+
+
+def _rollout_case(n, seed):
+    pos, vel, mass = W.plummer(n, seed)
+    rng = np.random.default_rng(seed + 1)
+    target = pos + 0.01 * rng.normal(size=pos.shape)
+    return pos, vel, mass, target
+
+
+def test_rollout_gradient_matches_direct_sum_rollout(fmm):
+    """64 kick-drift-kick steps (dt = 1e-3), L = sum |x_T - target|^2, with
+    checkpoints every 8 steps: dL/dx_0, dL/dv_0 and dL/dm through the FMM
+    adjoint against the reverse-mode gradient of the direct-sum rollout."""
+    from paper_2012_02207_amd import rollout as R
+    n, dt, steps = 1024, 1e-3, 64
+    pos, vel, mass, target = _rollout_case(n, 31)
+    print(f"[gpu] rollout gradient N={n} steps={steps}", flush=True)
+    solver = R.make_solver(p=10, err_tol=1e-9)
+    x0, v0, m = (_dev(a).requires_grad_(True) for a in (pos, vel, mass))
+    xT, _ = R.leapfrog(x0, v0, m, solver, dt, steps, checkpoint_every=8)
+    loss = ((xT - _dev(target)) ** 2).sum()
+    loss.backward()
+    L, gx, gv, gm = A.rollout_gradient(pos, vel, mass, dt, steps, target)
+    assert abs(loss.item() - L) <= 1e-8 * L
+    for g, r in ((x0.grad, gx), (v0.grad, gv), (m.grad, gm)):
+        g = g.cpu().numpy()
+        assert np.linalg.norm(g - r) <= 1e-6 * np.linalg.norm(r), np.linalg.norm(g - r) / np.linalg.norm(r)
+    solver.close()
+
+
+def test_frozen_forces_reproduce_and_differentiate(fmm):
+    """fmm_forces_frozen at the recorded positions repeats fmm_forces bit for
+    bit; at shifted positions its central differences (h = 1e-6) of
+    L = sum ga . a + gp . pot match fmm_adjoint (same lists, smooth in x)."""
+    pos, _, mass = W.plummer(4096, 61)
+    rng = np.random.default_rng(9)
+    ga, gp = rng.normal(size=(4096, 3)), rng.normal(size=4096)
+    print("[gpu] frozen forces N=4096", flush=True)
+    f = fmm.FMM(p=10, err_tol=1e-7, n_leaf=64)
+    P, M = _dev(pos), _dev(mass)
+    a1, p1 = f.forces(P, M)
+    a2, p2 = f.forces_frozen(P, M)
+    assert torch.equal(a1, a2) and torch.equal(p1, p2)
+    g = fmm.FMM(p=10, err_tol=1e-7, n_leaf=64)
+    gx, gm = g.adjoint(P, M, _dev(ga), _dev(gp))
+    gx, gm = gx.cpu().numpy(), gm.cpu().numpy()
+    GA, GP = _dev(ga), _dev(gp)
+
+    def L(x, m):
+        a, pt = f.forces_frozen(x, m)
+        return float((a * GA).sum() + (pt * GP).sum())
+    h = 1e-6
+    for k in rng.choice(4096, 12, replace=False):
+        d = int(rng.integers(3))
+        e = torch.zeros_like(P)
+        e[k, d] = h
+        fd = (L(P + e, M) - L(P - e, M)) / (2 * h)
+        assert abs(fd - gx[k, d]) <= 1e-5 * np.abs(gx).max() + 1e-4 * abs(fd), (k, d, fd, gx[k, d])
+    for k in rng.choice(4096, 4, replace=False):
+        e = torch.zeros_like(M)
+        e[k] = h * float(mass[k])
+        fd = (L(P, M + e) - L(P, M - e)) / (2 * h * float(mass[k]))
+        assert abs(fd - gm[k]) <= 1e-5 * np.abs(gm).max() + 1e-4 * abs(fd), (k, fd, gm[k])
+    f.close()
+    g.close()
+
+
+def test_rollout_gradient_matches_finite_differences(fmm):
+    """Central differences (h = 1e-6) of the FMM rollout's loss on 12 seeded
+    coordinates of x_0 and 4 masses against the autograd gradient.  The
+    perturbed rollouts keep the tree and lists each force evaluation had in
+    the unperturbed one (one context per evaluation, fmm_forces_frozen), so
+    the loss is smooth in the inputs."""
+    from paper_2012_02207_amd import rollout as R
+    n, dt, steps, h = 2048, 1e-3, 16, 1e-6
+    pos, vel, mass, target = _rollout_case(n, 47)
+    print(f"[gpu] rollout finite differences N={n} steps={steps}", flush=True)
+    solver = R.make_solver(p=10, err_tol=1e-7)
+    tgt = _dev(target)
+    x0, v0, m = (_dev(a).requires_grad_(True) for a in (pos, vel, mass))
+    xT, _ = R.leapfrog(x0, v0, m, solver, dt, steps, checkpoint_every=4)
+    ((xT - tgt) ** 2).sum().backward()
+    gx, gm = x0.grad.cpu().numpy(), m.grad.cpu().numpy()
+    P, V, M = _dev(pos), _dev(vel), _dev(mass)
+    solvers = [R.make_solver(p=10, err_tol=1e-7) for _ in range(steps + 1)]
+    R.leapfrog_frozen(P, V, M, solvers, dt, steps, record=True)
+
+    def loss(p_, m_):
+        xT, _ = R.leapfrog_frozen(p_, V, m_, solvers, dt, steps)
+        return ((xT - tgt) ** 2).sum().item()
+    rng = np.random.default_rng(3)
+    for k in rng.choice(n, 12, replace=False):
+        d = int(rng.integers(3))
+        e = torch.zeros_like(P)
+        e[k, d] = h
+        fd = (loss(P + e, M) - loss(P - e, M)) / (2 * h)
+        print(f"x[{k},{d}]: fd {fd:.9e} adjoint {gx[k, d]:.9e}", flush=True)
+        assert abs(fd - gx[k, d]) <= 1e-5 * np.abs(gx).max() + 1e-4 * abs(fd), (k, d, fd, gx[k, d])
+    for k in rng.choice(n, 4, replace=False):
+        e = torch.zeros_like(M)
+        e[k] = h * float(mass[k])
+        fd = (loss(P, M + e) - loss(P, M - e)) / (2 * h * float(mass[k]))
+        print(f"m[{k}]: fd {fd:.9e} adjoint {gm[k]:.9e}", flush=True)
+        assert abs(fd - gm[k]) <= 1e-5 * np.abs(gm).max() + 1e-4 * abs(fd), (k, fd, gm[k])
+    for s in solvers + [solver]:
+        s.close()
