@@ -226,6 +226,94 @@ def run_ensemble(args):
     print(json.dumps(out))
 
 
+def run_rollout(args):
+    """The differentiable rollout: Plummer N = 2^18, 64 kick-drift-kick steps
+    (dt = 1e-3), L = sum |x_T - target|^2 with seeded targets x_0 + 0.01 N(0, 1),
+    gradients dL/dx_0, dL/dv_0, dL/dm through the FMM adjoint with checkpoints
+    every 8 steps (forces of a segment recomputed in the backward pass).  One
+    step of the benchmark = one forward rollout plus its full gradient.  The
+    gradient is checked against central differences (h = 1e-6) on 32 seeded
+    coordinates of x_0, with every force evaluation of the perturbed rollouts
+    keeping the tree and lists of the unperturbed one."""
+    import torch
+    from paper_2012_02207_amd import rollout as R, workloads as W
+    cfg = W.CONFIGS["rollout_256k"]
+    n, p, err_tol = cfg["n"], cfg["p"], cfg["err_tol"]
+    dt, nsteps, every = 1e-3, 64, 8
+    pos, vel, mass = W.plummer(n, cfg["seed"])
+    rng = np.random.default_rng(cfg["seed"] + 1)
+    target = pos + 0.01 * rng.normal(size=pos.shape)
+    dev = torch.device("cuda:0")
+    P, V, M, T = (torch.from_numpy(a).to(dev) for a in (pos, vel, mass, target))
+    solver = R.make_solver(p=p, err_tol=err_tol, n_leaf=args.n_leaf)
+
+    def step():
+        x0, v0, m = (a.clone().requires_grad_(True) for a in (P, V, M))
+        xT, _ = R.leapfrog(x0, v0, m, solver, dt, nsteps, checkpoint_every=every)
+        loss = ((xT - T) ** 2).sum()
+        loss.backward()
+        return loss.item(), x0.grad, v0.grad, m.grad
+    def note(msg):
+        print(f"[rollout] {msg}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+        note("warm-up step done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        L, gx, gv, gm = step()
+        note(f"timed step done ({time.perf_counter() - t0:.2f} s)")
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / args.steps
+    with torch.no_grad():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xT, _ = R.leapfrog(P, V, M, solver, dt, nsteps, checkpoint_every=0)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+    # finite differences with frozen lists
+    solvers = [R.make_solver(p=p, err_tol=err_tol, n_leaf=args.n_leaf) for _ in range(nsteps + 1)]
+    R.leapfrog_frozen(P, V, M, solvers, dt, nsteps, record=True)
+    note("recorded the lists of every force evaluation")
+
+    def loss_frozen(x):
+        xT, _ = R.leapfrog_frozen(x, V, M, solvers, dt, nsteps)
+        return ((xT - T) ** 2).sum().item()
+    gxn = gx.cpu().numpy()
+    h, rels = 1e-6, []
+    crng = np.random.default_rng(cfg["seed"] + 2)
+    for k in crng.choice(n, 32, replace=False):
+        d = int(crng.integers(3))
+        e = torch.zeros_like(P)
+        e[k, d] = h
+        fd = (loss_frozen(P + e) - loss_frozen(P - e)) / (2 * h)
+        rels.append(abs(fd - gxn[k, d]) / max(abs(fd), 1e-300))
+        note(f"finite difference {len(rels)}/32: rel {rels[-1]:.2e}")
+    for s_ in solvers:
+        s_.close()
+    rels = np.array(rels)
+    out = {
+        "metric": "differentiable rollout: forward + gradient of 64 leapfrog steps at N=2^18 "
+                  "(p=10, 1e-7), per second",
+        "value": 1.0 / t_step, "unit": "rollout gradients/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"rollout_256k: N={n}, Plummer, {nsteps} KDK steps, dt={dt}, p={p}, "
+                               f"eps={err_tol}, checkpoints every {every} steps", "n": n, "p": p,
+                   "err_tol": err_tol, "steps": nsteps, "dt": dt, "checkpoint_every": every},
+        "forward_rollout_ms": 1e3 * t_fwd,
+        "backward_over_forward": (t_step - t_fwd) / t_fwd,
+        "force_evals_per_s_forward": (nsteps + 1) / t_fwd,
+        "loss": L,
+        "grad_norms": {"x0": float(gx.norm()), "v0": float(gv.norm()), "m": float(gm.norm())},
+        "finite_difference_check": {"coords": 32, "h": h, "median_rel": float(np.median(rels)),
+                                    "max_rel": float(rels.max())},
+    }
+    solver.close()
+    print(json.dumps(out))
+
+
 def ensemble_cpu_baseline(clusters, p, err_tol, n_leaf, count=8, seed=7):
     """The CPU oracle on a sample of whole clusters, scaled to all of them by
     their share of the bodies."""
@@ -256,7 +344,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plummer_1m",
-                    choices=["plummer_1m", "plummer_4k", "kroupa_4m", "ensemble_256"])
+                    choices=["plummer_1m", "plummer_4k", "kroupa_4m", "ensemble_256", "rollout_256k"])
     ap.add_argument("--precisions", default="fp64,mixed",
                     help="comma list; the last one is the reported value")
     ap.add_argument("--root-levels", type=int, default=3)
@@ -288,6 +376,8 @@ def main():
 
     if args.workload == "ensemble_256":
         return run_ensemble(args)
+    if args.workload == "rollout_256k":
+        return run_rollout(args)
     cfg = W.CONFIGS[args.workload]
     n, p, err_tol = cfg["n"], cfg["p"], cfg["err_tol"]
     if args.workload == "kroupa_4m":

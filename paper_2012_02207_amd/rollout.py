@@ -58,8 +58,8 @@ def leapfrog(pos, vel, mass, solver, dt, steps, eps_soft=0.0, checkpoint_every=8
     x, v = pos, vel
     done = 0
     while done < steps:
-        k = min(checkpoint_every, steps - done)
-        if checkpoint_every and torch.is_grad_enabled():
+        k = min(checkpoint_every, steps - done) if checkpoint_every > 0 else steps - done
+        if checkpoint_every > 0 and torch.is_grad_enabled():
             x, v, a = checkpoint(_segment, x, v, a, mass, solver, dt, k, eps_soft, use_reentrant=False)
         else:
             x, v, a = _segment(x, v, a, mass, solver, dt, k, eps_soft)
