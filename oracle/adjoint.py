@@ -80,6 +80,33 @@ def direct_adjoint(pos, mass, gacc, gpot=None, eps_soft=0.0, block=512):
     return gx, gm
 
 
+def direct_jerk(pos, vel, mass, eps_soft=0.0, block=512):
+    """Time derivative of a_i along the motion (the jerk):
+    j_i = sum_{j != i} m_j [w_ij / s^3 - 3 (u_ij . w_ij) u_ij / s^5],
+    u_ij = x_j - x_i, w_ij = v_j - v_i, differentiating a_i's defining sum."""
+    pos = np.asarray(pos, dtype=np.float64)
+    vel = np.asarray(vel, dtype=np.float64)
+    mass = np.asarray(mass, dtype=np.float64)
+    n = len(mass)
+    jerk = np.zeros((n, 3))
+    e2 = float(eps_soft) ** 2
+    for b0 in range(0, n, block):
+        b1 = min(n, b0 + block)
+        u = pos[None, :, :] - pos[b0:b1, None, :]
+        w = vel[None, :, :] - vel[b0:b1, None, :]
+        s2 = np.einsum("abc,abc->ab", u, u) + e2
+        ok = s2 > 0
+        ok[np.arange(b1 - b0), np.arange(b0, b1)] = False
+        inv = np.zeros_like(s2)
+        inv[ok] = 1.0 / np.sqrt(s2[ok])
+        inv3 = inv ** 3
+        inv5 = inv3 * inv * inv
+        uw = np.einsum("abc,abc->ab", u, w)
+        jerk[b0:b1] = ((mass[None, :] * inv3)[:, :, None] * w
+                       - 3.0 * (mass[None, :] * uw * inv5)[:, :, None] * u).sum(axis=1)
+    return jerk
+
+
 def leapfrog(pos, vel, mass, dt, steps, eps_soft=0.0, forces=direct_forces):
     """Kick-drift-kick leapfrog; returns the final positions and velocities."""
     x = np.array(pos, dtype=np.float64)

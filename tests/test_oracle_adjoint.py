@@ -98,3 +98,33 @@ def test_rollout_gradient_matches_finite_differences():
         e[k] = h
         fm = (loss(pos, vel, mass + e) - loss(pos, vel, mass - e)) / (2 * h)
         assert abs(gm[k] - fm) <= 1e-6 * max(1.0, abs(fm))
+
+
+def test_jerk_matches_time_difference_of_forces():
+    """j = da/dt along the motion: central difference of a(x + v t) in t."""
+    rng = np.random.default_rng(12)
+    n = 40
+    pos = rng.normal(size=(n, 3))
+    vel = rng.normal(size=(n, 3))
+    mass = rng.uniform(0.5, 1.5, n)
+    for eps in (0.0, 0.1):
+        j = A.direct_jerk(pos, vel, mass, eps)
+        h = 1e-5
+        ap, _ = A.direct_forces(pos + h * vel, mass, eps)
+        am, _ = A.direct_forces(pos - h * vel, mass, eps)
+        fd = (ap - am) / (2 * h)
+        assert np.abs(j - fd).max() <= 1e-7 * np.abs(fd).max()
+
+
+def test_jerk_galilean_invariance_and_two_body():
+    pos, vel, mass = W.plummer(200, 21)
+    j1 = A.direct_jerk(pos, vel, mass)
+    j2 = A.direct_jerk(pos, vel + np.array([0.3, -1.0, 2.0]), mass)
+    assert np.abs(j1 - j2).max() <= 1e-12 * np.abs(j1).max()
+    x = np.array([[0.0, 0.0, 0.0], [1.0, 2.0, -2.0]])
+    v = np.array([[0.1, 0.0, 0.0], [0.0, 0.5, 0.0]])
+    m = np.array([1.0, 2.0])
+    u, w = x[1] - x[0], v[1] - v[0]
+    r = np.linalg.norm(u)
+    want = m[1] * (w / r ** 3 - 3 * np.dot(u, w) * u / r ** 5)
+    assert np.allclose(A.direct_jerk(x, v, m)[0], want, rtol=1e-14, atol=0)
