@@ -169,6 +169,18 @@ fmm_status fmm_adjoint(fmm_ctx* ctx, int64_t n, const double* pos, const double*
                        int p, double err_tol, const double* gacc, const double* gpot, double* gpos,
                        double* gmass, void* stream);
 
+/* Forces and their time derivative along the motion (the jerk, for
+ * fourth-order Hermite integrators; section 5 of the paper):
+ * jerk_k = sum_j m_j [w / s^3 - 3 (u . w) u / s^5], u = x_j - x_k,
+ * w = v_j - v_k.  vel (n x 3) is a device buffer in the caller's order; acc,
+ * pot and jerk are written like fmm_forces' outputs.  The far field is the
+ * tidal tensor of the force pass applied to v_k plus the field gradient of
+ * the dipoles m_j v_j, the second from an expansion pass on the same tree and
+ * lists (the operator of fmm_adjoint).  FP64; errors as fmm_adjoint. */
+fmm_status fmm_jerk(fmm_ctx* ctx, int64_t n, const double* pos, const double* vel, const double* mass,
+                    double eps_soft, int p, double err_tol, double* acc, double* pot, double* jerk,
+                    void* stream);
+
 /* Largest number of systems one fmm_forces_batch call accepts. */
 #define FMM_MAX_SYSTEMS 65536
 

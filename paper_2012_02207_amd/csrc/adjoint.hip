@@ -17,6 +17,10 @@
 // relations d/dz Y_n^m = Y_{n-1}^m, (d/dx + i d/dy) Y_n^m = Y_{n-1}^{m+1},
 // (d/dx - i d/dy) Y_n^m = -Y_{n-1}^{m-1}), followed by the same M2M, M2L
 // (FP64) and L2L.  The near field sums the softened pair terms directly.
+//
+// The jerk (da_k/dt along the motion, section 5) is the same operator:
+// da_k/dt = T_k v_k + sum_j K(x_j - x_k) m_j v_j, the tidal tensor applied to
+// the body's own velocity plus the field gradient of the dipoles m_j v_j.
 #include <hip/hip_runtime.h>
 
 #include "fmm_device.h"
@@ -60,6 +64,18 @@ __global__ void k_adj_gather(int64_t n, const int* perm, const double* gacc, con
   int64_t o = perm[i];
   gs[i] = make_double4(gacc[3 * o], gacc[3 * o + 1], gacc[3 * o + 2], gpot ? gpot[o] : 0.0);
   as[i] = make_double4(acc[3 * o], acc[3 * o + 1], acc[3 * o + 2], 0.0);
+}
+
+// jerk: the tidal tensor acts on the body's velocity, the sources are the
+// dipoles -m_j v_j (charge 0), so that grad Psi = sum_j K(x_j - x_k) m_j v_j
+__global__ void k_jerk_gather(int64_t n, const int* perm, const double* vel, const double* mass,
+                              double4* tv, double4* src) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t o = perm[i];
+  double vx = vel[3 * o], vy = vel[3 * o + 1], vz = vel[3 * o + 2], m = mass[o];
+  tv[i] = make_double4(vx, vy, vz, 0.0);
+  src[i] = make_double4(m * vx, m * vy, m * vz, 0.0);
 }
 
 // P2M of charges q = gp and dipoles d = -ga at the leaf's centre:
@@ -218,7 +234,12 @@ __device__ __forceinline__ double rsqrt_fp64(double x) {
   return y;
 }
 
-// one thread per body (sorted order); results in the caller's order
+// One thread per body (sorted order); results in the caller's order.
+// tv[i]: the vector the tidal tensor acts on (ga_i; in the jerk, v_i) and
+// gp_i in .w; src[j]: source dipole -(.xyz) and charge (.w) of body j.
+//   gradient: gpos = T ga - gp a + m grad Psi,  gmass = Psi;
+//   jerk:     jerk = T v + grad Psi.
+template <bool JERK>
 __global__ void __launch_bounds__(256) k_adj_leaf(int p, int64_t n, const int* __restrict__ leaf_of,
                                                   const int* __restrict__ cb, const int* __restrict__ ce,
                                                   const int* __restrict__ off, const int* __restrict__ srcl,
@@ -227,7 +248,8 @@ __global__ void __launch_bounds__(256) k_adj_leaf(int p, int64_t n, const int* _
                                                   const double* __restrict__ lfwd,
                                                   const double* __restrict__ ladj,
                                                   const double4* __restrict__ pm,
-                                                  const double4* __restrict__ gs,
+                                                  const double4* __restrict__ tv,
+                                                  const double4* __restrict__ src,
                                                   const double4* __restrict__ as,
                                                   const int* __restrict__ perm, double eps2, double* gpos,
                                                   double* gmass) {
@@ -235,7 +257,7 @@ __global__ void __launch_bounds__(256) k_adj_leaf(int p, int64_t n, const int* _
   if (i >= n) return;
   int B = leaf_of[i];
   int nc = ncoef(p);
-  double4 me = pm[i], g = gs[i], af = as[i];
+  double4 me = pm[i], g = tv[i];
   double X = me.x - cx[B], Y = me.y - cy[B], Z = me.z - cz[B];
   // far field: Hess Phi from the forward expansion (order 2), Psi and grad Psi
   // from the adjoint expansion (orders 0, 1)
@@ -259,7 +281,7 @@ __global__ void __launch_bounds__(256) k_adj_leaf(int p, int64_t n, const int* _
       double ux = me.x - s.x, uy = me.y - s.y, uz = me.z - s.z;
       double s2 = fma(ux, ux, fma(uy, uy, fma(uz, uz, eps2)));
       if (j == i || !(s2 > 0.0)) continue;
-      double4 gj = gs[j];
+      double4 gj = src[j];
       double inv = rsqrt_fp64(s2), inv2 = inv * inv, inv3 = inv2 * inv, inv5 = inv3 * inv2;
       double ugj = fma(ux, gj.x, fma(uy, gj.y, uz * gj.z));
       psi = fma(ugj, inv3, fma(-gj.w, inv, psi));
@@ -275,38 +297,62 @@ __global__ void __launch_bounds__(256) k_adj_leaf(int p, int64_t n, const int* _
     }
   }
   int64_t o = perm[i];
-  gpos[3 * o] = gx - kx - g.w * af.x + me.w * px;
-  gpos[3 * o + 1] = gy - ky - g.w * af.y + me.w * py;
-  gpos[3 * o + 2] = gz - kz - g.w * af.z + me.w * pz;
-  gmass[o] = psi;
+  if constexpr (JERK) {
+    gpos[3 * o] = gx - kx + px;
+    gpos[3 * o + 1] = gy - ky + py;
+    gpos[3 * o + 2] = gz - kz + pz;
+  } else {
+    double4 af = as[i];
+    gpos[3 * o] = gx - kx - g.w * af.x + me.w * px;
+    gpos[3 * o + 1] = gy - ky - g.w * af.y + me.w * py;
+    gpos[3 * o + 2] = gz - kz - g.w * af.z + me.w * pz;
+    gmass[o] = psi;
+  }
 }
 
-// the expansion pass of the adjoint sources and the leaf evaluation; the
-// forward pass (tree, lists, local expansions, acc) must be in place
-void adjoint_pass(Ctx& c, const double* gacc, const double* gpot, const double* acc_fwd, double* gpos,
-                  double* gmass) {
+// the expansion pass over the sources src (dipoles -xyz, charges w) and the
+// leaf evaluation; the forward pass (tree, lists, local expansions) must be
+// in place
+template <bool JERK>
+static void source_pass(Ctx& c, const double4* tv, const double4* src, const double4* as, double* out3,
+                        double* out1) {
   hipStream_t s = c.stream;
   int64_t n = c.n;
   int nc = (int)c.ncell;
   size_t ne = (size_t)nc * ncoef(c.p) * 2;
   ensure(c.ws, c.madj, ne);
   ensure(c.ws, c.ladj, ne);
-  ensure(c.ws, c.gsort, (size_t)n);
-  ensure(c.ws, c.asort, (size_t)n);
   unsigned g = (unsigned)ceil_div(n, 256);
-  hipLaunchKernelGGL(k_adj_gather, dim3(g), dim3(256), 0, s, n, c.idx[0].p, gacc, gpot, acc_fwd, c.gsort.p,
-                     c.asort.p);
   hipLaunchKernelGGL(k_p2m_adj, dim3((unsigned)c.nleaf), dim3(PA_T), 0, s, c.p, c.leaves.p, (int)c.nleaf,
-                     c.c_begin.p, c.c_end.p, c.pm.p, c.gsort.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.madj.p);
+                     c.c_begin.p, c.c_end.p, c.pm.p, src, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.madj.p);
   HIPCHK(hipGetLastError());
   m2m_levels(c, c.madj.p);
   HIPCHK(hipMemsetAsync(c.ladj.p, 0, ne * sizeof(double), s));
   launch_m2l_fp64_buffers(c, nc, c.madj.p, c.ladj.p);
   launch_l2l_buf(c, c.ladj.p);
-  hipLaunchKernelGGL(k_adj_leaf, dim3(g), dim3(256), 0, s, c.p, n, c.leaf_of.p, c.c_begin.p, c.c_end.p,
-                     c.p2p.off.p, c.p2p.src.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.loc.p, c.ladj.p, c.pm.p,
-                     c.gsort.p, c.asort.p, c.idx[0].p, c.eps_soft * c.eps_soft, gpos, gmass);
+  hipLaunchKernelGGL(k_adj_leaf<JERK>, dim3(g), dim3(256), 0, s, c.p, n, c.leaf_of.p, c.c_begin.p, c.c_end.p,
+                     c.p2p.off.p, c.p2p.src.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.loc.p, c.ladj.p, c.pm.p, tv,
+                     src, as, c.idx[0].p, c.eps_soft * c.eps_soft, out3, out1);
   HIPCHK(hipGetLastError());
+}
+
+void adjoint_pass(Ctx& c, const double* gacc, const double* gpot, const double* acc_fwd, double* gpos,
+                  double* gmass) {
+  int64_t n = c.n;
+  ensure(c.ws, c.gsort, (size_t)n);
+  ensure(c.ws, c.asort, (size_t)n);
+  hipLaunchKernelGGL(k_adj_gather, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c.stream, n, c.idx[0].p,
+                     gacc, gpot, acc_fwd, c.gsort.p, c.asort.p);
+  source_pass<false>(c, c.gsort.p, c.gsort.p, c.asort.p, gpos, gmass);
+}
+
+void jerk_pass(Ctx& c, const double* vel, const double* mass, double* jerk) {
+  int64_t n = c.n;
+  ensure(c.ws, c.gsort, (size_t)n);
+  ensure(c.ws, c.asort, (size_t)n);
+  hipLaunchKernelGGL(k_jerk_gather, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c.stream, n, c.idx[0].p,
+                     vel, mass, c.gsort.p, c.asort.p);
+  source_pass<true>(c, c.gsort.p, c.asort.p, nullptr, jerk, nullptr);
 }
 
 }  // namespace fmm

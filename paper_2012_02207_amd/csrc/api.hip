@@ -455,6 +455,25 @@ fmm_status fmm_adjoint(fmm_ctx* ctx, int64_t n, const double* pos, const double*
   return st;
 }
 
+fmm_status fmm_jerk(fmm_ctx* ctx, int64_t n, const double* pos, const double* vel, const double* mass,
+                    double eps_soft, int p, double err_tol, double* acc, double* pot, double* jerk,
+                    void* stream) {
+  if (!ctx || !vel || !jerk) return FMM_EINVAL;
+  Ctx& c = ctx->c;
+  if (p < 1 || p > FMM_GPU_PMAX) return p < 1 || p > 30 ? FMM_EINVAL : FMM_EUNSUPPORTED;
+  fmm_params saved = c.prm;
+  c.prm.precision = FMM_FP64;
+  int64_t off[2] = {0, n};
+  fmm_status st = forces_impl(ctx, 1, off, n, pos, mass, eps_soft, p, err_tol, acc, pot, stream);
+  if (st == FMM_OK)
+    st = guarded(ctx, [&]() {
+      jerk_pass(c, vel, mass, jerk);
+      return FMM_OK;
+    });
+  c.prm = saved;
+  return st;
+}
+
 // ---- autotuner: n_leaf per (device, precision, p, tolerance, size class) ----
 namespace {
 using TuneKey = std::tuple<int, int, int, double, int, int>;

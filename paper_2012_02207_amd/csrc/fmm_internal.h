@@ -190,5 +190,6 @@ void launch_m2l_mixed(Ctx& c);
 bool mixed_supported(int p);
 void adjoint_pass(Ctx& c, const double* gacc, const double* gpot, const double* acc_fwd, double* gpos,
                   double* gmass);
+void jerk_pass(Ctx& c, const double* vel, const double* mass, double* jerk);
 
 }  // namespace fmm

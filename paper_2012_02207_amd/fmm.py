@@ -25,7 +25,8 @@ EXPORTS = dict(keys=(0, np.uint64), perm=(1, np.int32), cell_level=(2, np.int32)
                m2l=(18, np.int32), p2p=(19, np.int32), local=(20, np.float64),
                rootbox=(21, np.float64))
 SYMBOLS = ["fmm_default_params", "fmm_create", "fmm_set_params", "fmm_build", "fmm_forces",
-           "fmm_forces_batch", "fmm_forces_frozen", "fmm_autotune", "fmm_adjoint", "fmm_stats", "fmm_export", "fmm_set_workspace_limit",
+           "fmm_forces_batch", "fmm_forces_frozen", "fmm_autotune", "fmm_adjoint", "fmm_jerk",
+           "fmm_stats", "fmm_export", "fmm_set_workspace_limit",
            "fmm_direct", "fmm_strerror", "fmm_last_error", "fmm_destroy"]
 
 
@@ -75,6 +76,7 @@ def load_library():
                                      C.c_double, P, P, P]
     lib.fmm_autotune.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), P, P, C.c_double, C.c_int,
                                  C.c_double, P, P, P, C.POINTER(C.c_int)]
+    lib.fmm_jerk.argtypes = [P, C.c_int64, P, P, P, C.c_double, C.c_int, C.c_double, P, P, P, P]
     lib.fmm_forces_frozen.argtypes = [P, C.c_int64, P, P, C.c_double, P, P, P]
     lib.fmm_adjoint.argtypes = [P, C.c_int64, P, P, C.c_double, C.c_int, C.c_double, P, P, P, P, P]
     lib.fmm_stats.argtypes = [P, C.POINTER(Stats)]
@@ -87,7 +89,7 @@ def load_library():
     lib.fmm_last_error.restype = C.c_char_p
     lib.fmm_destroy.argtypes = [P]
     for f in ("fmm_create", "fmm_set_params", "fmm_build", "fmm_forces", "fmm_forces_batch",
-              "fmm_forces_frozen", "fmm_autotune", "fmm_adjoint", "fmm_stats", "fmm_export", "fmm_set_workspace_limit",
+              "fmm_forces_frozen", "fmm_autotune", "fmm_adjoint", "fmm_jerk", "fmm_stats", "fmm_export", "fmm_set_workspace_limit",
               "fmm_direct"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
@@ -256,6 +258,23 @@ class FMM:
             _dev_ptr(acc, torch.float64, (n, 3), "acc"), _dev_ptr(pot, torch.float64, (n,), "pot"),
             _stream()))
         return acc, pot
+
+    def jerk(self, pos, vel, mass, eps_soft=0.0, p=None, err_tol=None):
+        """(acc, pot, jerk): forces and their time derivative along the motion."""
+        torch = _torch()
+        n = mass.shape[0]
+        acc = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        pot = torch.empty((n,), dtype=torch.float64, device=pos.device)
+        jerk = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        self._check(self._lib.fmm_jerk(
+            self._h, n, _dev_ptr(pos, torch.float64, (n, 3), "pos"),
+            _dev_ptr(vel, torch.float64, (n, 3), "vel"), _dev_ptr(mass, torch.float64, (n,), "mass"),
+            float(eps_soft), int(self.params.p if p is None else p),
+            float(self.params.err_tol if err_tol is None else err_tol),
+            _dev_ptr(acc, torch.float64, (n, 3), "acc"), _dev_ptr(pot, torch.float64, (n,), "pot"),
+            _dev_ptr(jerk, torch.float64, (n, 3), "jerk"), _stream()))
+        self.n = n
+        return acc, pot, jerk
 
     def adjoint(self, pos, mass, gacc, gpot=None, eps_soft=0.0, p=None, err_tol=None):
         """(dL/dpos, dL/dmass) for dL/dacc = gacc and dL/dpot = gpot (or zero);

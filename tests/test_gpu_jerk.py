@@ -1,0 +1,33 @@
+"""The jerk (time derivative of the forces along the motion) of the GPU pass
+against the direct-sum jerk of the oracle, on a Plummer sphere with its
+velocities.  The far field comes from expansions accurate to the acceptance
+tolerance, so the bound follows it: median <= 10 err_tol, 99th percentile
+<= 1e3 err_tol.  The accelerations returned beside the jerk are those of
+fmm_forces, bit for bit."""
+import numpy as np
+import pytest
+
+from oracle import adjoint as A
+from paper_2012_02207_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.parametrize("eps_soft,p,tol", [(0.0, 10, 1e-7), (0.01, 8, 1e-6)])
+def test_jerk_matches_direct_sum(eps_soft, p, tol):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2012_02207_amd import fmm
+    pos, vel, mass = W.plummer(4096, 77)
+    print(f"[gpu] jerk N=4096 p={p} tol={tol} eps_soft={eps_soft}", flush=True)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    f = fmm.FMM(p=p, err_tol=tol, n_leaf=64)
+    acc, pot, jerk = f.jerk(d(pos), d(vel), d(mass), eps_soft=eps_soft)
+    a2, p2 = f.forces(d(pos), d(mass), eps_soft=eps_soft)
+    assert torch.equal(acc, a2) and torch.equal(pot, p2)
+    ref = A.direct_jerk(pos, vel, mass, eps_soft)
+    e = np.linalg.norm(jerk.cpu().numpy() - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    print(f"jerk rel error: median {np.median(e):.2e} p99 {np.percentile(e, 99):.2e}")
+    assert np.median(e) <= 10 * tol and np.percentile(e, 99) <= 1e3 * tol
+    f.close()
