@@ -40,7 +40,19 @@ void ws_free(Workspace& w, void* p, size_t bytes) {
   w.bytes -= bytes;
 }
 
-void launch_leaf_eval(Ctx& c, double* acc, double* pot);
+// launches of a scope go to another stream of the context
+struct OnStream {
+  Ctx& c;
+  hipStream_t old;
+  OnStream(Ctx& cc, hipStream_t s) : c(cc), old(cc.stream) { c.stream = s; }
+  ~OnStream() { c.stream = old; }
+};
+
+// stream `to` waits for the work enqueued so far on `from` (event e)
+static void stream_wait(hipEvent_t e, hipStream_t from, hipStream_t to) {
+  HIPCHK(hipEventRecord(e, from));
+  HIPCHK(hipStreamWaitEvent(to, e, 0));
+}
 void launch_l2l(Ctx& c);
 
 
@@ -63,22 +75,50 @@ __global__ void k_count_low_pairs(const int* off, const int* src, int ncell, int
   if (s) atomicAdd(out, s);
 }
 
+// The near field (and, in mixed precision, the FP64 M2L of the root-level
+// pairs into a buffer of its own) on the side stream run beside the main M2L
+// on the caller's stream (both ALU bound, with different occupancy limits);
+// after the join the root-level part is added, then L2L and the final L2P +
+// sum.  loc gets exactly one contribution per kernel, so the order of the two
+// M2L parts does not change the result.
+__global__ void k_add_into(double* dst, const double* src, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] += src[i];
+}
+
 void evaluate(Ctx& c, double* acc, double* pot) {
   hipStream_t s = c.stream;
   int nc = (int)c.ncell;
   size_t nl = (size_t)nc * ncoef(c.p) * 2;
+  bool mixed = c.prm.precision == FMM_MIXED;
+  bool root64 = mixed && mixed_first_lo(c) > 0;
   ensure(c.ws, c.loc, nl);
+  ensure(c.ws, c.nearbuf, (size_t)c.n);
+  if (root64) ensure(c.ws, c.loc64, nl);
+  stream_wait(c.fork[2], s, c.side);
+  {
+    OnStream on(c, c.side);
+    if (c.have_events) HIPCHK(hipEventRecord(c.ev[6], c.side));
+    launch_near_field(c);
+    if (c.have_events) HIPCHK(hipEventRecord(c.ev[7], c.side));
+    if (root64) launch_m2l_mixed_root(c, c.loc64.p);
+  }
   if (c.have_events) HIPCHK(hipEventRecord(c.ev[4], s));
   HIPCHK(hipMemsetAsync(c.loc.p, 0, nl * sizeof(double), s));
-  if (c.prm.precision == FMM_MIXED)
-    launch_m2l_mixed(c);
+  if (mixed)
+    launch_m2l_mixed_lo(c);
   else
     launch_m2l_fp64(c);
+  stream_wait(c.fork[3], c.side, s);
+  if (root64)
+    hipLaunchKernelGGL(k_add_into, dim3((unsigned)ceil_div((int64_t)nl, 256)), dim3(256), 0, s, c.loc.p,
+                       c.loc64.p, (int64_t)nl);
   if (c.have_events) HIPCHK(hipEventRecord(c.ev[5], s));
   launch_l2l(c);
-  if (c.have_events) HIPCHK(hipEventRecord(c.ev[6], s));
-  launch_leaf_eval(c, acc, pot);
-  if (c.have_events) HIPCHK(hipEventRecord(c.ev[7], s));
+  if (c.have_events) HIPCHK(hipEventRecord(c.ev[11], s));
+  if (c.have_events) HIPCHK(hipEventRecord(c.ev[12], s));
+  launch_far_final(c, acc, pot);
+  if (c.have_events) HIPCHK(hipEventRecord(c.ev[13], s));
 }
 
 }  // namespace fmm
@@ -145,6 +185,8 @@ fmm_status fmm_create(fmm_ctx** out, const fmm_params* prm) {
     HIPCHK(hipGetDevice(&ctx->c.device));
     HIPCHK(hipHostMalloc((void**)&ctx->c.hbuf, 128 * sizeof(long long), hipHostMallocDefault));
     for (auto& e : ctx->c.ev) HIPCHK(hipEventCreate(&e));
+    for (auto& e : ctx->c.fork) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIPCHK(hipStreamCreateWithFlags(&ctx->c.side, hipStreamNonBlocking));
     return FMM_OK;
   });
   if (st != FMM_OK) {
@@ -176,6 +218,27 @@ static void run_build(Ctx& c, int64_t n, const double* pos, const double* mass) 
   upward_pass(c);
   if (c.have_events) HIPCHK(hipEventRecord(c.ev[2], c.stream));
   c.built = true;
+}
+
+// Tree, then the upward pass (P2M, M2M, P_k) on the side stream beside the
+// scalar-force estimate on the caller's stream (the estimate needs the cells,
+// not the multipoles); joined before the acceptance walk, which needs both.
+static void build_and_estimate(Ctx& c, int64_t n, const double* pos, const double* mass) {
+  c.built = c.estimated = c.walked = c.evaluated = false;
+  build_tree(c, n, pos, mass);
+  HIPCHK(hipEventRecord(c.ev[1], c.stream));
+  stream_wait(c.fork[0], c.stream, c.side);
+  {
+    OnStream on(c, c.side);
+    upward_pass(c);
+    HIPCHK(hipEventRecord(c.ev[14], c.side));
+  }
+  c.built = true;
+  HIPCHK(hipEventRecord(c.ev[2], c.stream));
+  estimate_walk(c);
+  c.estimated = true;
+  stream_wait(c.fork[1], c.side, c.stream);
+  HIPCHK(hipEventRecord(c.ev[3], c.stream));
 }
 
 fmm_status fmm_build(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass, void* stream) {
@@ -230,10 +293,7 @@ static fmm_status forces_impl(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets
     }
     c.have_events = true;
     HIPCHK(hipEventRecord(c.ev[0], c.stream));
-    run_build(c, n, pos, mass);
-    estimate_walk(c);
-    c.estimated = true;
-    HIPCHK(hipEventRecord(c.ev[3], c.stream));
+    build_and_estimate(c, n, pos, mass);
     mac_walk(c);
     c.walked = true;
     evaluate(c, acc, pot);
@@ -278,8 +338,7 @@ fmm_status fmm_stats(fmm_ctx* ctx, fmm_stats_t* out) {
       out->n_p2p_cells = c.p2p.count;
       out->n_m2l_fp32 = 0;
       if (c.prm.precision == FMM_MIXED) {
-        int K = c.prm.root_levels;
-        int first_lo = K <= c.depth ? c.lvl_first[K] : (int)c.ncell;
+        int first_lo = mixed_first_lo(c);
         unsigned long long* d = (unsigned long long*)(c.counters.p + 48);
         HIPCHK(hipMemsetAsync(d, 0, 8, c.stream));
         int cnt = (int)c.ncell - first_lo;
@@ -312,16 +371,20 @@ fmm_status fmm_stats(fmm_ctx* ctx, fmm_stats_t* out) {
     };
     if (c.have_events) {
       out->ms_tree = el(0, 1);
-      out->ms_upward = el(1, 2);
       if (c.evaluated) {
+        // upward pass (side stream) and estimate (caller's stream) both start
+        // at the end of the tree and overlap; so do the near field (side) and
+        // M2L + L2L; ms_local is L2L plus the final L2P and sum
+        out->ms_upward = el(1, 14);
         out->ms_estimate = el(2, 3);
         out->ms_walk = el(3, 4);
         out->ms_m2l = el(4, 5);
-        out->ms_local = el(5, 6);
+        out->ms_local = el(5, 11) + el(12, 13);
         out->ms_p2p = el(6, 7);
         out->ms_total = el(0, 8);
         out->ms_m2l_kernel = el(9, 10);
       } else {
+        out->ms_upward = el(1, 2);
         out->ms_total = el(0, 2);
       }
     }
@@ -422,6 +485,7 @@ fmm_status fmm_forces_frozen(fmm_ctx* ctx, int64_t n, const double* pos, const d
     HIPCHK(hipEventRecord(c.ev[1], c.stream));
     expansions_up(c);
     HIPCHK(hipEventRecord(c.ev[2], c.stream));
+    HIPCHK(hipEventRecord(c.ev[14], c.stream));
     HIPCHK(hipEventRecord(c.ev[3], c.stream));  // no estimate, no walk
     evaluate(c, acc, pot);
     HIPCHK(hipEventRecord(c.ev[8], c.stream));
@@ -599,7 +663,7 @@ void fmm_destroy(fmm_ctx* ctx) {
     rel(c.idx[k]);
     rel(c.front[k]);
   }
-  rel(c.sx); rel(c.sy); rel(c.sz); rel(c.sm); rel(c.pm); rel(c.pkb); rel(c.scale); rel(c.nmult); rel(c.fpart); rel(c.leaf_of); rel(c.leaves); rel(c.madj); rel(c.ladj); rel(c.fwd_acc); rel(c.fwd_pot); rel(c.gsort); rel(c.asort); rel(c.sys_off); rel(c.skey[0]); rel(c.skey[1]); rel(c.spos[0]); rel(c.spos[1]); rel(c.sort_hist);
+  rel(c.sx); rel(c.sy); rel(c.sz); rel(c.sm); rel(c.pm); rel(c.pkb); rel(c.scale); rel(c.nmult); rel(c.fpart); rel(c.leaf_of); rel(c.leaves); rel(c.nearbuf); rel(c.loc64); rel(c.madj); rel(c.ladj); rel(c.fwd_acc); rel(c.fwd_pot); rel(c.gsort); rel(c.asort); rel(c.sys_off); rel(c.skey[0]); rel(c.skey[1]); rel(c.spos[0]); rel(c.spos[1]); rel(c.sort_hist);
   rel(c.bbox_part); rel(c.rootbox); rel(c.c_level); rel(c.c_begin); rel(c.c_end); rel(c.c_parent);
   rel(c.c_child0); rel(c.c_nchild); rel(c.c_split); rel(c.c_mass); rel(c.c_sx); rel(c.c_sy);
   rel(c.c_sz); rel(c.c_cx); rel(c.c_cy); rel(c.c_cz); rel(c.c_rad); rel(c.c_rad2bits); rel(c.mult);
@@ -609,7 +673,13 @@ void fmm_destroy(fmm_ctx* ctx) {
     rel(L->raw); rel(L->tmp); rel(L->off); rel(L->src);
   }
   if (c.hbuf) (void)hipHostFree(c.hbuf);
+  if (c.side) {
+    (void)hipStreamSynchronize(c.side);
+    (void)hipStreamDestroy(c.side);
+  }
   for (auto& e : c.ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : c.fork)
     if (e) (void)hipEventDestroy(e);
   delete ctx;
 }

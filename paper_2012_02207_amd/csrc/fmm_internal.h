@@ -136,6 +136,7 @@ struct Ctx {
   dbuf<double> pkb;   // ncell x (p+1): C(p, k) * P_k, as the acceptance test forms it
   dbuf<double> fcell, fmin;
   dbuf<double> loc;   // ncell x ncoef x 2
+  dbuf<double> loc64; // mixed precision: FP64 M2L of the root-level pairs, added to loc
   dbuf<double> scale; // mixed precision: expansion scale per cell
   dbuf<float> nmult;  // mixed precision: normalised FP32 moments, (p+1)^2 per cell
 
@@ -158,7 +159,16 @@ struct Ctx {
   long long* hbuf = nullptr;
 
   // timing
-  hipEvent_t ev[12] = {};  // stage boundaries 0..8; 9, 10 around the main M2L kernel
+  // timing events: stage boundaries 0..8 on the caller's stream; 9, 10 around
+  // the main M2L kernel; 11..13 the local stage around the join with the
+  // near field; 14 the end of the upward pass on the side stream
+  hipEvent_t ev[16] = {};
+  // second stream (default priority) for work independent of the caller's
+  // stream: the upward pass beside the estimate walk, the near field beside
+  // M2L and L2L; forked and joined with the events below
+  hipStream_t side = nullptr;
+  hipEvent_t fork[4] = {};
+  dbuf<double4> nearbuf;  // near-field (acc, pot) per sorted body
   bool have_events = false;
 };
 
@@ -186,7 +196,11 @@ void launch_m2l_fp64_range(Ctx& c, int first_lo);
 void launch_m2l_fp64_buffers(Ctx& c, int first_lo, const double* mult, double* loc);
 void m2m_levels(Ctx& c, double* mult);
 void launch_l2l_buf(Ctx& c, double* loc);
-void launch_m2l_mixed(Ctx& c);
+void launch_near_field(Ctx& c);
+void launch_far_final(Ctx& c, double* acc, double* pot);
+void launch_m2l_mixed_lo(Ctx& c);
+void launch_m2l_mixed_root(Ctx& c, double* loc64);
+int mixed_first_lo(Ctx& c);
 bool mixed_supported(int p);
 void adjoint_pass(Ctx& c, const double* gacc, const double* gpot, const double* acc_fwd, double* gpos,
                   double* gmass);

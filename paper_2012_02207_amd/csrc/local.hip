@@ -157,32 +157,25 @@ __device__ __forceinline__ void l2p_eval(int p, const double* __restrict__ L, do
   ph = -s00;
 }
 
-// P2P + L2P, one wavefront per sink leaf.  The n_B sink bodies are replicated
-// over G = 64 / n_B lane groups, and group g takes every G-th body of each
-// source leaf, so nearly every lane works even though leaves hold ~20 bodies.
-// Each source leaf is staged once in LDS with one coalesced load and read by
-// the groups as broadcasts.  The G partial sums are combined in group order
-// (deterministic); group 0 adds the far field by L2P (the leaf's local
-// expansion shifted to the body: Phi = -Re L'_0^0,
-// a = (-Re L'_1^1, -Im L'_1^1, Re L'_1^0)) and writes the caller-order result.
+// P2P, one wavefront per sink leaf.  The n_B sink bodies are replicated over
+// G = 64 / n_B lane groups, and group g takes every G-th body of each source
+// leaf, so nearly every lane works even though leaves hold ~20 bodies.  Each
+// source leaf is staged once in LDS with one coalesced load and read by the
+// groups as broadcasts.  The G partial sums are combined in group order
+// (deterministic) into the body's near-field (acc, pot), sorted order.
 // MIXED: pair arithmetic in FP32 on the separation formed in FP64 and rounded
 // once; FP32 partial sums are carried into FP64 after every source leaf
 // (blocked compensation: the FP32 error grows with the leaf, not the list).
 constexpr int LG_WAVES = 4;
 
 template <bool MIXED>
-__global__ void __launch_bounds__(64 * LG_WAVES) k_leaf_group(int p, const int* __restrict__ leaves,
+__global__ void __launch_bounds__(64 * LG_WAVES) k_leaf_group(const int* __restrict__ leaves,
                                                               int nleaves, const int* __restrict__ cb,
                                                               const int* __restrict__ ce,
                                                               const int* __restrict__ off,
                                                               const int* __restrict__ srcl,
-                                                              const double* __restrict__ cx,
-                                                              const double* __restrict__ cy,
-                                                              const double* __restrict__ cz,
-                                                              const double* __restrict__ loc,
                                                               const double4* __restrict__ pm,
-                                                              const int* __restrict__ perm, double eps2,
-                                                              double* acc, double* pot,
+                                                              double eps2, double4* nearbuf,
                                                               unsigned long long* npairs) {
   __shared__ double4 sbuf[LG_WAVES][64];
   __shared__ double rbuf[LG_WAVES][4][64];
@@ -292,22 +285,17 @@ __global__ void __launch_bounds__(64 * LG_WAVES) k_leaf_group(int p, const int* 
         tz += rbuf[wv][2][l];
         tp += rbuf[wv][3][l];
       }
-      const double* L = loc + (size_t)B * ncoef(p) * 2;
-      double ax, ay, az, ph;
-      l2p_eval(p, L, me.x - cx[B], me.y - cy[B], me.z - cz[B], ax, ay, az, ph);
-      int o = perm[i];
-      acc[3 * (int64_t)o] = ax + tx;
-      acc[3 * (int64_t)o + 1] = ay + ty;
-      acc[3 * (int64_t)o + 2] = az + tz;
-      pot[o] = ph + tp;
+      nearbuf[i] = make_double4(tx, ty, tz, tp);
     }
     __builtin_amdgcn_wave_barrier();
   }
   if (lane == 0 && pairs > 0) atomicAdd(npairs, (unsigned long long)pairs);
 }
 
-void launch_leaf_eval(Ctx& c, double* acc, double* pot) {
+// Near field of every body into c.nearbuf (sorted order), on c.stream.
+void launch_near_field(Ctx& c) {
   if (c.nleaf <= 0) return;
+  ensure(c.ws, c.nearbuf, (size_t)c.n);
   const int* leaves = c.leaves.p;
   // body-pair count of the near field, read by fmm_stats
   unsigned long long* npairs = (unsigned long long*)(c.counters.p + 40);
@@ -316,13 +304,40 @@ void launch_leaf_eval(Ctx& c, double* acc, double* pot) {
   unsigned grid = 8u * (unsigned)((nblk + 7) / 8);
   double e2 = c.eps_soft * c.eps_soft;
   if (c.prm.precision == FMM_MIXED)
-    hipLaunchKernelGGL(k_leaf_group<true>, dim3(grid), dim3(64 * LG_WAVES), 0, c.stream, c.p, leaves,
-                       (int)c.nleaf, c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.c_cx.p, c.c_cy.p,
-                       c.c_cz.p, c.loc.p, c.pm.p, c.idx[0].p, e2, acc, pot, npairs);
+    hipLaunchKernelGGL(k_leaf_group<true>, dim3(grid), dim3(64 * LG_WAVES), 0, c.stream, leaves, (int)c.nleaf,
+                       c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.pm.p, e2, c.nearbuf.p, npairs);
   else
-    hipLaunchKernelGGL(k_leaf_group<false>, dim3(grid), dim3(64 * LG_WAVES), 0, c.stream, c.p, leaves,
-                       (int)c.nleaf, c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.c_cx.p, c.c_cy.p,
-                       c.c_cz.p, c.loc.p, c.pm.p, c.idx[0].p, e2, acc, pot, npairs);
+    hipLaunchKernelGGL(k_leaf_group<false>, dim3(grid), dim3(64 * LG_WAVES), 0, c.stream, leaves, (int)c.nleaf,
+                       c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.pm.p, e2, c.nearbuf.p, npairs);
+  HIPCHK(hipGetLastError());
+}
+
+// Far field by L2P (the leaf's local expansion shifted to the body:
+// Phi = -Re L'_0^0, a = (-Re L'_1^1, -Im L'_1^1, Re L'_1^0)) plus the near
+// field, summed in FP64 and written in the caller's order; one thread per body.
+__global__ void __launch_bounds__(256) k_far_final(int p, int64_t n, const int* __restrict__ leaf_of,
+                                                   const double* __restrict__ cx, const double* __restrict__ cy,
+                                                   const double* __restrict__ cz, const double* __restrict__ loc,
+                                                   const double4* __restrict__ pm,
+                                                   const double4* __restrict__ nearbuf,
+                                                   const int* __restrict__ perm, double* acc, double* pot) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int B = leaf_of[i];
+  double4 me = pm[i], nf = nearbuf[i];
+  double ax, ay, az, ph;
+  l2p_eval(p, loc + (size_t)B * ncoef(p) * 2, me.x - cx[B], me.y - cy[B], me.z - cz[B], ax, ay, az, ph);
+  int64_t o = perm[i];
+  acc[3 * o] = ax + nf.x;
+  acc[3 * o + 1] = ay + nf.y;
+  acc[3 * o + 2] = az + nf.z;
+  pot[o] = ph + nf.w;
+}
+
+void launch_far_final(Ctx& c, double* acc, double* pot) {
+  hipLaunchKernelGGL(k_far_final, dim3((unsigned)ceil_div(c.n, 256)), dim3(256), 0, c.stream, c.p, c.n,
+                     c.leaf_of.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.loc.p, c.pm.p, c.nearbuf.p, c.idx[0].p,
+                     acc, pot);
   HIPCHK(hipGetLastError());
 }
 

@@ -419,7 +419,7 @@ bool mixed_supported(int p) { return p >= 1 && p <= FMM_GPU_PMAX; }
 
 void launch_m2l_fp64_range(Ctx& c, int first_lo);
 
-void launch_m2l_mixed(Ctx& c) {
+void launch_m2l_mixed_lo(Ctx& c) {
   if (!g_mx_tables) {
     // orthogonal swap matrices G W_n G^-1 in FP32, structural non-zeros only
     std::vector<float> cs;
@@ -434,10 +434,7 @@ void launch_m2l_mixed(Ctx& c) {
     g_mx_tables = true;
   }
   int nc = (int)c.ncell;
-  int K = c.prm.root_levels;
-  int first_lo = K <= c.depth ? c.lvl_first[K] : nc;
-  // FP64 for every pair touching a root-level cell (overwrites loc)
-  launch_m2l_fp64_range(c, first_lo);
+  int first_lo = mixed_first_lo(c);
   if (first_lo >= nc) {
     if (c.have_events) {  // no FP32 pairs: the main M2L kernel time is zero
       HIPCHK(hipEventRecord(c.ev[9], c.stream));
@@ -455,6 +452,20 @@ void launch_m2l_mixed(Ctx& c) {
   if (!dispatch32<1>(c, first_lo)) throw hip_error{hipErrorInvalidValue, "M2L order not compiled"};
   HIPCHK(hipGetLastError());
   if (c.have_events) HIPCHK(hipEventRecord(c.ev[10], c.stream));
+}
+
+// first cell below the root levels (ids are breadth first)
+int mixed_first_lo(Ctx& c) {
+  int K = c.prm.root_levels;
+  return K <= c.depth ? c.lvl_first[K] : (int)c.ncell;
+}
+
+// FP64 M2L of every pair touching a root-level cell into loc64 (zeroed here),
+// for sinks that have such pairs
+void launch_m2l_mixed_root(Ctx& c, double* loc64) {
+  size_t nl = (size_t)c.ncell * ncoef(c.p) * 2;
+  HIPCHK(hipMemsetAsync(loc64, 0, nl * sizeof(double), c.stream));
+  launch_m2l_fp64_buffers(c, mixed_first_lo(c), c.mult.p, loc64);
 }
 
 }  // namespace fmm
