@@ -166,6 +166,47 @@ __device__ __forceinline__ void l2p_eval(int p, const double* __restrict__ L, do
 // MIXED: pair arithmetic in FP32 on the separation formed in FP64 and rounded
 // once; FP32 partial sums are carried into FP64 after every source leaf
 // (blocked compensation: the FP32 error grows with the leaf, not the list).
+// one source body s (mass ms) acting on the sink me
+__device__ __forceinline__ void pair32(const double4& s, float ms, const double4& me, float eps2f, float& fx,
+                                       float& fy, float& fz, float& fp) {
+  float dx = (float)(s.x - me.x), dy = (float)(s.y - me.y), dz = (float)(s.z - me.z);
+  float d2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f)));
+  float rinv = __builtin_amdgcn_rsqf(d2);
+  rinv = d2 > 0.f ? rinv : 0.f;
+  float mr = ms * rinv;
+  float mr3 = mr * rinv * rinv;
+  fx = fmaf(mr3, dx, fx);
+  fy = fmaf(mr3, dy, fy);
+  fz = fmaf(mr3, dz, fz);
+  fp -= mr;
+}
+
+__device__ __forceinline__ void pair64(const double4& s, double ms, const double4& me, double eps2, double& nx,
+                                       double& ny, double& nz, double& np) {
+  double dx = s.x - me.x, dy = s.y - me.y, dz = s.z - me.z;
+  double d2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+  double rinv = rsqrt_d(d2);
+  rinv = d2 > 0.0 ? rinv : 0.0;
+  double mr = ms * rinv;
+  double mr3 = mr * rinv * rinv;
+  nx = fma(mr3, dx, nx);
+  ny = fma(mr3, dy, ny);
+  nz = fma(mr3, dz, nz);
+  np -= mr;
+}
+
+// staged source record: FP64 position; in mixed mode the mass is rounded to
+// FP32 once here and kept in the low word of .w
+template <bool MIXED>
+__device__ __forceinline__ double4 stage(double4 v) {
+  if constexpr (MIXED) v.w = __longlong_as_double((long long)__float_as_uint((float)v.w));
+  return v;
+}
+
+__device__ __forceinline__ float mass32(const double4& v) {
+  return __uint_as_float((unsigned)__double_as_longlong(v.w));
+}
+
 constexpr int LG_WAVES = 4;
 
 template <bool MIXED>
@@ -208,7 +249,7 @@ __global__ void __launch_bounds__(64 * LG_WAVES) k_leaf_group(const int* __restr
       je = ce[A];
     }
     double4 cur = make_double4(0.0, 0.0, 0.0, 0.0);
-    if (q < qe && lane < je - j0) cur = pm[j0 + lane];
+    if (q < qe && lane < je - j0) cur = stage<MIXED>(pm[j0 + lane]);
     while (q < qe) {
       int na = min(64, je - j0);
       pairs += (long long)nB * na - max(0, min(i0 + nB, j0 + na) - max(i0, j0));
@@ -226,33 +267,38 @@ __global__ void __launch_bounds__(64 * LG_WAVES) k_leaf_group(const int* __restr
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the staged chunk is visible to the wave
       cur = make_double4(0.0, 0.0, 0.0, 0.0);
-      if (nq < qe && lane < nje - nj0) cur = pm[nj0 + lane];
+      if (nq < qe && lane < nje - nj0) cur = stage<MIXED>(pm[nj0 + lane]);
       int tmax = act ? na : 0;
-      for (int t = g; t < tmax; t += G) {
-        double4 sb = sbuf[wv][t];
-        int j = j0 + t;
-        if constexpr (MIXED) {
-          float dx = (float)(sb.x - me.x), dy = (float)(sb.y - me.y), dz = (float)(sb.z - me.z);
-          float d2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f)));
-          float rinv = __builtin_amdgcn_rsqf(d2);
-          rinv = (j != i && d2 > 0.f) ? rinv : 0.f;
-          float mr = (float)sb.w * rinv;
-          float mr3 = mr * rinv * rinv;
-          fx = fmaf(mr3, dx, fx);
-          fy = fmaf(mr3, dy, fy);
-          fz = fmaf(mr3, dz, fz);
-          fp -= mr;
-        } else {
-          double dx = sb.x - me.x, dy = sb.y - me.y, dz = sb.z - me.z;
-          double d2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
-          double rinv = rsqrt_d(d2);
-          rinv = (j != i && d2 > 0.0) ? rinv : 0.0;
-          double mr = sb.w * rinv;
-          double mr3 = mr * rinv * rinv;
-          nx = fma(mr3, dx, nx);
-          ny = fma(mr3, dy, ny);
-          nz = fma(mr3, dz, nz);
-          np -= mr;
+      // the sink's own leaf: its pair with itself gets mass 0 (with eps = 0
+      // the d2 > 0 test also removes it); other chunks hold no sink body
+      bool self = j0 < i0 + nB && i0 < j0 + na;
+      if (self) {
+        int ti = i - j0;
+        for (int t = g; t < tmax; t += G) {
+          double4 sb = sbuf[wv][t];
+          if constexpr (MIXED)
+            pair32(sb, t != ti ? mass32(sb) : 0.f, me, eps2f, fx, fy, fz, fp);
+          else
+            pair64(sb, t != ti ? sb.w : 0.0, me, eps2, nx, ny, nz, np);
+        }
+      } else {
+        int t = g;
+        for (; t + G < tmax; t += 2 * G) {
+          double4 s0 = sbuf[wv][t], s1 = sbuf[wv][t + G];
+          if constexpr (MIXED) {
+            pair32(s0, mass32(s0), me, eps2f, fx, fy, fz, fp);
+            pair32(s1, mass32(s1), me, eps2f, fx, fy, fz, fp);
+          } else {
+            pair64(s0, s0.w, me, eps2, nx, ny, nz, np);
+            pair64(s1, s1.w, me, eps2, nx, ny, nz, np);
+          }
+        }
+        if (t < tmax) {
+          double4 s0 = sbuf[wv][t];
+          if constexpr (MIXED)
+            pair32(s0, mass32(s0), me, eps2f, fx, fy, fz, fp);
+          else
+            pair64(s0, s0.w, me, eps2, nx, ny, nz, np);
         }
       }
       if constexpr (MIXED) {
