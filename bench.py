@@ -51,12 +51,6 @@ def m2l_flops(p):
     return swaps + rots + trans
 
 
-def l2p_flops(p):
-    """per body: harmonics (about 10 per coefficient) and the three shifted
-    sums (about 20 per coefficient)"""
-    return 30 * (p + 1) * (p + 2) // 2
-
-
 P2P_FLOPS = 20   # per directed body pair: acc + pot, softened, rsqrt counted once
 
 # HBM bytes per launch of a kernel from rocprofv3 FETCH_SIZE and WRITE_SIZE runs,
@@ -64,8 +58,11 @@ P2P_FLOPS = 20   # per directed body pair: acc + pot, softened, rsqrt counted on
 # (fetch x2.0, write x1.0).  Keyed by (kernel, workload, precision); valid only
 # while the kernel's source file has the recorded SHA-1 (else reported as null).
 MEASURED_TRAFFIC = {
-    ("k_m2l_fp32", "plummer_1m", "mixed"): (496.7e6, "paper_2012_02207_amd/csrc/m2l_mixed.hip",
-                                             "1b6e7c218b5a21aec1b8a256477155d025195a63"),
+    ("k_m2l_fp32", "plummer_1m", "mixed"): (496.8e6, "paper_2012_02207_amd/csrc/m2l_mixed.hip",
+                                             "77077b7db4ba7c79f1ac37810eb46023079aa7f9"),
+    ("k_leaf_group<true> (mixed P2P)", "plummer_1m", "mixed"): (172.3e6,
+                                                                "paper_2012_02207_amd/csrc/local.hip",
+                                                                "0420ced9a76ae9926da9c781d29ecc081e55d968"),
 }
 
 
@@ -191,9 +188,9 @@ def run_ensemble(args):
     m2l_ms = float(np.mean([s["ms_m2l_kernel"] for s in R["stats"]]))
     p2p_ms = float(np.mean([s["ms_p2p"] for s in R["stats"]]))
     f_m2l = m2l_flops(p) * st["n_m2l_fp32"]
-    f_leaf = P2P_FLOPS * st["n_p2p_pairs"] + l2p_flops(p) * n
+    f_leaf = P2P_FLOPS * st["n_p2p_pairs"]
     if p2p_ms >= m2l_ms:
-        dom = {"kernel": "k_leaf_group<true> (L2P + mixed P2P)", "flop": f_leaf, "ms": p2p_ms}
+        dom = {"kernel": "k_leaf_group<true> (mixed P2P)", "flop": f_leaf, "ms": p2p_ms}
     else:
         dom = {"kernel": "k_m2l_fp32", "flop": f_m2l, "ms": m2l_ms}
     achieved = dom["flop"] / (dom["ms"] * 1e-3)
@@ -426,12 +423,12 @@ def main():
     p2p_ms = np.mean([s["ms_p2p"] for s in R["stages"]])
     n_m2l_main = st["n_m2l"] if main_pr == "fp64" else st["n_m2l_fp32"]
     f_m2l = m2l_flops(p) * n_m2l_main
-    f_leaf = P2P_FLOPS * st["n_p2p_pairs"] + l2p_flops(p) * n
+    f_leaf = P2P_FLOPS * st["n_p2p_pairs"]
     peak = PEAK_FP64 if main_pr == "fp64" else PEAK_FP32
     kname = "k_m2l_fp64" if main_pr == "fp64" else "k_m2l_fp32"
     if p2p_ms >= m2l_ms:
-        dom = {"kernel": "k_leaf_group<false> (L2P + P2P)" if main_pr == "fp64"
-                         else "k_leaf_group<true> (L2P + mixed P2P)",
+        dom = {"kernel": "k_leaf_group<false> (P2P)" if main_pr == "fp64"
+                         else "k_leaf_group<true> (mixed P2P)",
                "flop": f_leaf, "ms": p2p_ms}
     else:
         dom = {"kernel": kname, "flop": f_m2l, "ms": m2l_ms}
