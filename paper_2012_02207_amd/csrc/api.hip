@@ -96,12 +96,16 @@ void evaluate(Ctx& c, double* acc, double* pot) {
   ensure(c.ws, c.nearbuf, (size_t)c.n);
   if (root64) ensure(c.ws, c.loc64, nl);
   stream_wait(c.fork[2], s, c.side);
+  if (root64) {  // a few long interaction lists: a kernel of its own beside the others
+    HIPCHK(hipStreamWaitEvent(c.side2, c.fork[2], 0));
+    OnStream on(c, c.side2);
+    launch_m2l_mixed_root(c, c.loc64.p);
+  }
   {
     OnStream on(c, c.side);
     if (c.have_events) HIPCHK(hipEventRecord(c.ev[6], c.side));
     launch_near_field(c);
     if (c.have_events) HIPCHK(hipEventRecord(c.ev[7], c.side));
-    if (root64) launch_m2l_mixed_root(c, c.loc64.p);
   }
   if (c.have_events) HIPCHK(hipEventRecord(c.ev[4], s));
   HIPCHK(hipMemsetAsync(c.loc.p, 0, nl * sizeof(double), s));
@@ -110,6 +114,7 @@ void evaluate(Ctx& c, double* acc, double* pot) {
   else
     launch_m2l_fp64(c);
   stream_wait(c.fork[3], c.side, s);
+  if (root64) stream_wait(c.fork[4], c.side2, s);
   if (root64)
     hipLaunchKernelGGL(k_add_into, dim3((unsigned)ceil_div((int64_t)nl, 256)), dim3(256), 0, s, c.loc.p,
                        c.loc64.p, (int64_t)nl);
@@ -187,6 +192,7 @@ fmm_status fmm_create(fmm_ctx** out, const fmm_params* prm) {
     for (auto& e : ctx->c.ev) HIPCHK(hipEventCreate(&e));
     for (auto& e : ctx->c.fork) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIPCHK(hipStreamCreateWithFlags(&ctx->c.side, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&ctx->c.side2, hipStreamNonBlocking));
     return FMM_OK;
   });
   if (st != FMM_OK) {
@@ -673,10 +679,11 @@ void fmm_destroy(fmm_ctx* ctx) {
     rel(L->raw); rel(L->tmp); rel(L->off); rel(L->src);
   }
   if (c.hbuf) (void)hipHostFree(c.hbuf);
-  if (c.side) {
-    (void)hipStreamSynchronize(c.side);
-    (void)hipStreamDestroy(c.side);
-  }
+  for (hipStream_t* st : {&c.side, &c.side2})
+    if (*st) {
+      (void)hipStreamSynchronize(*st);
+      (void)hipStreamDestroy(*st);
+    }
   for (auto& e : c.ev)
     if (e) (void)hipEventDestroy(e);
   for (auto& e : c.fork)

@@ -166,8 +166,8 @@ struct Ctx {
   // second stream (default priority) for work independent of the caller's
   // stream: the upward pass beside the estimate walk, the near field beside
   // M2L and L2L; forked and joined with the events below
-  hipStream_t side = nullptr;
-  hipEvent_t fork[4] = {};
+  hipStream_t side = nullptr, side2 = nullptr;  // side2: root-level FP64 M2L
+  hipEvent_t fork[6] = {};
   dbuf<double4> nearbuf;  // near-field (acc, pot) per sorted body
   bool have_events = false;
 };
