@@ -152,6 +152,17 @@ fmm_status fmm_forces(fmm_ctx* ctx, int64_t n, const double* pos, const double* 
 fmm_status fmm_forces_frozen(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass,
                              double eps_soft, double* acc, double* pot, void* stream);
 
+/* fmm_forces_frozen replayed as a HIP graph, for step loops that keep the
+ * tree: the first call (and any call with other buffers, eps_soft or stream,
+ * or after the tree was rebuilt) runs the evaluation once eagerly, captures it
+ * on the stream and instantiates the graph; later calls launch the graph.
+ * pos, mass, acc and pot are baked into the graph, so the caller updates
+ * pos/mass in place between calls.  The graph zeroes its buffers with kernels
+ * (no memset nodes).  No stage times are recorded for replayed calls.
+ * Errors as fmm_forces_frozen. */
+fmm_status fmm_forces_frozen_graph(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass,
+                                   double eps_soft, double* acc, double* pot, void* stream);
+
 /* Gradient of the force pass: for a scalar L(acc, pot) given gacc = dL/dacc
  * (n x 3) and gpot = dL/dpot (n, or NULL for zero), writes gpos = dL/dpos
  * (n x 3) and gmass = dL/dmass (n), all device buffers in the caller's body

@@ -40,6 +40,19 @@ void ws_free(Workspace& w, void* p, size_t bytes) {
   w.bytes -= bytes;
 }
 
+// zeroing by a kernel (not hipMemsetAsync), so the sequences stay capturable
+__global__ void k_zero32(uint32_t* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+void zero_fill(Ctx& c, void* p, size_t bytes) {
+  int64_t n = (int64_t)(bytes / 4);
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_zero32, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c.stream, (uint32_t*)p, n);
+  HIPCHK(hipGetLastError());
+}
+
 // launches of a scope go to another stream of the context
 struct OnStream {
   Ctx& c;
@@ -108,7 +121,7 @@ void evaluate(Ctx& c, double* acc, double* pot) {
     if (c.have_events) HIPCHK(hipEventRecord(c.ev[7], c.side));
   }
   if (c.have_events) HIPCHK(hipEventRecord(c.ev[4], s));
-  HIPCHK(hipMemsetAsync(c.loc.p, 0, nl * sizeof(double), s));
+  zero_fill(c, c.loc.p, nl * sizeof(double));
   if (mixed)
     launch_m2l_mixed_lo(c);
   else
@@ -193,6 +206,7 @@ fmm_status fmm_create(fmm_ctx** out, const fmm_params* prm) {
     for (auto& e : ctx->c.fork) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIPCHK(hipStreamCreateWithFlags(&ctx->c.side, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&ctx->c.side2, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&ctx->c.cap, hipStreamNonBlocking));
     return FMM_OK;
   });
   if (st != FMM_OK) {
@@ -219,6 +233,7 @@ static fmm_status common_checks(fmm_ctx* ctx, int64_t n, const double* pos, cons
 
 static void run_build(Ctx& c, int64_t n, const double* pos, const double* mass) {
   c.built = c.estimated = c.walked = c.evaluated = false;
+  c.graph_valid = false;
   build_tree(c, n, pos, mass);
   if (c.have_events) HIPCHK(hipEventRecord(c.ev[1], c.stream));
   upward_pass(c);
@@ -231,6 +246,7 @@ static void run_build(Ctx& c, int64_t n, const double* pos, const double* mass) 
 // not the multipoles); joined before the acceptance walk, which needs both.
 static void build_and_estimate(Ctx& c, int64_t n, const double* pos, const double* mass) {
   c.built = c.estimated = c.walked = c.evaluated = false;
+  c.graph_valid = false;
   build_tree(c, n, pos, mass);
   HIPCHK(hipEventRecord(c.ev[1], c.stream));
   stream_wait(c.fork[0], c.stream, c.side);
@@ -474,27 +490,87 @@ fmm_status fmm_export(fmm_ctx* ctx, int what, void* host_buf, size_t bytes) {
   });
 }
 
-fmm_status fmm_forces_frozen(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass,
-                             double eps_soft, double* acc, double* pot, void* stream) {
+// the frozen-tree evaluation: bodies and cell centres refreshed from the
+// stored order, P2M, M2M, then M2L, near field, L2L and the final sum
+static void run_frozen(Ctx& c, const double* pos, const double* mass, double* acc, double* pot) {
+  if (c.have_events) HIPCHK(hipEventRecord(c.ev[0], c.stream));
+  refresh_frozen(c, pos, mass);
+  if (c.have_events) HIPCHK(hipEventRecord(c.ev[1], c.stream));
+  expansions_up(c);
+  if (c.have_events) {
+    HIPCHK(hipEventRecord(c.ev[2], c.stream));
+    HIPCHK(hipEventRecord(c.ev[14], c.stream));
+    HIPCHK(hipEventRecord(c.ev[3], c.stream));  // no estimate, no walk
+  }
+  evaluate(c, acc, pot);
+  if (c.have_events) HIPCHK(hipEventRecord(c.ev[8], c.stream));
+}
+
+static fmm_status frozen_checks(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass,
+                                double eps_soft, double* acc, double* pot) {
   fmm_status st = common_checks(ctx, n, pos, mass);
   if (st != FMM_OK) return st;
   if (!acc || !pot || !(eps_soft >= 0) || !std::isfinite(eps_soft)) return FMM_EINVAL;
+  if (!ctx->c.evaluated || ctx->c.n != n) return FMM_ENOTBUILT;
+  return FMM_OK;
+}
+
+fmm_status fmm_forces_frozen(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass,
+                             double eps_soft, double* acc, double* pot, void* stream) {
+  fmm_status st = frozen_checks(ctx, n, pos, mass, eps_soft, acc, pot);
+  if (st != FMM_OK) return st;
   Ctx& c = ctx->c;
-  if (!c.evaluated || c.n != n) return FMM_ENOTBUILT;
   return guarded(ctx, [&]() {
     c.stream = (hipStream_t)stream;
     c.err.clear();
     c.eps_soft = eps_soft;
     c.have_events = true;
-    HIPCHK(hipEventRecord(c.ev[0], c.stream));
-    refresh_frozen(c, pos, mass);
-    HIPCHK(hipEventRecord(c.ev[1], c.stream));
-    expansions_up(c);
-    HIPCHK(hipEventRecord(c.ev[2], c.stream));
-    HIPCHK(hipEventRecord(c.ev[14], c.stream));
-    HIPCHK(hipEventRecord(c.ev[3], c.stream));  // no estimate, no walk
-    evaluate(c, acc, pot);
-    HIPCHK(hipEventRecord(c.ev[8], c.stream));
+    run_frozen(c, pos, mass, acc, pot);
+    return FMM_OK;
+  });
+}
+
+fmm_status fmm_forces_frozen_graph(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass,
+                                   double eps_soft, double* acc, double* pot, void* stream) {
+  fmm_status st = frozen_checks(ctx, n, pos, mass, eps_soft, acc, pot);
+  if (st != FMM_OK) return st;
+  Ctx& c = ctx->c;
+  return guarded(ctx, [&]() {
+    c.stream = (hipStream_t)stream;
+    c.err.clear();
+    c.eps_soft = eps_soft;
+    c.have_events = false;  // no timing events inside the graph
+    const void* key[5] = {pos, mass, acc, pot, stream};
+    bool same = c.graph_valid && c.gkey_eps == eps_soft;
+    for (int k = 0; k < 5 && same; k++) same = c.gkey[k] == key[k];
+    if (!same) {
+      if (c.gexec) {
+        HIPCHK(hipGraphExecDestroy(c.gexec));
+        c.gexec = nullptr;
+      }
+      c.graph_valid = false;
+      run_frozen(c, pos, mass, acc, pot);  // eager once: every buffer is in place before capture
+      hipGraph_t g = nullptr;
+      {
+        OnStream on(c, c.cap);  // captured on a stream of the context, launched on the caller's
+        HIPCHK(hipStreamBeginCapture(c.cap, hipStreamCaptureModeRelaxed));
+        try {
+          run_frozen(c, pos, mass, acc, pot);
+        } catch (...) {
+          (void)hipStreamEndCapture(c.cap, &g);
+          if (g) (void)hipGraphDestroy(g);
+          throw;
+        }
+        HIPCHK(hipStreamEndCapture(c.cap, &g));
+      }
+      hipError_t e = hipGraphInstantiate(&c.gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      check(e, "hipGraphInstantiate");
+      for (int k = 0; k < 5; k++) c.gkey[k] = key[k];
+      c.gkey_eps = eps_soft;
+      c.graph_valid = true;
+    }
+    HIPCHK(hipGraphLaunch(c.gexec, c.stream));
     return FMM_OK;
   });
 }
@@ -679,7 +755,8 @@ void fmm_destroy(fmm_ctx* ctx) {
     rel(L->raw); rel(L->tmp); rel(L->off); rel(L->src);
   }
   if (c.hbuf) (void)hipHostFree(c.hbuf);
-  for (hipStream_t* st : {&c.side, &c.side2})
+  if (c.gexec) (void)hipGraphExecDestroy(c.gexec);
+  for (hipStream_t* st : {&c.side, &c.side2, &c.cap})
     if (*st) {
       (void)hipStreamSynchronize(*st);
       (void)hipStreamDestroy(*st);

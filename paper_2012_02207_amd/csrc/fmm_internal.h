@@ -169,6 +169,14 @@ struct Ctx {
   hipStream_t side = nullptr, side2 = nullptr;  // side2: root-level FP64 M2L
   hipEvent_t fork[6] = {};
   dbuf<double4> nearbuf;  // near-field (acc, pot) per sorted body
+
+  // replay of the frozen-tree evaluation as a HIP graph (captured per set of
+  // buffers; dropped whenever the tree is rebuilt)
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap = nullptr;  // capture stream (the caller's may be the null stream)
+  bool graph_valid = false;
+  const void* gkey[5] = {};
+  double gkey_eps = 0.0;
   bool have_events = false;
 };
 
@@ -181,7 +189,8 @@ uint32_t* radix_sort_narrow(Ctx& c, const uint64_t* in, uint32_t* b0, uint32_t* 
 void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass);
 void upward_pass(Ctx& c);
 void expansions_up(Ctx& c);
-void cell_moments(Ctx& c);
+void cell_moments(Ctx& c, bool with_radius);
+void zero_fill(Ctx& c, void* p, size_t bytes);
 void refresh_frozen(Ctx& c, const double* pos, const double* mass);
 void estimate_walk(Ctx& c);
 void mac_walk(Ctx& c);

@@ -345,7 +345,7 @@ void launch_near_field(Ctx& c) {
   const int* leaves = c.leaves.p;
   // body-pair count of the near field, read by fmm_stats
   unsigned long long* npairs = (unsigned long long*)(c.counters.p + 40);
-  HIPCHK(hipMemsetAsync(npairs, 0, sizeof(unsigned long long), c.stream));
+  zero_fill(c, npairs, sizeof(unsigned long long));
   int nblk = (int)((c.nleaf + LG_WAVES - 1) / LG_WAVES);
   unsigned grid = 8u * (unsigned)((nblk + 7) / 8);
   double e2 = c.eps_soft * c.eps_soft;

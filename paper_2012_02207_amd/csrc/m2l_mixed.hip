@@ -464,7 +464,7 @@ int mixed_first_lo(Ctx& c) {
 // for sinks that have such pairs
 void launch_m2l_mixed_root(Ctx& c, double* loc64) {
   size_t nl = (size_t)c.ncell * ncoef(c.p) * 2;
-  HIPCHK(hipMemsetAsync(loc64, 0, nl * sizeof(double), c.stream));
+  zero_fill(c, loc64, nl * sizeof(double));
   launch_m2l_fp64_buffers(c, mixed_first_lo(c), c.mult.p, loc64);
 }
 

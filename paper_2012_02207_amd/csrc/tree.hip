@@ -639,7 +639,7 @@ __global__ void k_leaf_of(const int* cb, const int* ce, const int* nch, int ncel
 static inline dim3 grid1(int64_t n, int t = 256) { return dim3((unsigned)ceil_div(n, t)); }
 
 // mass, centre of mass and radius of every cell from the sorted bodies
-void cell_moments(Ctx& c) {
+void cell_moments(Ctx& c, bool with_radius) {
   hipStream_t s = c.stream;
   int nc = (int)c.ncell, nsys = c.nsys;
   long long* tot = (long long*)c.counters.p;
@@ -660,6 +660,7 @@ void cell_moments(Ctx& c) {
                        c.c_cx.p, c.c_cy.p, c.c_cz.p);
     HIPCHK(hipGetLastError());
   }
+  if (!with_radius) return;
   // radii
   ensure(c.ws, c.c_split, (size_t)2 * nc + 64);
   int* nchunk = c.c_split.p;
@@ -674,12 +675,15 @@ void cell_moments(Ctx& c) {
 }
 
 // Positions and masses changed, tree topology, order and lists kept: the
-// sorted bodies and the cell moments are recomputed from the stored order.
+// sorted bodies, cell masses and centres are recomputed from the stored
+// order.  The radii are not (they serve the acceptance test, which is not
+// rerun, and the FP32 scaling, for which any positive size works), so the
+// sequence needs no host round trip.
 void refresh_frozen(Ctx& c, const double* pos, const double* mass) {
   hipLaunchKernelGGL(k_gather, grid1(c.n), dim3(256), 0, c.stream, pos, mass, c.idx[0].p, c.n, c.sx.p,
                      c.sy.p, c.sz.p, c.sm.p, c.pm.p);
   HIPCHK(hipGetLastError());
-  cell_moments(c);
+  cell_moments(c, false);
 }
 
 void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
@@ -787,7 +791,7 @@ void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
   c.depth = (int)c.lvl_first.size() - 1;
   int nc = (int)c.ncell;
 
-  cell_moments(c);
+  cell_moments(c, true);
   hipLaunchKernelGGL(k_leaf_of, grid1(nc), dim3(256), 0, s, c.c_begin.p, c.c_end.p, c.c_nchild.p, nc,
                      c.leaf_of.p);
   HIPCHK(hipGetLastError());

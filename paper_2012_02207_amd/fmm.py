@@ -25,7 +25,8 @@ EXPORTS = dict(keys=(0, np.uint64), perm=(1, np.int32), cell_level=(2, np.int32)
                m2l=(18, np.int32), p2p=(19, np.int32), local=(20, np.float64),
                rootbox=(21, np.float64))
 SYMBOLS = ["fmm_default_params", "fmm_create", "fmm_set_params", "fmm_build", "fmm_forces",
-           "fmm_forces_batch", "fmm_forces_frozen", "fmm_autotune", "fmm_adjoint", "fmm_jerk",
+           "fmm_forces_batch", "fmm_forces_frozen",
+           "fmm_forces_frozen_graph", "fmm_autotune", "fmm_adjoint", "fmm_jerk",
            "fmm_stats", "fmm_export", "fmm_set_workspace_limit",
            "fmm_direct", "fmm_strerror", "fmm_last_error", "fmm_destroy"]
 
@@ -78,6 +79,7 @@ def load_library():
                                  C.c_double, P, P, P, C.POINTER(C.c_int)]
     lib.fmm_jerk.argtypes = [P, C.c_int64, P, P, P, C.c_double, C.c_int, C.c_double, P, P, P, P]
     lib.fmm_forces_frozen.argtypes = [P, C.c_int64, P, P, C.c_double, P, P, P]
+    lib.fmm_forces_frozen_graph.argtypes = [P, C.c_int64, P, P, C.c_double, P, P, P]
     lib.fmm_adjoint.argtypes = [P, C.c_int64, P, P, C.c_double, C.c_int, C.c_double, P, P, P, P, P]
     lib.fmm_stats.argtypes = [P, C.POINTER(Stats)]
     lib.fmm_export.argtypes = [P, C.c_int, P, C.c_size_t]
@@ -89,7 +91,7 @@ def load_library():
     lib.fmm_last_error.restype = C.c_char_p
     lib.fmm_destroy.argtypes = [P]
     for f in ("fmm_create", "fmm_set_params", "fmm_build", "fmm_forces", "fmm_forces_batch",
-              "fmm_forces_frozen", "fmm_autotune", "fmm_adjoint", "fmm_jerk", "fmm_stats", "fmm_export", "fmm_set_workspace_limit",
+              "fmm_forces_frozen", "fmm_forces_frozen_graph", "fmm_autotune", "fmm_adjoint", "fmm_jerk", "fmm_stats", "fmm_export", "fmm_set_workspace_limit",
               "fmm_direct"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
@@ -243,8 +245,9 @@ class FMM:
         self.params.n_leaf = chosen.value
         return chosen.value
 
-    def forces_frozen(self, pos, mass, eps_soft=0.0, out=None):
-        """Forces with the tree and lists of the last evaluation kept (see fmm_forces_frozen)."""
+    def forces_frozen(self, pos, mass, eps_soft=0.0, out=None, graph=False):
+        """Forces with the tree and lists of the last evaluation kept (see fmm_forces_frozen);
+        graph=True replays the evaluation as a captured HIP graph (fmm_forces_frozen_graph)."""
         torch = _torch()
         n = mass.shape[0]
         if out is None:
@@ -252,7 +255,8 @@ class FMM:
             pot = torch.empty((n,), dtype=torch.float64, device=pos.device)
         else:
             acc, pot = out
-        self._check(self._lib.fmm_forces_frozen(
+        fn = self._lib.fmm_forces_frozen_graph if graph else self._lib.fmm_forces_frozen
+        self._check(fn(
             self._h, n, _dev_ptr(pos, torch.float64, (n, 3), "pos"),
             _dev_ptr(mass, torch.float64, (n,), "mass"), float(eps_soft),
             _dev_ptr(acc, torch.float64, (n, 3), "acc"), _dev_ptr(pot, torch.float64, (n,), "pot"),
