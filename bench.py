@@ -183,6 +183,29 @@ def run_ensemble(args):
 
     res = {"batched_mixed": run("mixed", True), "batched_fp64": run("fp64", True),
            "sequential_fp64": run("fp64", False), "sequential_mixed": run("mixed", False)}
+
+    def frozen_loop():
+        """Steps that keep the batch's tree (fmm_forces_frozen): eager launches
+        against the same sequence replayed as one captured HIP graph."""
+        f = fmm.FMM(p=p, err_tol=err_tol, n_leaf=res["batched_mixed"]["n_leaf"], precision="mixed",
+                    root_levels=args.root_levels)
+        acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        pot = torch.empty((n,), dtype=torch.float64, device=dev)
+        f.forces_batch(dpos, dmass, off, out=(acc, pot))
+        out = {}
+        for graph in (False, True):
+            for _ in range(max(1, args.warmup)):
+                f.forces_frozen(dpos, dmass, out=(acc, pot), graph=graph)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                f.forces_frozen(dpos, dmass, out=(acc, pot), graph=graph)
+            torch.cuda.synchronize()
+            out["graph" if graph else "eager"] = {"ms": 1e3 * (time.perf_counter() - t0) / args.steps}
+        f.close()
+        out["graph_speedup"] = out["eager"]["ms"] / out["graph"]["ms"]
+        return out
+    frozen = frozen_loop()
     R = res["batched_mixed"]
     st = R["stats"][-1]
     m2l_ms = float(np.mean([s["ms_m2l_kernel"] for s in R["stats"]]))
@@ -211,6 +234,7 @@ def run_ensemble(args):
                    "root_levels": args.root_levels},
         "particle_evals_per_s": R["particle_evals_per_s"],
         "forms": forms,
+        "frozen_tree_steps": frozen,
         "stages_ms": {k: round(float(np.mean([s[k] for s in R["stats"]])), 4)
                       for k in ("ms_tree", "ms_upward", "ms_estimate", "ms_walk", "ms_m2l",
                                 "ms_local", "ms_p2p", "ms_total")},
