@@ -99,7 +99,7 @@ __global__ void k_add_into(double* dst, const double* src, int64_t n) {
   if (i < n) dst[i] += src[i];
 }
 
-void evaluate(Ctx& c, double* acc, double* pot) {
+void evaluate(Ctx& c, double* acc, double* pot, bool group_m2l) {
   hipStream_t s = c.stream;
   int nc = (int)c.ncell;
   size_t nl = (size_t)nc * ncoef(c.p) * 2;
@@ -109,16 +109,17 @@ void evaluate(Ctx& c, double* acc, double* pot) {
   ensure(c.ws, c.nearbuf, (size_t)c.n);
   if (root64) ensure(c.ws, c.loc64, nl);
   stream_wait(c.fork[2], s, c.side);
-  if (root64) {  // a few long interaction lists: a kernel of its own beside the others
-    HIPCHK(hipStreamWaitEvent(c.side2, c.fork[2], 0));
-    OnStream on(c, c.side2);
-    launch_m2l_mixed_root(c, c.loc64.p);
-  }
   {
     OnStream on(c, c.side);
     if (c.have_events) HIPCHK(hipEventRecord(c.ev[6], c.side));
     launch_near_field(c);
     if (c.have_events) HIPCHK(hipEventRecord(c.ev[7], c.side));
+  }
+  if (group_m2l) group_list(c, c.m2l);  // beside the near field
+  if (root64) {  // a few long interaction lists: a kernel of its own beside the others
+    stream_wait(c.fork[5], s, c.side2);
+    OnStream on(c, c.side2);
+    launch_m2l_mixed_root(c, c.loc64.p);
   }
   if (c.have_events) HIPCHK(hipEventRecord(c.ev[4], s));
   zero_fill(c, c.loc.p, nl * sizeof(double));
@@ -317,8 +318,9 @@ static fmm_status forces_impl(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets
     HIPCHK(hipEventRecord(c.ev[0], c.stream));
     build_and_estimate(c, n, pos, mass);
     mac_walk(c);
+    group_list(c, c.p2p);  // the near field starts first; the M2L list is grouped beside it
     c.walked = true;
-    evaluate(c, acc, pot);
+    evaluate(c, acc, pot, true);
     c.evaluated = true;
     HIPCHK(hipEventRecord(c.ev[8], c.stream));
     return FMM_OK;
@@ -502,7 +504,7 @@ static void run_frozen(Ctx& c, const double* pos, const double* mass, double* ac
     HIPCHK(hipEventRecord(c.ev[14], c.stream));
     HIPCHK(hipEventRecord(c.ev[3], c.stream));  // no estimate, no walk
   }
-  evaluate(c, acc, pot);
+  evaluate(c, acc, pot, false);
   if (c.have_events) HIPCHK(hipEventRecord(c.ev[8], c.stream));
 }
 

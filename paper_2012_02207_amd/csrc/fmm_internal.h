@@ -193,8 +193,10 @@ void cell_moments(Ctx& c, bool with_radius);
 void zero_fill(Ctx& c, void* p, size_t bytes);
 void refresh_frozen(Ctx& c, const double* pos, const double* mass);
 void estimate_walk(Ctx& c);
-void mac_walk(Ctx& c);
-void evaluate(Ctx& c, double* acc, double* pot);
+void mac_walk(Ctx& c);  // lists left ungrouped: see group_list
+void group_list(Ctx& c, CellList& L);
+void evaluate(Ctx& c, double* acc, double* pot, bool group_m2l);
+void launch_normalize32(Ctx& c);
 void direct_sum(int64_t n, const double* pos, const double* mass, double eps2, int64_t nsink,
                 const int32_t* sinks, double* acc, double* pot, hipStream_t s);
 bool check_inputs_dev(Ctx& c, const double* pos, const double* mass, int64_t n);

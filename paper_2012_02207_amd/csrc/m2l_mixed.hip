@@ -442,16 +442,23 @@ void launch_m2l_mixed_lo(Ctx& c) {
     }
     return;
   }
+  if (c.have_events) HIPCHK(hipEventRecord(c.ev[9], c.stream));
+  if (!dispatch32<1>(c, first_lo)) throw hip_error{hipErrorInvalidValue, "M2L order not compiled"};
+  HIPCHK(hipGetLastError());
+  if (c.have_events) HIPCHK(hipEventRecord(c.ev[10], c.stream));
+}
+
+// expansion scales and normalised FP32 moments of every cell (mixed
+// precision); run with the upward pass, as soon as the multipoles exist
+void launch_normalize32(Ctx& c) {
+  int nc = (int)c.ncell;
   ensure(c.ws, c.scale, (size_t)nc);
   ensure(c.ws, c.nmult, (size_t)nc * (c.p + 1) * (c.p + 1));
   hipLaunchKernelGGL(k_scale, dim3((nc + 255) / 256), dim3(256), 0, c.stream, nc, c.c_rad.p, c.scale.p);
   int64_t tot = (int64_t)nc * (c.p + 1) * (c.p + 1);
   hipLaunchKernelGGL(k_normalize32, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, c.stream, c.p, nc,
                      c.mult.p, c.scale.p, c.nmult.p);
-  if (c.have_events) HIPCHK(hipEventRecord(c.ev[9], c.stream));
-  if (!dispatch32<1>(c, first_lo)) throw hip_error{hipErrorInvalidValue, "M2L order not compiled"};
   HIPCHK(hipGetLastError());
-  if (c.have_events) HIPCHK(hipEventRecord(c.ev[10], c.stream));
 }
 
 // first cell below the root levels (ids are breadth first)

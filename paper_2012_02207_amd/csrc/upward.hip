@@ -286,6 +286,7 @@ void expansions_up(Ctx& c) {
   hipLaunchKernelGGL(k_pk, dim3((unsigned)ceil_div(npk, 256)), dim3(256), 0, s, p, nc, c.mult.p, c.pk.p,
                      c.pkb.p);
   HIPCHK(hipGetLastError());
+  if (c.prm.precision == FMM_MIXED && mixed_supported(p)) launch_normalize32(c);
 }
 
 }  // namespace fmm

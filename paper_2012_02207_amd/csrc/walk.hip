@@ -276,7 +276,7 @@ static void group_by_sink(Ctx& c, CellList& L) {
 }
 
 template <int KIND, int P>
-static void run_walk(Ctx& c, CellList& acc, CellList& nearl) {
+static void run_walk(Ctx& c, CellList& acc, CellList& nearl, bool group) {
   hipStream_t s = c.stream;
   CellView v{};
   v.nch = c.c_nchild.p;
@@ -344,8 +344,10 @@ static void run_walk(Ctx& c, CellList& acc, CellList& nearl) {
   }
   acc.count = nacc;
   nearl.count = nnear;
-  group_by_sink(c, acc);
-  group_by_sink(c, nearl);
+  if (group) {
+    group_by_sink(c, acc);
+    group_by_sink(c, nearl);
+  }
 }
 
 // ---- scalar-force estimate -----------------------------------------------
@@ -466,7 +468,7 @@ void estimate_walk(Ctx& c) {
   ensure(c.ws, c.fcell, nc);
   ensure(c.ws, c.fmin, nc);
   ensure(c.ws, c.fpart, (size_t)c.n);
-  run_walk<0, 0>(c, c.est_far, c.est_near);
+  run_walk<0, 0>(c, c.est_far, c.est_near, true);
   hipLaunchKernelGGL(k_fcell, dim3((nc + 255) / 256), dim3(256), 0, s, nc, c.est_far.off.p,
                      c.est_far.src.p, c.c_mass.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.fcell.p);
   {
@@ -490,12 +492,15 @@ static bool mac_dispatch(Ctx& c) {
     return false;
   } else {
     if (c.p == P) {
-      run_walk<1, P>(c, c.m2l, c.p2p);
+      run_walk<1, P>(c, c.m2l, c.p2p, false);  // grouped by the caller (group_list)
       return true;
     }
     return mac_dispatch<P + 1>(c);
   }
 }
+
+// the acceptance walk's list grouped by sink (CSR, sources ascending)
+void group_list(Ctx& c, CellList& L) { group_by_sink(c, L); }
 
 void mac_walk(Ctx& c) {
   if (!mac_dispatch<1>(c)) throw hip_error{hipErrorInvalidValue, "walk order not compiled"};

@@ -197,6 +197,35 @@ def test_errors(fmm):
     assert torch.isfinite(acc).all()
 
 
+def test_errors_of_the_other_entry_points(fmm):
+    F = fmm
+    pos, vel, mass = W.plummer(300, 4)
+    f = F.FMM(p=4)
+    # frozen evaluation needs a previous evaluation of the same size
+    with pytest.raises(F.FmmError) as e:
+        f.forces_frozen(_dev(pos), _dev(mass))
+    assert e.value.status == F.FMM_ENOTBUILT
+    f.forces(_dev(pos), _dev(mass))
+    with pytest.raises(F.FmmError) as e:
+        f.forces_frozen(_dev(pos[:200]), _dev(mass[:200]))
+    assert e.value.status == F.FMM_ENOTBUILT
+    # batches: offsets must start at 0, increase strictly and end at n
+    for off in ([0, 100, 100, 300], [5, 300], [0, 200, 100, 300]):
+        with pytest.raises((F.FmmError, ValueError)):
+            f.forces_batch(_dev(pos), _dev(mass), np.array(off))
+    # orders without a compiled kernel
+    with pytest.raises(F.FmmError) as e:
+        f.adjoint(_dev(pos), _dev(mass), _dev(np.ones((300, 3))), p=20)
+    assert e.value.status == F.FMM_EUNSUPPORTED
+    with pytest.raises(F.FmmError) as e:
+        f.jerk(_dev(pos), _dev(vel), _dev(mass), p=0)
+    assert e.value.status == F.FMM_EINVAL
+    # still usable
+    a, _ = f.forces(_dev(pos), _dev(mass))
+    assert torch.isfinite(a).all()
+    f.close()
+
+
 # ---------------------------------------------------------------- mixed precision
 # Mixed precision keeps keys, tree, P2M/M2M, the estimate and the acceptance test
 # in FP64, so its interaction lists equal the FP64 ones.  Its forces are compared
