@@ -91,14 +91,9 @@ __global__ void k_count_low_pairs(const int* off, const int* src, int ncell, int
 // The near field (and, in mixed precision, the FP64 M2L of the root-level
 // pairs into a buffer of its own) on the side stream run beside the main M2L
 // on the caller's stream (both ALU bound, with different occupancy limits);
-// after the join the root-level part is added, then L2L and the final L2P +
-// sum.  loc gets exactly one contribution per kernel, so the order of the two
-// M2L parts does not change the result.
-__global__ void k_add_into(double* dst, const double* src, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] += src[i];
-}
-
+// after the join the root-level part is added (for the sinks that have one),
+// then L2L and the final L2P + sum.  loc gets exactly one contribution per
+// kernel, so the order of the two M2L parts does not change the result.
 void evaluate(Ctx& c, double* acc, double* pot, bool group_m2l) {
   hipStream_t s = c.stream;
   int nc = (int)c.ncell;
@@ -129,9 +124,7 @@ void evaluate(Ctx& c, double* acc, double* pot, bool group_m2l) {
     launch_m2l_fp64(c);
   stream_wait(c.fork[3], c.side, s);
   if (root64) stream_wait(c.fork[4], c.side2, s);
-  if (root64)
-    hipLaunchKernelGGL(k_add_into, dim3((unsigned)ceil_div((int64_t)nl, 256)), dim3(256), 0, s, c.loc.p,
-                       c.loc64.p, (int64_t)nl);
+  if (root64) add_root_locals(c, c.loc.p, c.loc64.p);
   if (c.have_events) HIPCHK(hipEventRecord(c.ev[5], s));
   launch_l2l(c);
   if (c.have_events) HIPCHK(hipEventRecord(c.ev[11], s));
@@ -747,7 +740,7 @@ void fmm_destroy(fmm_ctx* ctx) {
     rel(c.idx[k]);
     rel(c.front[k]);
   }
-  rel(c.sx); rel(c.sy); rel(c.sz); rel(c.sm); rel(c.pm); rel(c.pkb); rel(c.scale); rel(c.nmult); rel(c.fpart); rel(c.leaf_of); rel(c.leaves); rel(c.nearbuf); rel(c.loc64); rel(c.madj); rel(c.ladj); rel(c.fwd_acc); rel(c.fwd_pot); rel(c.gsort); rel(c.asort); rel(c.sys_off); rel(c.skey[0]); rel(c.skey[1]); rel(c.spos[0]); rel(c.spos[1]); rel(c.sort_hist);
+  rel(c.sx); rel(c.sy); rel(c.sz); rel(c.sm); rel(c.pm); rel(c.pkb); rel(c.scale); rel(c.nmult); rel(c.fpart); rel(c.leaf_of); rel(c.leaves); rel(c.nearbuf); rel(c.loc64); rel(c.root_sinks); rel(c.madj); rel(c.ladj); rel(c.fwd_acc); rel(c.fwd_pot); rel(c.gsort); rel(c.asort); rel(c.sys_off); rel(c.skey[0]); rel(c.skey[1]); rel(c.spos[0]); rel(c.spos[1]); rel(c.sort_hist);
   rel(c.bbox_part); rel(c.rootbox); rel(c.c_level); rel(c.c_begin); rel(c.c_end); rel(c.c_parent);
   rel(c.c_child0); rel(c.c_nchild); rel(c.c_split); rel(c.c_mass); rel(c.c_sx); rel(c.c_sy);
   rel(c.c_sz); rel(c.c_cx); rel(c.c_cy); rel(c.c_cz); rel(c.c_rad); rel(c.c_rad2bits); rel(c.mult);

@@ -137,6 +137,7 @@ struct Ctx {
   dbuf<double> fcell, fmin;
   dbuf<double> loc;   // ncell x ncoef x 2
   dbuf<double> loc64; // mixed precision: FP64 M2L of the root-level pairs, added to loc
+  dbuf<int> root_sinks;  // mixed precision: the sinks that have root-level pairs
   dbuf<double> scale; // mixed precision: expansion scale per cell
   dbuf<float> nmult;  // mixed precision: normalised FP32 moments, (p+1)^2 per cell
 
@@ -205,12 +206,15 @@ bool check_inputs_dev(Ctx& c, const double* pos, const double* mass, int64_t n);
 void launch_m2l_fp64(Ctx& c);
 void launch_m2l_fp64_range(Ctx& c, int first_lo);
 void launch_m2l_fp64_buffers(Ctx& c, int first_lo, const double* mult, double* loc);
+void launch_m2l_fp64_sinks(Ctx& c, int first_lo, const double* mult, double* loc, const int* sinks,
+                           const int* nsinks);
 void m2m_levels(Ctx& c, double* mult);
 void launch_l2l_buf(Ctx& c, double* loc);
 void launch_near_field(Ctx& c);
 void launch_far_final(Ctx& c, double* acc, double* pot);
 void launch_m2l_mixed_lo(Ctx& c);
 void launch_m2l_mixed_root(Ctx& c, double* loc64);
+void add_root_locals(Ctx& c, double* loc, const double* loc64);
 int mixed_first_lo(Ctx& c);
 bool mixed_supported(int p);
 void adjoint_pass(Ctx& c, const double* gacc, const double* gpot, const double* acc_fwd, double* gpos,

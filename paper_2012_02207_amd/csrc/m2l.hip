@@ -183,27 +183,15 @@ __device__ __forceinline__ void reduce_order(const double* v, double* acc_slot, 
 
 constexpr int M2L_WAVES = 4;  // sinks per workgroup (one per wavefront)
 
+// M2L of the list of one sink cell B (one wavefront; lane = lane id); with
+// B >= first_lo only the sources below first_lo are taken
 template <int P>
-__global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l_fp64(int ncell, int first_lo, const int* __restrict__ off,
-                                                             const int* __restrict__ src,
-                                                             const double* __restrict__ cx,
-                                                             const double* __restrict__ cy,
-                                                             const double* __restrict__ cz,
-                                                             const double* __restrict__ mult,
-                                                             double* __restrict__ loc) {
+__device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, const int* __restrict__ off,
+                                              const int* __restrict__ src, const double* __restrict__ cx,
+                                              const double* __restrict__ cy, const double* __restrict__ cz,
+                                              const double* __restrict__ mult, double* __restrict__ loc,
+                                              const ldouble* swt) {
   constexpr int NC = ncoef(P);
-  constexpr int NSW = cswoff(P + 1);
-  __shared__ double swt[NSW];
-  for (int t = threadIdx.x; t < NSW; t += 64 * M2L_WAVES) swt[t] = c_cswap[t];
-  __syncthreads();
-  // XCD-aware mapping: consecutive workgroups land on different XCDs, so give
-  // each XCD a contiguous range of sinks (neighbouring sinks share sources)
-  int nblk = (ncell + M2L_WAVES - 1) / M2L_WAVES;
-  int per = (nblk + 7) >> 3;
-  int blk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  int wv = threadIdx.x >> 6;
-  int B = blk * M2L_WAVES + wv;
-  if (blk >= nblk || B >= ncell) return;
   int b = off[B], e = off[B + 1];
   if (B >= first_lo) {
     // mixed precision: only the sources above the root levels (a prefix of
@@ -219,7 +207,6 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l_fp64(int ncell, int firs
     e = lo;
   }
   if (b == e) return;
-  int lane = threadIdx.x & 63;
   // lane-major accumulator: lane j holds coefficient j of order n in acc[n]
   double acc[P + 1];
 #pragma unroll
@@ -259,7 +246,7 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l_fp64(int ncell, int firs
     // An opaque view of the LDS swap table per iteration: without it the
     // compiler hoists every (loop-invariant) coefficient read out of the
     // source loop and spills them.
-    const ldouble* sw_it = (const ldouble*)swt;
+    const ldouble* sw_it = swt;
     // Source orders k >= K0 reach only output orders n <= P - k < K0: rotate
     // them first and fold them at once into a partial local expansion Lp
     // (orders 0..P-K0), so that only the low orders of the rotated multipole
@@ -382,25 +369,65 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l_fp64(int ncell, int firs
   });
 }
 
+// All sinks (one wavefront each, in XCD-contiguous ranges: neighbouring sinks
+// share sources), or, with LIST, the sinks[0 .. *nsinks) in a grid-stride loop.
+template <int P, bool LIST>
+__global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l_fp64(int ncell, int first_lo, const int* __restrict__ sinks,
+                                                             const int* __restrict__ nsinks,
+                                                             const int* __restrict__ off,
+                                                             const int* __restrict__ src,
+                                                             const double* __restrict__ cx,
+                                                             const double* __restrict__ cy,
+                                                             const double* __restrict__ cz,
+                                                             const double* __restrict__ mult,
+                                                             double* __restrict__ loc) {
+  constexpr int NSW = cswoff(P + 1);
+  __shared__ double swt[NSW];
+  for (int t = threadIdx.x; t < NSW; t += 64 * M2L_WAVES) swt[t] = c_cswap[t];
+  __syncthreads();
+  int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if constexpr (LIST) {
+    int cnt = *nsinks;
+    for (int it = blockIdx.x * M2L_WAVES + wv; it < cnt; it += gridDim.x * M2L_WAVES)
+      m2l_sink_fp64<P>(sinks[it], first_lo, lane, off, src, cx, cy, cz, mult, loc, (const ldouble*)swt);
+  } else {
+    int nblk = (ncell + M2L_WAVES - 1) / M2L_WAVES;
+    int per = (nblk + 7) >> 3;
+    int blk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    int B = blk * M2L_WAVES + wv;
+    if (blk < nblk && B < ncell)
+      m2l_sink_fp64<P>(B, first_lo, lane, off, src, cx, cy, cz, mult, loc, (const ldouble*)swt);
+  }
+}
+
+// sinks == nullptr: every sink cell; otherwise the listed sinks (count on the
+// device, so the launch needs no host synchronisation)
 template <int P>
-static void launch_p(Ctx& c, int first_lo, const double* mult, double* loc) {
+static void launch_p(Ctx& c, int first_lo, const double* mult, double* loc, const int* sinks, const int* nsinks) {
   int nc = (int)c.ncell;
+  if (sinks) {
+    constexpr unsigned LIST_BLOCKS = 512;
+    hipLaunchKernelGGL((k_m2l_fp64<P, true>), dim3(LIST_BLOCKS), dim3(64 * M2L_WAVES), 0, c.stream, nc, first_lo,
+                       sinks, nsinks, c.m2l.off.p, c.m2l.src.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, mult, loc);
+    return;
+  }
   int nblk = (nc + M2L_WAVES - 1) / M2L_WAVES;
   unsigned grid = 8u * (unsigned)((nblk + 7) / 8);
-  hipLaunchKernelGGL(k_m2l_fp64<P>, dim3(grid), dim3(64 * M2L_WAVES), 0, c.stream, nc, first_lo, c.m2l.off.p, c.m2l.src.p,
-                     c.c_cx.p, c.c_cy.p, c.c_cz.p, mult, loc);
+  hipLaunchKernelGGL((k_m2l_fp64<P, false>), dim3(grid), dim3(64 * M2L_WAVES), 0, c.stream, nc, first_lo,
+                     (const int*)nullptr, (const int*)nullptr, c.m2l.off.p, c.m2l.src.p, c.c_cx.p, c.c_cy.p,
+                     c.c_cz.p, mult, loc);
 }
 
 template <int P>
-static bool dispatch(Ctx& c, int first_lo, const double* mult, double* loc) {
+static bool dispatch(Ctx& c, int first_lo, const double* mult, double* loc, const int* sinks, const int* nsinks) {
   if constexpr (P > FMM_GPU_PMAX) {
     return false;
   } else {
     if (c.p == P) {
-      launch_p<P>(c, first_lo, mult, loc);
+      launch_p<P>(c, first_lo, mult, loc, sinks, nsinks);
       return true;
     }
-    return dispatch<P + 1>(c, first_lo, mult, loc);
+    return dispatch<P + 1>(c, first_lo, mult, loc, sinks, nsinks);
   }
 }
 
@@ -416,21 +443,35 @@ void launch_m2l_fp64_range(Ctx& c, int first_lo) {
   launch_m2l_fp64_buffers(c, first_lo, c.mult.p, c.loc.p);
 }
 
+static void upload_m2l_tables() {
+  if (g_m2l_tables) return;
+  // compact the dense tables to their structural non-zeros (row-major)
+  static_assert(CSWAP_DOUBLES <= 8192, "compacted swap table");
+  std::vector<double> cs;
+  for (int n = 0; n <= FMM_GPU_PMAX; n++)
+    for (int i = 0; i < 2 * n + 1; i++)
+      for (int j = 0; j < 2 * n + 1; j++)
+        if (swap_nz(n, i, j)) cs.push_back(fmm_swap_table[swoff(n) + i * (2 * n + 1) + j]);
+  HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_cswap), cs.data(), sizeof(double) * cs.size()));
+  HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_fact_m2l), fmm_fact_table, sizeof(double) * (2 * FMM_GPU_PMAX + 2)));
+  g_m2l_tables = true;
+}
+
 // the same over other expansion buffers (same tree and list)
 void launch_m2l_fp64_buffers(Ctx& c, int first_lo, const double* mult, double* loc) {
-  if (!g_m2l_tables) {
-    // compact the dense tables to their structural non-zeros (row-major)
-    static_assert(CSWAP_DOUBLES <= 8192, "compacted swap table");
-    std::vector<double> cs;
-    for (int n = 0; n <= FMM_GPU_PMAX; n++)
-      for (int i = 0; i < 2 * n + 1; i++)
-        for (int j = 0; j < 2 * n + 1; j++)
-          if (swap_nz(n, i, j)) cs.push_back(fmm_swap_table[swoff(n) + i * (2 * n + 1) + j]);
-    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_cswap), cs.data(), sizeof(double) * cs.size()));
-    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_fact_m2l), fmm_fact_table, sizeof(double) * (2 * FMM_GPU_PMAX + 2)));
-    g_m2l_tables = true;
-  }
-  if (!dispatch<1>(c, first_lo, mult, loc)) throw hip_error{hipErrorInvalidValue, "M2L order not compiled"};
+  upload_m2l_tables();
+  if (!dispatch<1>(c, first_lo, mult, loc, nullptr, nullptr))
+    throw hip_error{hipErrorInvalidValue, "M2L order not compiled"};
+  HIPCHK(hipGetLastError());
+}
+
+// only the sinks sinks[0 .. *nsinks) (device memory); every coefficient of a
+// listed sink is written, the others are left untouched
+void launch_m2l_fp64_sinks(Ctx& c, int first_lo, const double* mult, double* loc, const int* sinks,
+                           const int* nsinks) {
+  upload_m2l_tables();
+  if (!dispatch<1>(c, first_lo, mult, loc, sinks, nsinks))
+    throw hip_error{hipErrorInvalidValue, "M2L order not compiled"};
   HIPCHK(hipGetLastError());
 }
 

@@ -128,53 +128,122 @@ __device__ __forceinline__ void zrot(float* v, float c1, float s1) {
   });
 }
 
-// Transpose-reduce of D values per lane over the 64 lanes: at each butterfly
-// step a lane keeps half of its remaining values and adds the partner's copy
-// of that half (about D + 6 shuffles instead of 6 D).  Afterwards the total of
-// value j sits in lane j * (64 / Dp) (Dp = D rounded up to a power of two),
-// which adds it to its accumulator acc_slot.
-constexpr int pow2_ceil(int d) {
-  int p = 1;
-  while (p < d) p <<= 1;
-  return p;
+// Cross-lane sum of D values per lane (transpose-reduce) in six halving steps
+// with partner distances 32, 16, 8, 4, 2, 1.  With L values left, a lane keeps
+// the first ceil(L/2) of them or the rest (padded with a zero), by that bit of
+// its lane id, and adds its partner's copy of the kept part; once a single
+// value is left the steps are plain butterflies.  Distances 32 and 16 exchange
+// register halves between lane groups (permlane32/16 swaps, no LDS traffic);
+// distances 8 to 1 read the partner through DPP (row mirror, half-row mirror,
+// two quad permutations: each pairs lanes that differ in that bit).  The total
+// of value j ends in lane reduce_owner(D, j).
+constexpr int reduce_len(int D, int t) {
+  int L = D;
+  for (int k = 0; k < t; k++) L = (L + 1) / 2;
+  return L;
 }
-constexpr int ilog2(int d) {
-  int k = 0;
-  while ((1 << k) < d) k++;
-  return k;
+constexpr int reduce_owner(int D, int j) {
+  int lane = 0, L = D;
+  for (int t = 0; t < 6; t++) {
+    if (L >= 2) {
+      int h = (L + 1) / 2;
+      if (j >= h) {
+        lane |= 32 >> t;
+        j -= h;
+      }
+      L = h;
+    }
+  }
+  return lane;
 }
 
+// the entry j whose total lane ends with, and whether it is a real entry
+// (not one of the zero pads): reduce_owner inverted
 template <int D>
-__device__ __forceinline__ void reduce_order(const float* v, double* acc_slot, int lane, bool act) {
-  constexpr int DP = pow2_ceil(D);
-  float x[DP];
-  static_for<0, DP>([&](auto jc) {
-    constexpr int j = jc;
-    if constexpr (j < D)
-      x[j] = act ? v[j] : 0.f;
-    else
-      x[j] = 0.f;
-  });
-  static_for<0, ilog2(DP)>([&](auto tc) {
+__device__ __forceinline__ void reduce_slot(int lane, int& j, int& real) {
+  j = 0;
+  int left = D;  // real entries in this lane's part
+  bool ok = true;
+  static_for<0, 6>([&](auto tc) {
     constexpr int t = tc;
-    constexpr int s = 32 >> t;          // partner distance
-    constexpr int half = DP >> (t + 1);
-    bool hi = (lane & s) != 0;
-    static_for<0, half>([&](auto ic) {
-      constexpr int i = ic;
-      float keep = hi ? x[i + half] : x[i];
-      float give = hi ? x[i] : x[i + half];
-      x[i] = keep + __shfl_xor(give, s, 64);
-    });
+    constexpr int L = reduce_len(D, t);
+    bool bit = (lane & (32 >> t)) != 0;
+    if constexpr (L >= 2) {
+      constexpr int H = (L + 1) / 2;
+      j += bit ? H : 0;
+      left = bit ? left - H : min(left, H);
+    } else {
+      ok = ok && !bit;
+    }
   });
-  static_for<ilog2(DP), 6>([&](auto tc) {
-    constexpr int s = 32 >> tc;
-    x[0] += __shfl_xor(x[0], s, 64);
+  real = ok && left >= 1;
+}
+
+// lanes 32..63 of a <-> lanes 0..31 of b (T = 0), or the odd 16-lane rows of a
+// <-> the even rows of b (T = 1)
+template <int T>
+__device__ __forceinline__ void lane_swap(float& a, float& b) {
+  unsigned ua = __builtin_bit_cast(unsigned, a), ub = __builtin_bit_cast(unsigned, b);
+  if constexpr (T == 0) {
+    auto r = __builtin_amdgcn_permlane32_swap(ua, ub, false, false);
+    a = __builtin_bit_cast(float, (unsigned)r[0]);
+    b = __builtin_bit_cast(float, (unsigned)r[1]);
+  } else {
+    auto r = __builtin_amdgcn_permlane16_swap(ua, ub, false, false);
+    a = __builtin_bit_cast(float, (unsigned)r[0]);
+    b = __builtin_bit_cast(float, (unsigned)r[1]);
+  }
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_read(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+
+// x[0..D) of every lane -> the cross-lane totals; each lane adds its last
+// value to *acc_slot (meaningful in the owner lanes only)
+template <int D>
+__device__ __forceinline__ void reduce_order(float* x, double* acc_slot, int lane) {
+  static_for<0, 6>([&](auto tc) {
+    constexpr int t = tc;
+    constexpr int L = reduce_len(D, t);
+    if constexpr (t < 2) {
+      if constexpr (L == 1) {
+        float a = x[0], b = x[0];
+        lane_swap<t>(a, b);
+        x[0] = a + b;
+      } else {
+        constexpr int H = (L + 1) / 2;
+        static_for<0, H>([&](auto ic) {
+          constexpr int i = ic;
+          float a = x[i], b = 0.f;
+          if constexpr (i + H < L) b = x[i + H];
+          lane_swap<t>(a, b);
+          x[i] = a + b;
+        });
+      }
+    } else {
+      // row mirror, half-row mirror, quad_perm [2,3,0,1], quad_perm [1,0,3,2]
+      constexpr int CTRL = t == 2 ? 0x140 : t == 3 ? 0x141 : t == 4 ? 0x4E : 0xB1;
+      if constexpr (L == 1) {
+        x[0] = x[0] + dpp_read<CTRL>(x[0]);
+      } else {
+        constexpr int H = (L + 1) / 2;
+        bool hi = (lane & (32 >> t)) != 0;
+        static_for<0, H>([&](auto ic) {
+          constexpr int i = ic;
+          float lo_sum = x[i] + dpp_read<CTRL>(x[i]);
+          if constexpr (i + H < L) {
+            float hi_sum = x[i + H] + dpp_read<CTRL>(x[i + H]);
+            x[i] = hi ? hi_sum : lo_sum;
+          } else {
+            x[i] = hi ? 0.f : lo_sum;
+          }
+        });
+      }
+    }
   });
-  constexpr int K = 6 - ilog2(DP);      // owner lanes: low K bits zero
-  int j = lane >> K;
-  bool own = ((lane & ((1 << K) - 1)) == 0) && j < D;
-  *acc_slot += own ? (double)x[0] : 0.0;
+  *acc_slot += (double)x[0];
 }
 
 }  // namespace mx
@@ -252,7 +321,9 @@ __global__ void __launch_bounds__(64 * MX_WAVES) k_m2l_fp32(int ncell, int first
       sa = 1.f;
     }
     float cb = (float)(Rz * rinv), sb = (float)(-rho * rinv);
-    float tA = (float)(scale[A] * rinv), tB = (float)(sB * rinv), fr = (float)rinv;
+    // an inactive lane (past the end of the list) gets zero factors, so all its
+    // outputs are zero
+    float tA = (float)(scale[A] * rinv), tB = (float)(sB * rinv), fr = act ? (float)rinv : 0.f;
     float pA[P + 1], pB[P + 1];
     pA[0] = 1.f;
     pB[0] = fr;
@@ -348,19 +419,19 @@ __global__ void __launch_bounds__(64 * MX_WAVES) k_m2l_fp32(int ncell, int first
       zrot<n>(w, cb, -sb);
       swap_apply<n>(w, sw);
       zrot<n>(w, ca, -sa);
-      reduce_order<2 * n + 1>(w, &acc[n], lane, act);
+      reduce_order<2 * n + 1>(w, &acc[n], lane);
     });
   }
   // back to standard coefficients: L_n^0 += Lt n! / rho_B^n,
   // L_n^m += Lt sqrt((n-m)!(n+m)!/2) / rho_B^n; real-basis entry j of order n
-  // is owned by lane j * 64 / Dp (see reduce_order)
+  // is held by lane reduce_owner(2n+1, j)
   double* out = loc + (size_t)B * NC * 2;
   double isB = 1.0 / sB, pw = 1.0;
   static_for<0, P + 1>([&](auto nc) {
     constexpr int n = nc;
-    constexpr int K = 6 - ilog2(pow2_ceil(2 * n + 1));
-    int j = lane >> K;
-    if ((lane & ((1 << K) - 1)) == 0 && j < 2 * n + 1) {
+    int j, real;
+    reduce_slot<2 * n + 1>(lane, j, real);
+    if (real) {
       int m = (j + 1) >> 1;
       bool im = j > 0 && !(j & 1);
       double f = (m == 0 ? 1.0 : sqrt(0.5)) * sqrt(fmm_fact_dev(n - m) * fmm_fact_dev(n + m)) * pw;
@@ -467,12 +538,49 @@ int mixed_first_lo(Ctx& c) {
   return K <= c.depth ? c.lvl_first[K] : (int)c.ncell;
 }
 
-// FP64 M2L of every pair touching a root-level cell into loc64 (zeroed here),
-// for sinks that have such pairs
+// sinks with at least one FP64 pair: every sink above first_lo with a
+// non-empty list, and those below whose (ascending) list starts above it.
+// The list order depends on the atomics; each sink's result does not.
+__global__ void k_root_sinks(int ncell, int first_lo, const int* __restrict__ off, const int* __restrict__ src,
+                             int* __restrict__ sinks, int* __restrict__ count) {
+  int B = blockIdx.x * blockDim.x + threadIdx.x;
+  if (B >= ncell) return;
+  int b = off[B], e = off[B + 1];
+  bool has = b < e && (B < first_lo || src[b] < first_lo);
+  if (has) sinks[atomicAdd(count, 1)] = B;
+}
+
+// loc[B] += loc64[B] for the listed sinks (grid-stride over coefficients)
+__global__ void k_add_sinks(const int* __restrict__ sinks, const int* __restrict__ count, int ncd,
+                            double* __restrict__ loc, const double* __restrict__ loc64) {
+  int64_t tot = (int64_t)(*count) * ncd;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+    size_t k = (size_t)sinks[t / ncd] * ncd + (size_t)(t % ncd);
+    loc[k] += loc64[k];
+  }
+}
+
+// FP64 M2L of every pair touching a root-level cell into loc64, for the sinks
+// that have such pairs (listed in c.root_sinks, count at counters[64]); the
+// other sinks' entries of loc64 are not written
 void launch_m2l_mixed_root(Ctx& c, double* loc64) {
-  size_t nl = (size_t)c.ncell * ncoef(c.p) * 2;
-  zero_fill(c, loc64, nl * sizeof(double));
-  launch_m2l_fp64_buffers(c, mixed_first_lo(c), c.mult.p, loc64);
+  int nc = (int)c.ncell;
+  ensure(c.ws, c.root_sinks, (size_t)nc);
+  ensure(c.ws, c.counters, 512);
+  int* count = c.counters.p + 64;
+  zero_fill(c, count, sizeof(int));
+  int first_lo = mixed_first_lo(c);
+  hipLaunchKernelGGL(k_root_sinks, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, c.stream, nc, first_lo,
+                     c.m2l.off.p, c.m2l.src.p, c.root_sinks.p, count);
+  HIPCHK(hipGetLastError());
+  launch_m2l_fp64_sinks(c, first_lo, c.mult.p, loc64, c.root_sinks.p, count);
+}
+
+// loc += loc64 over the sinks launch_m2l_mixed_root listed
+void add_root_locals(Ctx& c, double* loc, const double* loc64) {
+  hipLaunchKernelGGL(k_add_sinks, dim3(1024), dim3(256), 0, c.stream, c.root_sinks.p, c.counters.p + 64,
+                     ncoef(c.p) * 2, loc, loc64);
+  HIPCHK(hipGetLastError());
 }
 
 }  // namespace fmm
