@@ -267,8 +267,11 @@ __device__ __forceinline__ int split_point(const int* src, int b, int e, int fir
   return lo;
 }
 
+// One wavefront per sink, a source per lane.  Three waves per SIMD (at most
+// 168 VGPRs); the FP64 per-order sums live in LDS (a slot per lane), not in
+// registers, which would spill at that budget.
 template <int P>
-__global__ void __launch_bounds__(64 * MX_WAVES) k_m2l_fp32(int ncell, int first_lo,
+__global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per_eu(3))) k_m2l_fp32(int ncell, int first_lo,
                                                             const int* __restrict__ off,
                                                             const int* __restrict__ src,
                                                             const double* __restrict__ cx,
@@ -295,9 +298,10 @@ __global__ void __launch_bounds__(64 * MX_WAVES) k_m2l_fp32(int ncell, int first
   int b = split_point(src, off[B], e, first_lo);
   if (b == e) return;
   int lane = threadIdx.x & 63;
-  double acc[P + 1];
+  __shared__ double accs[MX_WAVES][P + 1][64];
+  double* acc = &accs[wv][0][0] + lane;
 #pragma unroll
-  for (int t = 0; t <= P; t++) acc[t] = 0.0;
+  for (int t = 0; t <= P; t++) acc[64 * t] = 0.0;
   double bx = cx[B], by = cy[B], bz = cz[B], sB = scale[B];
   const lfloat* sw_it = (const lfloat*)swt;
 
@@ -419,7 +423,7 @@ __global__ void __launch_bounds__(64 * MX_WAVES) k_m2l_fp32(int ncell, int first
       zrot<n>(w, cb, -sb);
       swap_apply<n>(w, sw);
       zrot<n>(w, ca, -sa);
-      reduce_order<2 * n + 1>(w, &acc[n], lane);
+      reduce_order<2 * n + 1>(w, &acc[64 * n], lane);
     });
   }
   // back to standard coefficients: L_n^0 += Lt n! / rho_B^n,
@@ -435,7 +439,7 @@ __global__ void __launch_bounds__(64 * MX_WAVES) k_m2l_fp32(int ncell, int first
       int m = (j + 1) >> 1;
       bool im = j > 0 && !(j & 1);
       double f = (m == 0 ? 1.0 : sqrt(0.5)) * sqrt(fmm_fact_dev(n - m) * fmm_fact_dev(n + m)) * pw;
-      out[2 * cidx(n, m) + (im ? 1 : 0)] += acc[n] * f;
+      out[2 * cidx(n, m) + (im ? 1 : 0)] += acc[64 * n] * f;
     }
     pw *= isB;
   });
