@@ -94,7 +94,10 @@ __global__ void k_count_low_pairs(const int* off, const int* src, int ncell, int
 // after the join the root-level part is added (for the sinks that have one),
 // then L2L and the final L2P + sum.  loc gets exactly one contribution per
 // kernel, so the order of the two M2L parts does not change the result.
-void evaluate(Ctx& c, double* acc, double* pot, bool group_m2l) {
+// group: the lists come straight from the walk; the near-field list is
+// grouped on the side stream (with its own sort scratch) while the M2L list is
+// grouped on the caller's stream.
+void evaluate(Ctx& c, double* acc, double* pot, bool group) {
   hipStream_t s = c.stream;
   int nc = (int)c.ncell;
   size_t nl = (size_t)nc * ncoef(c.p) * 2;
@@ -104,13 +107,19 @@ void evaluate(Ctx& c, double* acc, double* pot, bool group_m2l) {
   ensure(c.ws, c.nearbuf, (size_t)c.n);
   if (root64) ensure(c.ws, c.loc64, nl);
   stream_wait(c.fork[2], s, c.side);
+  // the (longer) M2L grouping is enqueued first, so that it runs while the
+  // host enqueues the other
+  if (group) group_list(c, c.m2l);
   {
     OnStream on(c, c.side);
+    if (group) {
+      SideScratch alt(c);
+      group_list(c, c.p2p);
+    }
     if (c.have_events) HIPCHK(hipEventRecord(c.ev[6], c.side));
     launch_near_field(c);
     if (c.have_events) HIPCHK(hipEventRecord(c.ev[7], c.side));
   }
-  if (group_m2l) group_list(c, c.m2l);  // beside the near field
   if (root64) {  // a few long interaction lists: a kernel of its own beside the others
     stream_wait(c.fork[5], s, c.side2);
     OnStream on(c, c.side2);
@@ -246,6 +255,7 @@ static void build_and_estimate(Ctx& c, int64_t n, const double* pos, const doubl
   stream_wait(c.fork[0], c.stream, c.side);
   {
     OnStream on(c, c.side);
+    SideScratch alt(c);  // the estimate walk sorts its lists meanwhile
     upward_pass(c);
     HIPCHK(hipEventRecord(c.ev[14], c.side));
   }
@@ -311,7 +321,6 @@ static fmm_status forces_impl(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets
     HIPCHK(hipEventRecord(c.ev[0], c.stream));
     build_and_estimate(c, n, pos, mass);
     mac_walk(c);
-    group_list(c, c.p2p);  // the near field starts first; the M2L list is grouped beside it
     c.walked = true;
     evaluate(c, acc, pot, true);
     c.evaluated = true;
@@ -740,7 +749,7 @@ void fmm_destroy(fmm_ctx* ctx) {
     rel(c.idx[k]);
     rel(c.front[k]);
   }
-  rel(c.sx); rel(c.sy); rel(c.sz); rel(c.sm); rel(c.pm); rel(c.pkb); rel(c.scale); rel(c.nmult); rel(c.fpart); rel(c.leaf_of); rel(c.leaves); rel(c.nearbuf); rel(c.loc64); rel(c.root_sinks); rel(c.madj); rel(c.ladj); rel(c.fwd_acc); rel(c.fwd_pot); rel(c.gsort); rel(c.asort); rel(c.sys_off); rel(c.skey[0]); rel(c.skey[1]); rel(c.spos[0]); rel(c.spos[1]); rel(c.sort_hist);
+  rel(c.sx); rel(c.sy); rel(c.sz); rel(c.sm); rel(c.pm); rel(c.pkb); rel(c.scale); rel(c.nmult); rel(c.fpart); rel(c.leaf_of); rel(c.leaves); rel(c.nearbuf); rel(c.loc64); rel(c.root_sinks); rel(c.madj); rel(c.ladj); rel(c.fwd_acc); rel(c.fwd_pot); rel(c.gsort); rel(c.asort); rel(c.sys_off); rel(c.skey[0]); rel(c.skey[1]); rel(c.spos[0]); rel(c.spos[1]); rel(c.sort_hist); rel(c.sort_hist2); rel(c.scan_tmp2);
   rel(c.bbox_part); rel(c.rootbox); rel(c.c_level); rel(c.c_begin); rel(c.c_end); rel(c.c_parent);
   rel(c.c_child0); rel(c.c_nchild); rel(c.c_split); rel(c.c_mass); rel(c.c_sx); rel(c.c_sy);
   rel(c.c_sz); rel(c.c_cx); rel(c.c_cy); rel(c.c_cz); rel(c.c_rad); rel(c.c_rad2bits); rel(c.mult);

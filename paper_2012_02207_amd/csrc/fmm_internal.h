@@ -155,6 +155,9 @@ struct Ctx {
   // scan scratch
   dbuf<int> scan_tmp;
   dbuf<long long> scan_tmp64;
+  // a second set of sort and scan scratch for work on the side stream that
+  // runs while the caller's stream sorts or scans (see SideScratch)
+  dbuf<int> sort_hist2, scan_tmp2;
 
   // host pinned scratch for small read-backs
   long long* hbuf = nullptr;
@@ -181,6 +184,21 @@ struct Ctx {
   bool have_events = false;
 };
 
+// Sorts and scans take their scratch from c.sort_hist and c.scan_tmp; within
+// this scope they use the second set, so that a sort on the side stream may
+// run concurrently with one on the caller's stream.
+struct SideScratch {
+  Ctx& c;
+  explicit SideScratch(Ctx& cc) : c(cc) {
+    std::swap(c.sort_hist, c.sort_hist2);
+    std::swap(c.scan_tmp, c.scan_tmp2);
+  }
+  ~SideScratch() {
+    std::swap(c.sort_hist, c.sort_hist2);
+    std::swap(c.scan_tmp, c.scan_tmp2);
+  }
+};
+
 // ------------------------------------------------------------------ stages
 void exclusive_scan(Ctx& c, const int* in, int* out, int64_t n, long long* total_dev);
 long long read_total(Ctx& c, const long long* total_dev);
@@ -196,7 +214,7 @@ void refresh_frozen(Ctx& c, const double* pos, const double* mass);
 void estimate_walk(Ctx& c);
 void mac_walk(Ctx& c);  // lists left ungrouped: see group_list
 void group_list(Ctx& c, CellList& L);
-void evaluate(Ctx& c, double* acc, double* pot, bool group_m2l);
+void evaluate(Ctx& c, double* acc, double* pot, bool group);
 void launch_normalize32(Ctx& c);
 void direct_sum(int64_t n, const double* pos, const double* mass, double eps2, int64_t nsink,
                 const int32_t* sinks, double* acc, double* pot, hipStream_t s);
