@@ -253,15 +253,16 @@ static void build_and_estimate(Ctx& c, int64_t n, const double* pos, const doubl
   build_tree(c, n, pos, mass);
   HIPCHK(hipEventRecord(c.ev[1], c.stream));
   stream_wait(c.fork[0], c.stream, c.side);
-  {
+  HIPCHK(hipEventRecord(c.ev[2], c.stream));
+  // the upward pass goes to the side stream while the estimate walk runs, so
+  // that neither waits for the other's launches
+  estimate_walk(c, [&]() {
     OnStream on(c, c.side);
     SideScratch alt(c);  // the estimate walk sorts its lists meanwhile
     upward_pass(c);
     HIPCHK(hipEventRecord(c.ev[14], c.side));
-  }
+  });
   c.built = true;
-  HIPCHK(hipEventRecord(c.ev[2], c.stream));
-  estimate_walk(c);
   c.estimated = true;
   stream_wait(c.fork[1], c.side, c.stream);
   HIPCHK(hipEventRecord(c.ev[3], c.stream));

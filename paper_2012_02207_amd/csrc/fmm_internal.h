@@ -10,6 +10,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <functional>
+
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -211,7 +213,9 @@ void expansions_up(Ctx& c);
 void cell_moments(Ctx& c, bool with_radius);
 void zero_fill(Ctx& c, void* p, size_t bytes);
 void refresh_frozen(Ctx& c, const double* pos, const double* mass);
-void estimate_walk(Ctx& c);
+// the scalar-force estimate; beside (if any) is called once while the walk
+// runs on the device, to enqueue independent work on another stream
+void estimate_walk(Ctx& c, const std::function<void()>& beside = {});
 void mac_walk(Ctx& c);  // lists left ungrouped: see group_list
 void group_list(Ctx& c, CellList& L);
 void evaluate(Ctx& c, double* acc, double* pot, bool group);

@@ -283,6 +283,15 @@ __global__ void __launch_bounds__(64 * LG_WAVES) k_leaf_group(const int* __restr
         }
       } else {
         int t = g;
+        if constexpr (MIXED) {
+          for (; t + 3 * G < tmax; t += 4 * G) {
+            double4 s0 = sbuf[wv][t], s1 = sbuf[wv][t + G], s2 = sbuf[wv][t + 2 * G], s3 = sbuf[wv][t + 3 * G];
+            pair32(s0, mass32(s0), me, eps2f, fx, fy, fz, fp);
+            pair32(s1, mass32(s1), me, eps2f, fx, fy, fz, fp);
+            pair32(s2, mass32(s2), me, eps2f, fx, fy, fz, fp);
+            pair32(s3, mass32(s3), me, eps2f, fx, fy, fz, fp);
+          }
+        }
         for (; t + G < tmax; t += 2 * G) {
           double4 s0 = sbuf[wv][t], s1 = sbuf[wv][t + G];
           if constexpr (MIXED) {

@@ -474,25 +474,31 @@ __device__ inline int octant_lower_bound(const uint64_t* key, int b, int e, int 
   return lo;
 }
 
+// children of every cell of one level; cells that stay leaves are counted in
+// *nleaf (one atomic per wavefront)
 __global__ void k_split_level(int first, int count, int level, int n_leaf, const uint64_t* key,
-                              const int* cb, const int* ce, int* split, int* nch) {
+                              const int* cb, const int* ce, int* split, int* nch, int* nleaf) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= count) return;
-  int c = first + t;
-  int b = cb[c], e = ce[c];
+  bool ok = t < count;
   int cnt = 0;
-  if (e - b > n_leaf && level < FMM_MAX_LEVEL) {
-    int shift = 3 * (FMM_MAX_LEVEL - (level + 1));
-    int prev = b;
-    split[9 * t] = b;
-    for (int o = 1; o <= 8; o++) {
-      int s = o < 8 ? octant_lower_bound(key, prev, e, o, shift) : e;
-      split[9 * t + o] = s;
-      if (s > prev) cnt++;
-      prev = s;
+  if (ok) {
+    int c = first + t;
+    int b = cb[c], e = ce[c];
+    if (e - b > n_leaf && level < FMM_MAX_LEVEL) {
+      int shift = 3 * (FMM_MAX_LEVEL - (level + 1));
+      int prev = b;
+      split[9 * t] = b;
+      for (int o = 1; o <= 8; o++) {
+        int s = o < 8 ? octant_lower_bound(key, prev, e, o, shift) : e;
+        split[9 * t + o] = s;
+        if (s > prev) cnt++;
+        prev = s;
+      }
     }
+    nch[t] = cnt;
   }
-  nch[t] = cnt;
+  unsigned long long leaves = __ballot(ok && cnt == 0);
+  if ((threadIdx.x & 63) == 0 && leaves) atomicAdd(nleaf, (int)__popcll(leaves));
 }
 
 __global__ void k_emit_children(int first, int count, int level, int next_first, const int* split,
@@ -582,7 +588,7 @@ __global__ void k_mass_com(int first, int count, int level, const int* cb, const
 
 // radius: exact max over each cell's bodies of the squared distance to its
 // centre (order independent), in chunks of RAD_CH bodies
-constexpr int RAD_T = 256, RAD_CH = 2048;
+constexpr int RAD_T = 256, RAD_CH = 1024;
 
 __global__ void k_rad_chunks(const int* cb, const int* ce, int ncell, int* nchunk) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -590,12 +596,16 @@ __global__ void k_rad_chunks(const int* cb, const int* ce, int ncell, int* nchun
   nchunk[c] = (int)ceil_div(ce[c] - cb[c], RAD_CH);
 }
 
+// one wavefront per chunk (the count stays on the device, so the launch needs
+// no host round trip; the grid covers an upper bound of it)
 __global__ void __launch_bounds__(RAD_T) k_radius(const int* cb, const int* ce, const int* choff,
-                                                 int ncell, const double* sx, const double* sy,
-                                                 const double* sz, const double* cx, const double* cy,
-                                                 const double* cz, unsigned long long* r2bits) {
-  __shared__ double sh[RAD_T];
-  int blk = blockIdx.x;
+                                                 const long long* nchunks, int ncell, const double* sx,
+                                                 const double* sy, const double* sz, const double* cx,
+                                                 const double* cy, const double* cz,
+                                                 unsigned long long* r2bits) {
+  int blk = blockIdx.x * (RAD_T / 64) + (threadIdx.x >> 6);
+  int lane = threadIdx.x & 63;
+  if (blk >= (int)*nchunks) return;
   // cell owning this chunk: last c with choff[c] <= blk
   int lo = 0, hi = ncell - 1;
   while (lo < hi) {
@@ -610,18 +620,16 @@ __global__ void __launch_bounds__(RAD_T) k_radius(const int* cb, const int* ce, 
   int64_t e = b + RAD_CH < ce[c] ? b + RAD_CH : ce[c];
   double x0 = cx[c], y0 = cy[c], z0 = cz[c];
   double best = 0.0;
-  for (int64_t i = b + threadIdx.x; i < e; i += RAD_T) {
+  for (int64_t i = b + lane; i < e; i += 64) {
     double dx = sx[i] - x0, dy = sy[i] - y0, dz = sz[i] - z0;
     double d2 = (dx * dx + dy * dy) + dz * dz;
     if (d2 > best) best = d2;
   }
-  sh[threadIdx.x] = best;
-  __syncthreads();
-  for (int o = RAD_T / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o && sh[threadIdx.x + o] > sh[threadIdx.x]) sh[threadIdx.x] = sh[threadIdx.x + o];
-    __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) {
+    double other = __shfl_xor(best, o, 64);
+    if (other > best) best = other;
   }
-  if (threadIdx.x == 0) atomicMax(&r2bits[c], (unsigned long long)__double_as_longlong(sh[0]));
+  if (lane == 0) atomicMax(&r2bits[c], (unsigned long long)__double_as_longlong(best));
 }
 
 __global__ void k_radius_final(const unsigned long long* r2bits, int ncell, double* rad) {
@@ -667,10 +675,12 @@ void cell_moments(Ctx& c, bool with_radius) {
   int* choff = nchunk + nc + 32;
   hipLaunchKernelGGL(k_rad_chunks, grid1(nc), dim3(256), 0, s, c.c_begin.p, c.c_end.p, nc, nchunk);
   exclusive_scan(c, nchunk, choff, nc, tot);
-  long long nchunks = read_total(c, tot);
-  HIPCHK(hipMemsetAsync(c.c_rad2bits.p, 0, sizeof(unsigned long long) * nc, s));
-  hipLaunchKernelGGL(k_radius, dim3((unsigned)nchunks), dim3(RAD_T), 0, s, c.c_begin.p, c.c_end.p,
-                     choff, nc, c.sx.p, c.sy.p, c.sz.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.c_rad2bits.p);
+  zero_fill(c, c.c_rad2bits.p, sizeof(unsigned long long) * nc);
+  // every body is in one cell per level: at most (depth + 1) n / RAD_CH + ncell chunks
+  int64_t max_chunks = (int64_t)(c.depth + 1) * ceil_div(c.n, RAD_CH) + nc;
+  unsigned grid = (unsigned)ceil_div(max_chunks, RAD_T / 64);
+  hipLaunchKernelGGL(k_radius, dim3(grid), dim3(RAD_T), 0, s, c.c_begin.p, c.c_end.p, choff, tot, nc, c.sx.p,
+                     c.sy.p, c.sz.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.c_rad2bits.p);
   hipLaunchKernelGGL(k_radius_final, grid1(nc), dim3(256), 0, s, c.c_rad2bits.p, nc, c.c_rad.p);
 }
 
@@ -766,6 +776,9 @@ void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
   int64_t total_cells = nsys;
   ensure(c.ws, c.counters, 256);
   long long* tot = (long long*)c.counters.p;
+  int* nleaf_dev = c.counters.p + 2;  // read back with the level totals
+  zero_fill(c, nleaf_dev, sizeof(int));
+  long long nleaf = 0;
   for (int level = 0;; level++) {
     int first = c.lvl_first[level], count = c.lvl_count[level];
     ensure(c.ws, c.c_split, (size_t)count * 11 + 64);
@@ -773,10 +786,14 @@ void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
     int* nch = split + (size_t)9 * count;
     int* choff = nch + count;
     hipLaunchKernelGGL(k_split_level, grid1(count), dim3(256), 0, s, first, count, level,
-                       c.prm.n_leaf, c.key[0].p, c.c_begin.p, c.c_end.p, split, nch);
+                       c.prm.n_leaf, c.key[0].p, c.c_begin.p, c.c_end.p, split, nch, nleaf_dev);
     HIPCHK(hipGetLastError());
     exclusive_scan(c, nch, choff, count, tot);
-    long long next = read_total(c, tot);
+    // children of this level, and the leaves so far, in one read-back
+    HIPCHK(hipMemcpyAsync(c.hbuf, tot, 2 * sizeof(long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    long long next = c.hbuf[0];
+    nleaf = ((const int*)c.hbuf)[2];
     if ((size_t)(total_cells + next) > c.c_level.cap) ensure_cells((size_t)(total_cells + next) * 2, true);
     hipLaunchKernelGGL(k_emit_children, grid1(count), dim3(256), 0, s, first, count, level,
                        (int)total_cells, split, nch, choff, c.c_level.p, c.c_begin.p, c.c_end.p,
@@ -795,8 +812,7 @@ void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
   hipLaunchKernelGGL(k_leaf_of, grid1(nc), dim3(256), 0, s, c.c_begin.p, c.c_end.p, c.c_nchild.p, nc,
                      c.leaf_of.p);
   HIPCHK(hipGetLastError());
-  // leaf count (host, from the level loop is not available): count on device via scan of flags
-  c.nleaf = -1;  // filled lazily by fmm_stats
+  c.nleaf = nleaf;
 }
 
 }  // namespace fmm

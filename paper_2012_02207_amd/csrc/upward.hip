@@ -262,11 +262,10 @@ void upward_pass(Ctx& c) {
   int* flag = c.c_split.p;
   int* off = flag + nc + 32;
   int* leaves = c.leaves.p;
-  long long* tot = (long long*)c.counters.p;
   hipLaunchKernelGGL(k_list_leaves, dim3((nc + 255) / 256), dim3(256), 0, s, c.c_nchild.p, nc, flag);
-  exclusive_scan(c, flag, off, nc, tot);
+  exclusive_scan(c, flag, off, nc, nullptr);
   hipLaunchKernelGGL(k_compact_leaves, dim3((nc + 255) / 256), dim3(256), 0, s, flag, off, nc, leaves);
-  c.nleaf = read_total(c, tot);
+  // c.nleaf was counted by the tree build, so nothing here waits for the device
   expansions_up(c);
 }
 

@@ -16,6 +16,8 @@
 // sorted by source, so all consumers see a deterministic order.
 #include <hip/hip_runtime.h>
 
+#include <functional>
+
 #include <algorithm>
 
 #include "fmm_device.h"
@@ -275,8 +277,11 @@ static void group_by_sink(Ctx& c, CellList& L) {
   HIPCHK(hipGetLastError());
 }
 
+// beside: host work (launches on other streams) done once, right after the
+// first batch of walk steps is enqueued and before the host waits for them
 template <int KIND, int P>
-static void run_walk(Ctx& c, CellList& acc, CellList& nearl, bool group) {
+static void run_walk(Ctx& c, CellList& acc, CellList& nearl, bool group,
+                     const std::function<void()>& beside = {}) {
   hipStream_t s = c.stream;
   CellView v{};
   v.nch = c.c_nchild.p;
@@ -317,6 +322,7 @@ static void run_walk(Ctx& c, CellList& acc, CellList& nearl, bool group) {
                            (int)c.front[1 - (step & 1)].cap, ctr, acc.raw.p, (int)acc.raw.cap,
                            nearl.raw.p, (int)nearl.raw.cap, bits);
       HIPCHK(hipGetLastError());
+      if (beside && attempt == 0 && step == steps) beside();
       HIPCHK(hipMemcpyAsync(h, ctr, WC_INTS * sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       done = h[WC_FRONT + 32 * (step % 3)] == 0;  // frontier of the next step is empty
@@ -462,13 +468,13 @@ __global__ void k_fmin(int first, int count, const int* cb, const int* ce, const
   fmin[c] = m;
 }
 
-void estimate_walk(Ctx& c) {
+void estimate_walk(Ctx& c, const std::function<void()>& beside) {
   hipStream_t s = c.stream;
   int nc = (int)c.ncell;
   ensure(c.ws, c.fcell, nc);
   ensure(c.ws, c.fmin, nc);
   ensure(c.ws, c.fpart, (size_t)c.n);
-  run_walk<0, 0>(c, c.est_far, c.est_near, true);
+  run_walk<0, 0>(c, c.est_far, c.est_near, true, beside);
   hipLaunchKernelGGL(k_fcell, dim3((nc + 255) / 256), dim3(256), 0, s, nc, c.est_far.off.p,
                      c.est_far.src.p, c.c_mass.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.fcell.p);
   {
