@@ -306,17 +306,24 @@ __global__ void __launch_bounds__(RS_T) k_rs_hist(const K* key, int64_t n, int s
   hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
+// Ranks as above, then the tile is reordered by digit in LDS and written out
+// with consecutive lanes on consecutive destinations (each digit's run of the
+// tile is contiguous in the output), so the global writes coalesce.
 template <bool VAL, class KI, class KO>
 __global__ void __launch_bounds__(RS_T) k_rs_scatter(const KI* kin, const int* vin, KO* kout, int* vout,
                                                      int64_t n, int shift, const int* offs, int nblocks) {
   __shared__ int wcnt[RS_W][256];
-  __shared__ int goff[256];
+  __shared__ int goff[256], lofs[256], wsum[RS_W];
+  __shared__ KO sk[RS_TILE];
+  __shared__ int sv[VAL ? RS_TILE : 1];
   int w = threadIdx.x >> 6;
   int lane = threadIdx.x & 63;
   for (int t = threadIdx.x; t < RS_W * 256; t += RS_T) (&wcnt[0][0])[t] = 0;
   goff[threadIdx.x] = offs[(int64_t)threadIdx.x * nblocks + blockIdx.x];
   __syncthreads();
-  int64_t base = (int64_t)blockIdx.x * RS_TILE + (int64_t)w * (RS_TILE / RS_W);
+  int64_t tile0 = (int64_t)blockIdx.x * RS_TILE;
+  int64_t base = tile0 + (int64_t)w * (RS_TILE / RS_W);
+  int tcount = (int)(n - tile0 < RS_TILE ? n - tile0 : RS_TILE);
   KI k[RS_I];
   int v[RS_I], rank[RS_I];
   uint64_t lt = lanemask_lt();
@@ -340,23 +347,41 @@ __global__ void __launch_bounds__(RS_T) k_rs_scatter(const KI* kin, const int* v
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  {
-    int d = threadIdx.x, s = 0;
-    for (int ww = 0; ww < RS_W; ww++) {
-      int t = wcnt[ww][d];
-      wcnt[ww][d] = s;
-      s += t;
-    }
+  // per digit: offsets of the waves within the tile's run, and the run length
+  int d0 = threadIdx.x, tot = 0;
+  for (int ww = 0; ww < RS_W; ww++) {
+    int t = wcnt[ww][d0];
+    wcnt[ww][d0] = tot;
+    tot += t;
   }
+  // exclusive scan of the run lengths over the 256 digits (one per thread)
+  int incl = tot;
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int before_w = 0;
+  for (int ww = 0; ww < w; ww++) before_w += wsum[ww];
+  lofs[d0] = before_w + incl - tot;
   __syncthreads();
   for (int c = 0; c < RS_I; c++) {
     int64_t j = base + (int64_t)c * 64 + lane;
     if (j >= n) continue;
     int d = (int)((k[c] >> shift) & 255);
-    int64_t dst = (int64_t)goff[d] + wcnt[w][d] + rank[c];
+    int lp = lofs[d] + wcnt[w][d] + rank[c];
+    sk[lp] = (KO)k[c];
+    if (VAL) sv[lp] = v[c];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < tcount; t += RS_T) {
+    KO key = sk[t];
+    int d = (int)((key >> shift) & 255);
+    int64_t dst = (int64_t)goff[d] + (t - lofs[d]);
     if (dst < n) {  // always true when the ranks are consistent with the histogram
-      kout[dst] = (KO)k[c];
-      if (VAL) vout[dst] = v[c];
+      kout[dst] = key;
+      if (VAL) vout[dst] = sv[t];
     }
   }
 }
