@@ -291,7 +291,7 @@ __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per
   int nblk = (nlo + MX_WAVES - 1) / MX_WAVES;
   int per = (nblk + 7) >> 3;
   int blk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  int wv = threadIdx.x >> 6;
+  int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: B and its data in SGPRs
   int B = first_lo + blk * MX_WAVES + wv;
   if (blk >= nblk || B >= ncell) return;
   int e = off[B + 1];
