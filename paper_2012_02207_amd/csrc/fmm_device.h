@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "fmm_internal.h"
 
@@ -109,6 +110,149 @@ __device__ __forceinline__ double fmm_fact_dev(int n) {
   double r = 1.0;
   for (int i = 2; i <= n; i++) r *= (double)i;
   return r;
+}
+
+
+// ---- cross-lane transpose-reduce (the M2L kernels) ------------------------
+// D values per lane summed over the 64 lanes in six halving steps with
+// partner distances 32, 16, 8, 4, 2, 1.  With L values left, a lane keeps the
+// first ceil(L/2) of them or the rest, by that bit of its lane id, and adds its
+// partner's copy of the kept part; once a single value is left the steps are
+// plain butterflies.  A lane on the upper side of an odd L keeps one slot more
+// than there are values: that pad slot holds an unused sum, and pads only ever
+// meet pads (partners share every earlier bit), so they need no clearing.
+// The total of value j ends in lane reduce_owner(D, j).
+constexpr int reduce_len(int D, int t) {
+  int L = D;
+  for (int k = 0; k < t; k++) L = (L + 1) / 2;
+  return L;
+}
+constexpr int reduce_owner(int D, int j) {
+  int lane = 0, L = D;
+  for (int t = 0; t < 6; t++) {
+    if (L >= 2) {
+      int h = (L + 1) / 2;
+      if (j >= h) {
+        lane |= 32 >> t;
+        j -= h;
+      }
+      L = h;
+    }
+  }
+  return lane;
+}
+
+// reduce_owner inverted: the value j whose total this lane ends with, and
+// whether that is a real value (not a pad)
+template <int D>
+__device__ __forceinline__ void reduce_slot(int lane, int& j, int& real) {
+  j = 0;
+  int left = D;  // real values in this lane's part
+  bool ok = true;
+#pragma unroll
+  for (int t = 0; t < 6; t++) {
+    int L = reduce_len(D, t);
+    bool bit = (lane & (32 >> t)) != 0;
+    if (L >= 2) {
+      int H = (L + 1) / 2;
+      j += bit ? H : 0;
+      left = bit ? left - H : (left < H ? left : H);
+    } else {
+      ok = ok && !bit;
+    }
+  }
+  real = ok && left >= 1;
+}
+
+// DPP control of the steps at distances 8, 4, 2, 1 (t = 2..5): row mirror,
+// half-row mirror, quad_perm [2,3,0,1], quad_perm [1,0,3,2]; each pairs lanes
+// that differ in that bit
+constexpr int reduce_dpp_ctrl(int t) { return t == 2 ? 0x140 : t == 3 ? 0x141 : t == 4 ? 0x4E : 0xB1; }
+
+// lanes 32..63 of a <-> lanes 0..31 of b (T = 0), or the odd 16-lane rows of a
+// <-> the even rows of b (T = 1)
+template <int T>
+__device__ __forceinline__ void lane_swap(uint32_t& a, uint32_t& b) {
+  if constexpr (T == 0) {
+    auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    a = (uint32_t)r[0];
+    b = (uint32_t)r[1];
+  } else {
+    auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+    a = (uint32_t)r[0];
+    b = (uint32_t)r[1];
+  }
+}
+template <int T>
+__device__ __forceinline__ void lane_swap(float& a, float& b) {
+  uint32_t ua = __builtin_bit_cast(uint32_t, a), ub = __builtin_bit_cast(uint32_t, b);
+  lane_swap<T>(ua, ub);
+  a = __builtin_bit_cast(float, ua);
+  b = __builtin_bit_cast(float, ub);
+}
+template <int T>
+__device__ __forceinline__ void lane_swap(double& a, double& b) {
+  uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+  uint32_t alo = (uint32_t)ua, ahi = (uint32_t)(ua >> 32), blo = (uint32_t)ub, bhi = (uint32_t)(ub >> 32);
+  lane_swap<T>(alo, blo);
+  lane_swap<T>(ahi, bhi);
+  a = __builtin_bit_cast(double, ((uint64_t)ahi << 32) | alo);
+  b = __builtin_bit_cast(double, ((uint64_t)bhi << 32) | blo);
+}
+
+// the value of v in the lane that DPP control CTRL selects
+template <int CTRL>
+__device__ __forceinline__ float dpp_read(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_read(double v) {
+  uint64_t u = __builtin_bit_cast(uint64_t, v);
+  int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// compile-time loop: f(std::integral_constant<int, i>) for i in [I, E)
+template <int I, int E, class F>
+__device__ __forceinline__ void unroll_for(F&& f) {
+  if constexpr (I < E) {
+    f(std::integral_constant<int, I>{});
+    unroll_for<I + 1, E>(f);
+  }
+}
+
+// x[0..D) of every lane -> the cross-lane totals (in place, see above); each
+// lane adds its last value to *acc_slot, meaningful in the owner lanes only
+template <int D, class T>
+__device__ __forceinline__ void reduce_lanes(T* x, double* acc_slot, int lane) {
+  unroll_for<0, 6>([&](auto tc) {
+    constexpr int t = tc;
+    constexpr int L = reduce_len(D, t);
+    constexpr int H = (L + 1) / 2;
+    if constexpr (t < 2) {
+      unroll_for<0, H>([&](auto ic) {
+        constexpr int i = ic;
+        T a = x[i], b = x[i];  // L == 1 (or the pad of an odd L): a butterfly
+        if constexpr (i + H < L) b = x[i + H];
+        lane_swap<t>(a, b);
+        x[i] = a + b;
+      });
+    } else {
+      constexpr int CTRL = reduce_dpp_ctrl(t);
+      bool hi = (lane & (32 >> t)) != 0;
+      unroll_for<0, H>([&](auto ic) {
+        constexpr int i = ic;
+        T r = x[i] + dpp_read<CTRL>(x[i]);
+        if constexpr (i + H < L) {
+          T q = x[i + H] + dpp_read<CTRL>(x[i + H]);
+          r = hi ? q : r;
+        }
+        x[i] = r;
+      });
+    }
+  });
+  *acc_slot += (double)x[0];
 }
 
 }  // namespace fmm

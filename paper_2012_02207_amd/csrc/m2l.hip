@@ -137,50 +137,6 @@ __device__ __forceinline__ void zrot(T* v, T c1, T s1) {
 // of that half (about D + 6 shuffles instead of 6 D).  Afterwards the total of
 // value j sits in lane j * (64 / Dp) (Dp = D rounded up to a power of two),
 // which adds it to its accumulator acc_slot.
-constexpr int pow2_ceil(int d) {
-  int p = 1;
-  while (p < d) p <<= 1;
-  return p;
-}
-constexpr int ilog2(int d) {
-  int k = 0;
-  while ((1 << k) < d) k++;
-  return k;
-}
-
-template <int D>
-__device__ __forceinline__ void reduce_order(const double* v, double* acc_slot, int lane, bool act) {
-  constexpr int DP = pow2_ceil(D);
-  double x[DP];
-  static_for<0, DP>([&](auto jc) {
-    constexpr int j = jc;
-    if constexpr (j < D)
-      x[j] = act ? v[j] : 0.0;
-    else
-      x[j] = 0.0;
-  });
-  static_for<0, ilog2(DP)>([&](auto tc) {
-    constexpr int t = tc;
-    constexpr int s = 32 >> t;          // partner distance
-    constexpr int half = DP >> (t + 1);
-    bool hi = (lane & s) != 0;
-    static_for<0, half>([&](auto ic) {
-      constexpr int i = ic;
-      double keep = hi ? x[i + half] : x[i];
-      double give = hi ? x[i] : x[i + half];
-      x[i] = keep + __shfl_xor(give, s, 64);
-    });
-  });
-  static_for<ilog2(DP), 6>([&](auto tc) {
-    constexpr int s = 32 >> tc;
-    x[0] += __shfl_xor(x[0], s, 64);
-  });
-  constexpr int K = 6 - ilog2(DP);      // owner lanes: low K bits zero
-  int j = lane >> K;
-  bool own = ((lane & ((1 << K) - 1)) == 0) && j < D;
-  *acc_slot += own ? (double)x[0] : 0.0;
-}
-
 constexpr int M2L_WAVES = 4;  // sinks per workgroup (one per wavefront)
 
 // M2L of the list of one sink cell B (one wavefront; lane = lane id); with
@@ -233,9 +189,11 @@ __device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, con
     }
     double cb = Rz * rinv, sb = -rho * rinv;
     // translation factors g_j = j! / r^{j+1}
+    // (an inactive lane, past the end of the list, gets zero factors, so all
+    // its outputs are zero)
     double g[P + 1];
     {
-      double rp = rinv;
+      double rp = act ? rinv : 0.0;
 #pragma unroll
       for (int j = 0; j <= P; j++) {
         g[j] = cfact(j) * rp;
@@ -349,17 +307,18 @@ __device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, con
       zrot<n>(w, cb, -sb);
       swap_apply<n>(w, sw);
       zrot<n>(w, ca, -sa);
-      reduce_order<2 * n + 1>(w, &acc[n], lane, act);
+      reduce_lanes<2 * n + 1>(w, &acc[n], lane);
     });
   }
   // back to the unscaled basis: L_n^m = (n-m)!(n+m)! Lhat_n^m; real-basis
-  // entry j of order n is owned by lane j * 64 / Dp (see reduce_order)
+  // entry j of order n is held by lane reduce_owner(2n+1, j) (the cross-lane
+  // sum in fmm_device.h)
   double* out = loc + (size_t)B * NC * 2;
   static_for<0, P + 1>([&](auto nc) {
     constexpr int n = nc;
-    constexpr int K = 6 - ilog2(pow2_ceil(2 * n + 1));
-    int j = lane >> K;
-    if ((lane & ((1 << K) - 1)) == 0 && j < 2 * n + 1) {
+    int j, real;
+    reduce_slot<2 * n + 1>(lane, j, real);
+    if (real) {
       int m = (j + 1) >> 1;
       bool im = j > 0 && !(j & 1);
       double f = c_fact_m2l[n - m] * c_fact_m2l[n + m];

@@ -128,124 +128,6 @@ __device__ __forceinline__ void zrot(float* v, float c1, float s1) {
   });
 }
 
-// Cross-lane sum of D values per lane (transpose-reduce) in six halving steps
-// with partner distances 32, 16, 8, 4, 2, 1.  With L values left, a lane keeps
-// the first ceil(L/2) of them or the rest (padded with a zero), by that bit of
-// its lane id, and adds its partner's copy of the kept part; once a single
-// value is left the steps are plain butterflies.  Distances 32 and 16 exchange
-// register halves between lane groups (permlane32/16 swaps, no LDS traffic);
-// distances 8 to 1 read the partner through DPP (row mirror, half-row mirror,
-// two quad permutations: each pairs lanes that differ in that bit).  The total
-// of value j ends in lane reduce_owner(D, j).
-constexpr int reduce_len(int D, int t) {
-  int L = D;
-  for (int k = 0; k < t; k++) L = (L + 1) / 2;
-  return L;
-}
-constexpr int reduce_owner(int D, int j) {
-  int lane = 0, L = D;
-  for (int t = 0; t < 6; t++) {
-    if (L >= 2) {
-      int h = (L + 1) / 2;
-      if (j >= h) {
-        lane |= 32 >> t;
-        j -= h;
-      }
-      L = h;
-    }
-  }
-  return lane;
-}
-
-// the entry j whose total lane ends with, and whether it is a real entry
-// (not one of the zero pads): reduce_owner inverted
-template <int D>
-__device__ __forceinline__ void reduce_slot(int lane, int& j, int& real) {
-  j = 0;
-  int left = D;  // real entries in this lane's part
-  bool ok = true;
-  static_for<0, 6>([&](auto tc) {
-    constexpr int t = tc;
-    constexpr int L = reduce_len(D, t);
-    bool bit = (lane & (32 >> t)) != 0;
-    if constexpr (L >= 2) {
-      constexpr int H = (L + 1) / 2;
-      j += bit ? H : 0;
-      left = bit ? left - H : min(left, H);
-    } else {
-      ok = ok && !bit;
-    }
-  });
-  real = ok && left >= 1;
-}
-
-// lanes 32..63 of a <-> lanes 0..31 of b (T = 0), or the odd 16-lane rows of a
-// <-> the even rows of b (T = 1)
-template <int T>
-__device__ __forceinline__ void lane_swap(float& a, float& b) {
-  unsigned ua = __builtin_bit_cast(unsigned, a), ub = __builtin_bit_cast(unsigned, b);
-  if constexpr (T == 0) {
-    auto r = __builtin_amdgcn_permlane32_swap(ua, ub, false, false);
-    a = __builtin_bit_cast(float, (unsigned)r[0]);
-    b = __builtin_bit_cast(float, (unsigned)r[1]);
-  } else {
-    auto r = __builtin_amdgcn_permlane16_swap(ua, ub, false, false);
-    a = __builtin_bit_cast(float, (unsigned)r[0]);
-    b = __builtin_bit_cast(float, (unsigned)r[1]);
-  }
-}
-
-template <int CTRL>
-__device__ __forceinline__ float dpp_read(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
-}
-
-// x[0..D) of every lane -> the cross-lane totals; each lane adds its last
-// value to *acc_slot (meaningful in the owner lanes only)
-template <int D>
-__device__ __forceinline__ void reduce_order(float* x, double* acc_slot, int lane) {
-  static_for<0, 6>([&](auto tc) {
-    constexpr int t = tc;
-    constexpr int L = reduce_len(D, t);
-    if constexpr (t < 2) {
-      if constexpr (L == 1) {
-        float a = x[0], b = x[0];
-        lane_swap<t>(a, b);
-        x[0] = a + b;
-      } else {
-        constexpr int H = (L + 1) / 2;
-        static_for<0, H>([&](auto ic) {
-          constexpr int i = ic;
-          float a = x[i], b = 0.f;
-          if constexpr (i + H < L) b = x[i + H];
-          lane_swap<t>(a, b);
-          x[i] = a + b;
-        });
-      }
-    } else {
-      // row mirror, half-row mirror, quad_perm [2,3,0,1], quad_perm [1,0,3,2]
-      constexpr int CTRL = t == 2 ? 0x140 : t == 3 ? 0x141 : t == 4 ? 0x4E : 0xB1;
-      if constexpr (L == 1) {
-        x[0] = x[0] + dpp_read<CTRL>(x[0]);
-      } else {
-        constexpr int H = (L + 1) / 2;
-        bool hi = (lane & (32 >> t)) != 0;
-        static_for<0, H>([&](auto ic) {
-          constexpr int i = ic;
-          float lo_sum = x[i] + dpp_read<CTRL>(x[i]);
-          if constexpr (i + H < L) {
-            float hi_sum = x[i + H] + dpp_read<CTRL>(x[i + H]);
-            x[i] = hi ? hi_sum : lo_sum;
-          } else {
-            x[i] = hi ? 0.f : lo_sum;
-          }
-        });
-      }
-    }
-  });
-  *acc_slot += (double)x[0];
-}
-
 }  // namespace mx
 
 constexpr int MX_CSWAP = mx::cswoff(FMM_GPU_PMAX + 1);
@@ -423,12 +305,12 @@ __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per
       zrot<n>(w, cb, -sb);
       swap_apply<n>(w, sw);
       zrot<n>(w, ca, -sa);
-      reduce_order<2 * n + 1>(w, &acc[64 * n], lane);
+      reduce_lanes<2 * n + 1>(w, &acc[64 * n], lane);
     });
   }
   // back to standard coefficients: L_n^0 += Lt n! / rho_B^n,
   // L_n^m += Lt sqrt((n-m)!(n+m)!/2) / rho_B^n; real-basis entry j of order n
-  // is held by lane reduce_owner(2n+1, j)
+  // is held by lane reduce_owner(2n+1, j) (the cross-lane sum in fmm_device.h)
   double* out = loc + (size_t)B * NC * 2;
   double isB = 1.0 / sB, pw = 1.0;
   static_for<0, P + 1>([&](auto nc) {
