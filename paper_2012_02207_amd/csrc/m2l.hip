@@ -146,7 +146,7 @@ __device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, con
                                               const int* __restrict__ src, const double* __restrict__ cx,
                                               const double* __restrict__ cy, const double* __restrict__ cz,
                                               const double* __restrict__ mult, double* __restrict__ loc,
-                                              const ldouble* swt) {
+                                              const ldouble* swt, double* acc) {
   constexpr int NC = ncoef(P);
   int b = off[B], e = off[B + 1];
   if (B >= first_lo) {
@@ -163,10 +163,9 @@ __device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, con
     e = lo;
   }
   if (b == e) return;
-  // lane-major accumulator: lane j holds coefficient j of order n in acc[n]
-  double acc[P + 1];
+  // per-order sums, one LDS slot per lane: acc[64 n]
 #pragma unroll
-  for (int t = 0; t <= P; t++) acc[t] = 0.0;
+  for (int t = 0; t <= P; t++) acc[64 * t] = 0.0;
   double bx = cx[B], by = cy[B], bz = cz[B];
 
   for (int base = b; base < e; base += 64) {
@@ -307,7 +306,7 @@ __device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, con
       zrot<n>(w, cb, -sb);
       swap_apply<n>(w, sw);
       zrot<n>(w, ca, -sa);
-      reduce_lanes<2 * n + 1>(w, &acc[n], lane);
+      reduce_lanes<2 * n + 1>(w, &acc[64 * n], lane);
     });
   }
   // back to the unscaled basis: L_n^m = (n-m)!(n+m)! Lhat_n^m; real-basis
@@ -322,7 +321,7 @@ __device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, con
       int m = (j + 1) >> 1;
       bool im = j > 0 && !(j & 1);
       double f = c_fact_m2l[n - m] * c_fact_m2l[n + m];
-      out[2 * cidx(n, m) + (im ? 1 : 0)] = acc[n] * f;
+      out[2 * cidx(n, m) + (im ? 1 : 0)] = acc[64 * n] * f;
       if (j == 0) out[2 * cidx(n, 0) + 1] = 0.0;
     }
   });
@@ -330,8 +329,12 @@ __device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, con
 
 // All sinks (one wavefront each, in XCD-contiguous ranges: neighbouring sinks
 // share sources), or, with LIST, the sinks[0 .. *nsinks) in a grid-stride loop.
+// Two waves per SIMD (256 registers each, a few spilled): measured faster than
+// one wave with everything in registers.  The per-order sums live in LDS and
+// the sink index is wave-uniform (its data in SGPRs), which keeps the spills
+// small.
 template <int P, bool LIST>
-__global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l_fp64(int ncell, int first_lo, const int* __restrict__ sinks,
+__global__ void __launch_bounds__(64 * M2L_WAVES) __attribute__((amdgpu_waves_per_eu(2))) k_m2l_fp64(int ncell, int first_lo, const int* __restrict__ sinks,
                                                              const int* __restrict__ nsinks,
                                                              const int* __restrict__ off,
                                                              const int* __restrict__ src,
@@ -344,18 +347,20 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) k_m2l_fp64(int ncell, int firs
   __shared__ double swt[NSW];
   for (int t = threadIdx.x; t < NSW; t += 64 * M2L_WAVES) swt[t] = c_cswap[t];
   __syncthreads();
-  int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  __shared__ double accs[M2L_WAVES][P + 1][64];
+  double* acc = &accs[wv][0][0] + lane;
   if constexpr (LIST) {
     int cnt = *nsinks;
     for (int it = blockIdx.x * M2L_WAVES + wv; it < cnt; it += gridDim.x * M2L_WAVES)
-      m2l_sink_fp64<P>(sinks[it], first_lo, lane, off, src, cx, cy, cz, mult, loc, (const ldouble*)swt);
+      m2l_sink_fp64<P>(sinks[it], first_lo, lane, off, src, cx, cy, cz, mult, loc, (const ldouble*)swt, acc);
   } else {
     int nblk = (ncell + M2L_WAVES - 1) / M2L_WAVES;
     int per = (nblk + 7) >> 3;
     int blk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     int B = blk * M2L_WAVES + wv;
     if (blk < nblk && B < ncell)
-      m2l_sink_fp64<P>(B, first_lo, lane, off, src, cx, cy, cz, mult, loc, (const ldouble*)swt);
+      m2l_sink_fp64<P>(B, first_lo, lane, off, src, cx, cy, cz, mult, loc, (const ldouble*)swt, acc);
   }
 }
 
