@@ -58,11 +58,11 @@ P2P_FLOPS = 20   # per directed body pair: acc + pot, softened, rsqrt counted on
 # (fetch x2.0, write x1.0).  Keyed by (kernel, workload, precision); valid only
 # while the kernel's source file has the recorded SHA-1 (else reported as null).
 MEASURED_TRAFFIC = {
-    ("k_m2l_fp32", "plummer_1m", "mixed"): (496.8e6, "paper_2012_02207_amd/csrc/m2l_mixed.hip",
-                                             "77077b7db4ba7c79f1ac37810eb46023079aa7f9"),
-    ("k_leaf_group<true> (mixed P2P)", "plummer_1m", "mixed"): (172.3e6,
+    ("k_m2l_fp32", "plummer_1m", "mixed"): (533.5e6, "paper_2012_02207_amd/csrc/m2l_mixed.hip",
+                                             "6294f0e874e137e68672e07330b08135c48962e8"),
+    ("k_leaf_group<true> (mixed P2P)", "plummer_1m", "mixed"): (177.4e6,
                                                                 "paper_2012_02207_amd/csrc/local.hip",
-                                                                "0420ced9a76ae9926da9c781d29ecc081e55d968"),
+                                                                "abe2e1e5227e5b242eecacc4a4cd4a7d3defb90b"),
 }
 
 
