@@ -53,16 +53,9 @@ void zero_fill(Ctx& c, void* p, size_t bytes) {
   HIPCHK(hipGetLastError());
 }
 
-// launches of a scope go to another stream of the context
-struct OnStream {
-  Ctx& c;
-  hipStream_t old;
-  OnStream(Ctx& cc, hipStream_t s) : c(cc), old(cc.stream) { c.stream = s; }
-  ~OnStream() { c.stream = old; }
-};
 
 // stream `to` waits for the work enqueued so far on `from` (event e)
-static void stream_wait(hipEvent_t e, hipStream_t from, hipStream_t to) {
+void stream_wait(hipEvent_t e, hipStream_t from, hipStream_t to) {
   HIPCHK(hipEventRecord(e, from));
   HIPCHK(hipStreamWaitEvent(to, e, 0));
 }
@@ -113,7 +106,7 @@ void evaluate(Ctx& c, double* acc, double* pot, bool group) {
   {
     OnStream on(c, c.side);
     if (group) {
-      SideScratch alt(c);
+      SideScratch alt(c, 2);
       group_list(c, c.p2p);
     }
     if (c.have_events) HIPCHK(hipEventRecord(c.ev[6], c.side));
@@ -258,7 +251,6 @@ static void build_and_estimate(Ctx& c, int64_t n, const double* pos, const doubl
   // that neither waits for the other's launches
   estimate_walk(c, [&]() {
     OnStream on(c, c.side);
-    SideScratch alt(c);  // the estimate walk sorts its lists meanwhile
     upward_pass(c);
     HIPCHK(hipEventRecord(c.ev[14], c.side));
   });
@@ -750,7 +742,7 @@ void fmm_destroy(fmm_ctx* ctx) {
     rel(c.idx[k]);
     rel(c.front[k]);
   }
-  rel(c.sx); rel(c.sy); rel(c.sz); rel(c.sm); rel(c.pm); rel(c.pkb); rel(c.scale); rel(c.nmult); rel(c.fpart); rel(c.leaf_of); rel(c.leaves); rel(c.nearbuf); rel(c.loc64); rel(c.root_sinks); rel(c.madj); rel(c.ladj); rel(c.fwd_acc); rel(c.fwd_pot); rel(c.gsort); rel(c.asort); rel(c.sys_off); rel(c.skey[0]); rel(c.skey[1]); rel(c.spos[0]); rel(c.spos[1]); rel(c.sort_hist); rel(c.sort_hist2); rel(c.scan_tmp2);
+  rel(c.sx); rel(c.sy); rel(c.sz); rel(c.sm); rel(c.pm); rel(c.pkb); rel(c.scale); rel(c.nmult); rel(c.fpart); rel(c.leaf_of); rel(c.leaves); rel(c.nearbuf); rel(c.loc64); rel(c.root_sinks); rel(c.madj); rel(c.ladj); rel(c.fwd_acc); rel(c.fwd_pot); rel(c.gsort); rel(c.asort); rel(c.sys_off); rel(c.skey[0]); rel(c.skey[1]); rel(c.spos[0]); rel(c.spos[1]); rel(c.sort_hist); rel(c.sort_hist2); rel(c.scan_tmp2); rel(c.sort_hist3); rel(c.scan_tmp3);
   rel(c.bbox_part); rel(c.rootbox); rel(c.c_level); rel(c.c_begin); rel(c.c_end); rel(c.c_parent);
   rel(c.c_child0); rel(c.c_nchild); rel(c.c_split); rel(c.c_mass); rel(c.c_sx); rel(c.c_sy);
   rel(c.c_sz); rel(c.c_cx); rel(c.c_cy); rel(c.c_cz); rel(c.c_rad); rel(c.c_rad2bits); rel(c.mult);

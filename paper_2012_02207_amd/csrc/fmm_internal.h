@@ -157,9 +157,9 @@ struct Ctx {
   // scan scratch
   dbuf<int> scan_tmp;
   dbuf<long long> scan_tmp64;
-  // a second set of sort and scan scratch for work on the side stream that
-  // runs while the caller's stream sorts or scans (see SideScratch)
-  dbuf<int> sort_hist2, scan_tmp2;
+  // second and third sets of sort and scan scratch for work on the side
+  // streams that runs while the caller's stream sorts or scans (SideScratch)
+  dbuf<int> sort_hist2, scan_tmp2, sort_hist3, scan_tmp3;
 
   // host pinned scratch for small read-backs
   long long* hbuf = nullptr;
@@ -173,7 +173,7 @@ struct Ctx {
   // stream: the upward pass beside the estimate walk, the near field beside
   // M2L and L2L; forked and joined with the events below
   hipStream_t side = nullptr, side2 = nullptr;  // side2: root-level FP64 M2L
-  hipEvent_t fork[6] = {};
+  hipEvent_t fork[8] = {};
   dbuf<double4> nearbuf;  // near-field (acc, pot) per sorted body
 
   // replay of the frozen-tree evaluation as a HIP graph (captured per set of
@@ -187,19 +187,32 @@ struct Ctx {
 };
 
 // Sorts and scans take their scratch from c.sort_hist and c.scan_tmp; within
-// this scope they use the second set, so that a sort on the side stream may
-// run concurrently with one on the caller's stream.
+// this scope they use the second (set = 2) or third (set = 3) set, so that
+// sorts on the side streams may run concurrently with one on the caller's.
 struct SideScratch {
   Ctx& c;
-  explicit SideScratch(Ctx& cc) : c(cc) {
-    std::swap(c.sort_hist, c.sort_hist2);
-    std::swap(c.scan_tmp, c.scan_tmp2);
+  dbuf<int>&h, &t;
+  SideScratch(Ctx& cc, int set)
+      : c(cc), h(set == 2 ? cc.sort_hist2 : cc.sort_hist3), t(set == 2 ? cc.scan_tmp2 : cc.scan_tmp3) {
+    std::swap(c.sort_hist, h);
+    std::swap(c.scan_tmp, t);
   }
   ~SideScratch() {
-    std::swap(c.sort_hist, c.sort_hist2);
-    std::swap(c.scan_tmp, c.scan_tmp2);
+    std::swap(c.sort_hist, h);
+    std::swap(c.scan_tmp, t);
   }
 };
+
+// launches of a scope go to another stream of the context
+struct OnStream {
+  Ctx& c;
+  hipStream_t old;
+  OnStream(Ctx& cc, hipStream_t s) : c(cc), old(cc.stream) { c.stream = s; }
+  ~OnStream() { c.stream = old; }
+};
+
+// `to` waits (on the device) for the work enqueued so far on `from`
+void stream_wait(hipEvent_t e, hipStream_t from, hipStream_t to);
 
 // ------------------------------------------------------------------ stages
 void exclusive_scan(Ctx& c, const int* in, int* out, int64_t n, long long* total_dev);

@@ -721,6 +721,16 @@ void refresh_frozen(Ctx& c, const double* pos, const double* mass) {
   cell_moments(c, false);
 }
 
+__global__ void k_list_leaves(const int* nch, int ncell, int* flag) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncell) flag[c] = nch[c] == 0 ? 1 : 0;
+}
+
+__global__ void k_compact_leaves(const int* flag, const int* off, int ncell, int* leaves) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncell && flag[c]) leaves[off[c]] = c;
+}
+
 void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
   hipStream_t s = c.stream;
   c.n = n;
@@ -836,6 +846,16 @@ void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
   cell_moments(c, true);
   hipLaunchKernelGGL(k_leaf_of, grid1(nc), dim3(256), 0, s, c.c_begin.p, c.c_end.p, c.c_nchild.p, nc,
                      c.leaf_of.p);
+  HIPCHK(hipGetLastError());
+  // the leaf cells in id order (built here, before any fork, so that every
+  // stream sees the list)
+  ensure(c.ws, c.c_split, (size_t)2 * nc + 64);
+  ensure(c.ws, c.leaves, (size_t)nc);
+  int* flag = c.c_split.p;
+  int* off = flag + nc + 32;
+  hipLaunchKernelGGL(k_list_leaves, grid1(nc), dim3(256), 0, s, c.c_nchild.p, nc, flag);
+  exclusive_scan(c, flag, off, nc, nullptr);
+  hipLaunchKernelGGL(k_compact_leaves, grid1(nc), dim3(256), 0, s, flag, off, nc, c.leaves.p);
   HIPCHK(hipGetLastError());
   c.nleaf = nleaf;
 }

@@ -226,16 +226,6 @@ __global__ void k_pk(int p, int ncell, const double* mult, double* pk, double* p
   pkb[t] = c_binom[p][k] * P;
 }
 
-__global__ void k_list_leaves(const int* nch, int ncell, int* flag) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < ncell) flag[c] = nch[c] == 0 ? 1 : 0;
-}
-
-__global__ void k_compact_leaves(const int* flag, const int* off, int ncell, int* leaves) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < ncell && flag[c]) leaves[off[c]] = c;
-}
-
 // M2M from the deepest parents to the roots over the multipole buffer `mult`
 void m2m_levels(Ctx& c, double* mult) {
   for (int level = c.depth - 1; level >= 0; level--) {
@@ -252,24 +242,15 @@ void upward_pass(Ctx& c) {
     HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_binom), fmm_binom_table, sizeof(fmm_binom_table)));
     g_up_tables = true;
   }
-  hipStream_t s = c.stream;
   int p = c.p, nc = (int)c.ncell;
   ensure(c.ws, c.mult, (size_t)nc * ncoef(p) * 2);
   ensure(c.ws, c.pk, (size_t)nc * (p + 1));
-  // leaf list
-  ensure(c.ws, c.c_split, (size_t)2 * nc + 64);
-  ensure(c.ws, c.leaves, (size_t)nc);
-  int* flag = c.c_split.p;
-  int* off = flag + nc + 32;
-  int* leaves = c.leaves.p;
-  hipLaunchKernelGGL(k_list_leaves, dim3((nc + 255) / 256), dim3(256), 0, s, c.c_nchild.p, nc, flag);
-  exclusive_scan(c, flag, off, nc, nullptr);
-  hipLaunchKernelGGL(k_compact_leaves, dim3((nc + 255) / 256), dim3(256), 0, s, flag, off, nc, leaves);
-  // c.nleaf was counted by the tree build, so nothing here waits for the device
+  // the leaf list and count come from the tree build, so nothing here waits
+  // for the device
   expansions_up(c);
 }
 
-// P2M at the leaves (list built above), M2M to the roots, P_k
+// P2M at the leaves (the list from the tree build), M2M to the roots, P_k
 void expansions_up(Ctx& c) {
   hipStream_t s = c.stream;
   int p = c.p, nc = (int)c.ncell;

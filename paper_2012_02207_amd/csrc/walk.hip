@@ -372,8 +372,8 @@ __global__ void k_fcell(int ncell, const int* off, const int* src, const double*
   F[B] = f;
 }
 
-// f_i = (F summed from the root down to the leaf) + sum_{j near, j != i} m_j / d^2,
-// partners in ascending id, bodies in sorted order, one running sum per body.
+// near_i = sum_{j near, j != i} m_j / d^2, partners in ascending id, bodies in
+// sorted order, one running sum per body (k_fmin adds the far part).
 // One wavefront per sink leaf, a lane per sink body; each source leaf is
 // staged in LDS (one coalesced load, the next one fetched while the current
 // one is summed) and read by all lanes as broadcasts.
@@ -382,10 +382,8 @@ constexpr int NF_WAVES = 4;
 __global__ void __launch_bounds__(64 * NF_WAVES) k_near_f(int nleaves, const int* __restrict__ leaves,
                                                           const int* __restrict__ cb,
                                                           const int* __restrict__ ce,
-                                                          const int* __restrict__ parent,
                                                           const int* __restrict__ off,
                                                           const int* __restrict__ src,
-                                                          const double* __restrict__ F,
                                                           const double4* __restrict__ pm, double* f) {
   __shared__ double4 sbuf[NF_WAVES][64];
   int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -395,13 +393,6 @@ __global__ void __launch_bounds__(64 * NF_WAVES) k_near_f(int nleaves, const int
   int li = blk * NF_WAVES + wv;
   if (blk >= nblk || li >= nleaves) return;
   int B = leaves[li];
-  double far = 0.0;
-  {
-    int path[FMM_MAX_LEVEL + 2];
-    int len = 0;
-    for (int q = B; q >= 0; q = parent[q]) path[len++] = q;
-    for (int t = len - 1; t >= 0; t--) far = far + F[path[t]];
-  }
   int b = cb[B], e = ce[B];
   int qb = off[B], qe = off[B + 1];
   for (int i0 = b; i0 < e; i0 += 64) {
@@ -445,21 +436,32 @@ __global__ void __launch_bounds__(64 * NF_WAVES) k_near_f(int nleaves, const int
       j0 = nj0;
       je = nje;
     }
-    if (act) f[i] = far + near;
+    if (act) f[i] = near;
     __builtin_amdgcn_wave_barrier();
   }
 }
 
-__global__ void k_fmin(int first, int count, const int* cb, const int* ce, const int* c0,
-                       const int* nch, const double* f, double* fmin) {
+// minimum of f over each cell of one level (deepest level first).  A leaf
+// first completes its bodies' estimates, f_i = (F summed from the root down to
+// the leaf) + near_i, in that order (f holds near_i on entry).
+__global__ void k_fmin(int first, int count, const int* cb, const int* ce, const int* c0, const int* nch,
+                       const int* parent, const double* F, double* f, double* fmin) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= count) return;
   int c = first + t;
   double m;
   if (nch[c] == 0) {
+    int path[FMM_MAX_LEVEL + 2];
+    int len = 0;
+    for (int q = c; q >= 0; q = parent[q]) path[len++] = q;
+    double far = 0.0;
+    for (int k = len - 1; k >= 0; k--) far = far + F[path[k]];
     m = INFINITY;
-    for (int i = cb[c]; i < ce[c]; i++)
-      if (f[i] < m) m = f[i];
+    for (int i = cb[c]; i < ce[c]; i++) {
+      double v = far + f[i];
+      f[i] = v;
+      if (v < m) m = v;
+    }
   } else {
     m = fmin[c0[c]];
     for (int k = 1; k < nch[c]; k++)
@@ -468,26 +470,36 @@ __global__ void k_fmin(int first, int count, const int* cb, const int* ce, const
   fmin[c] = m;
 }
 
+// The far sums F_B (list grouped on the second side stream, with the third
+// set of sort scratch) run beside the near sums on the caller's stream; the
+// join comes before the cell minima, which add the two.
 void estimate_walk(Ctx& c, const std::function<void()>& beside) {
   hipStream_t s = c.stream;
   int nc = (int)c.ncell;
   ensure(c.ws, c.fcell, nc);
   ensure(c.ws, c.fmin, nc);
   ensure(c.ws, c.fpart, (size_t)c.n);
-  run_walk<0, 0>(c, c.est_far, c.est_near, true, beside);
-  hipLaunchKernelGGL(k_fcell, dim3((nc + 255) / 256), dim3(256), 0, s, nc, c.est_far.off.p,
-                     c.est_far.src.p, c.c_mass.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.fcell.p);
+  run_walk<0, 0>(c, c.est_far, c.est_near, false, beside);
+  stream_wait(c.fork[6], s, c.side2);
+  {
+    OnStream on(c, c.side2);
+    SideScratch alt(c, 3);
+    group_by_sink(c, c.est_far);
+    hipLaunchKernelGGL(k_fcell, dim3((nc + 255) / 256), dim3(256), 0, c.side2, nc, c.est_far.off.p,
+                       c.est_far.src.p, c.c_mass.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.fcell.p);
+  }
+  group_by_sink(c, c.est_near);
   {
     int nblk = (int)ceil_div(c.nleaf, NF_WAVES);
     unsigned grid = 8u * (unsigned)ceil_div(nblk, 8);
     hipLaunchKernelGGL(k_near_f, dim3(grid), dim3(64 * NF_WAVES), 0, s, (int)c.nleaf, c.leaves.p,
-                       c.c_begin.p, c.c_end.p, c.c_parent.p, c.est_near.off.p, c.est_near.src.p,
-                       c.fcell.p, c.pm.p, c.fpart.p);
+                       c.c_begin.p, c.c_end.p, c.est_near.off.p, c.est_near.src.p, c.pm.p, c.fpart.p);
   }
+  stream_wait(c.fork[7], c.side2, s);
   for (int level = c.depth; level >= 0; level--) {
     int first = c.lvl_first[level], count = c.lvl_count[level];
     hipLaunchKernelGGL(k_fmin, dim3((count + 127) / 128), dim3(128), 0, s, first, count, c.c_begin.p,
-                       c.c_end.p, c.c_child0.p, c.c_nchild.p, c.fpart.p, c.fmin.p);
+                       c.c_end.p, c.c_child0.p, c.c_nchild.p, c.c_parent.p, c.fcell.p, c.fpart.p, c.fmin.p);
   }
   HIPCHK(hipGetLastError());
 }
