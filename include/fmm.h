@@ -40,7 +40,7 @@ typedef enum {
   FMM_EHIP = -3,         /* a HIP runtime call failed (message in fmm_last_error) */
   FMM_ENOTBUILT = -4,    /* export asked for data no call has produced yet        */
   FMM_EDATA = -5,        /* non-finite position or negative/non-finite mass       */
-  FMM_EUNSUPPORTED = -6  /* valid but not supported by this build                 */
+  FMM_EUNSUPPORTED = -6  /* valid but not supported by the compiled library      */
 } fmm_status;
 
 typedef enum {

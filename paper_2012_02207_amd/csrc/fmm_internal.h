@@ -137,6 +137,10 @@ struct Ctx {
   dbuf<double> pk;    // ncell x (p+1)
   dbuf<double> pkb;   // ncell x (p+1): C(p, k) * P_k, as the acceptance test forms it
   dbuf<double> fcell, fmin;
+  // chunks of <= CELL_CHUNK sorted bodies per cell (the radius and the cell
+  // minima of the estimate walk them): first chunk of each cell; the total
+  // stays on the device at counters[4..5]
+  dbuf<int> cell_choff;
   dbuf<double> loc;   // ncell x ncoef x 2
   dbuf<double> loc64; // mixed precision: FP64 M2L of the root-level pairs, added to loc
   dbuf<int> root_sinks;  // mixed precision: the sinks that have root-level pairs
@@ -224,6 +228,10 @@ void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass);
 void upward_pass(Ctx& c);
 void expansions_up(Ctx& c);
 void cell_moments(Ctx& c, bool with_radius);
+constexpr int CELL_CHUNK = 1024;  // bodies per chunk of a cell (radius, cell minima)
+// per-cell maximum (radius) or minimum (estimate) over the cells' bodies, a
+// wavefront per chunk; grid for every chunk the tree can have
+unsigned cell_chunk_blocks(const Ctx& c, int waves_per_block);
 void zero_fill(Ctx& c, void* p, size_t bytes);
 void refresh_frozen(Ctx& c, const double* pos, const double* mass);
 // the scalar-force estimate; beside (if any) is called once while the walk

@@ -207,10 +207,13 @@ __device__ __forceinline__ float mass32(const double4& v) {
   return __uint_as_float((unsigned)__double_as_longlong(v.w));
 }
 
+// Occupancy: 6 waves per SIMD for the FP32 pair loop (<= 80 VGPRs), 5 for the
+// FP64 one (measured best for each; the FP64 loop at 6 is slower), with the
+// sink leaf's data wave-uniform (SGPRs).
 constexpr int LG_WAVES = 4;
 
 template <bool MIXED>
-__global__ void __launch_bounds__(64 * LG_WAVES) k_leaf_group(const int* __restrict__ leaves,
+__global__ void __launch_bounds__(64 * LG_WAVES) __attribute__((amdgpu_waves_per_eu(MIXED ? 6 : 5))) k_leaf_group(const int* __restrict__ leaves,
                                                               int nleaves, const int* __restrict__ cb,
                                                               const int* __restrict__ ce,
                                                               const int* __restrict__ off,
@@ -220,7 +223,7 @@ __global__ void __launch_bounds__(64 * LG_WAVES) k_leaf_group(const int* __restr
                                                               unsigned long long* npairs) {
   __shared__ double4 sbuf[LG_WAVES][64];
   __shared__ double rbuf[LG_WAVES][4][64];
-  int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   int nblk = (nleaves + LG_WAVES - 1) / LG_WAVES;
   int per = (nblk + 7) >> 3;
   int blk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);

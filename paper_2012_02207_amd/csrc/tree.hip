@@ -499,30 +499,40 @@ __device__ inline int octant_lower_bound(const uint64_t* key, int b, int e, int 
   return lo;
 }
 
-// children of every cell of one level; cells that stay leaves are counted in
+// children of every cell of one level: eight lanes per cell, lane o finding
+// the first body of octant o by its own binary search (the searches run side
+// by side instead of one after another); cells that stay leaves are counted in
 // *nleaf (one atomic per wavefront)
 __global__ void k_split_level(int first, int count, int level, int n_leaf, const uint64_t* key,
                               const int* cb, const int* ce, int* split, int* nch, int* nleaf) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  bool ok = t < count;
+  int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int t = (int)(T >> 3), o = (int)(T & 7);
+  bool ok = t < count;  // the 8 lanes of a cell agree
   int cnt = 0;
+  bool splits = false;
+  int bound = 0, e = 0;
   if (ok) {
     int c = first + t;
-    int b = cb[c], e = ce[c];
-    if (e - b > n_leaf && level < FMM_MAX_LEVEL) {
+    int b = cb[c];
+    e = ce[c];
+    splits = e - b > n_leaf && level < FMM_MAX_LEVEL;
+    if (splits) {
       int shift = 3 * (FMM_MAX_LEVEL - (level + 1));
-      int prev = b;
-      split[9 * t] = b;
-      for (int o = 1; o <= 8; o++) {
-        int s = o < 8 ? octant_lower_bound(key, prev, e, o, shift) : e;
-        split[9 * t + o] = s;
-        if (s > prev) cnt++;
-        prev = s;
-      }
+      bound = o == 0 ? b : octant_lower_bound(key, b, e, o, shift);
     }
-    nch[t] = cnt;
   }
-  unsigned long long leaves = __ballot(ok && cnt == 0);
+  // octant o spans [bound_o, bound_{o+1}); bound_8 = e
+  int next = __shfl_down(bound, 1, 8);
+  if (o == 7) next = e;
+  int nonempty = splits && next > bound ? 1 : 0;
+  cnt = nonempty;
+  for (int m = 1; m < 8; m <<= 1) cnt += __shfl_xor(cnt, m, 8);
+  if (ok && splits) {
+    split[9 * t + o] = bound;
+    if (o == 7) split[9 * t + 8] = e;
+  }
+  if (ok && o == 0) nch[t] = cnt;
+  unsigned long long leaves = __ballot(ok && o == 0 && cnt == 0);
   if ((threadIdx.x & 63) == 0 && leaves) atomicAdd(nleaf, (int)__popcll(leaves));
 }
 
@@ -613,7 +623,7 @@ __global__ void k_mass_com(int first, int count, int level, const int* cb, const
 
 // radius: exact max over each cell's bodies of the squared distance to its
 // centre (order independent), in chunks of RAD_CH bodies
-constexpr int RAD_T = 256, RAD_CH = 1024;
+constexpr int RAD_T = 256, RAD_CH = CELL_CHUNK;
 
 __global__ void k_rad_chunks(const int* cb, const int* ce, int ncell, int* nchunk) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -671,6 +681,12 @@ __global__ void k_leaf_of(const int* cb, const int* ce, const int* nch, int ncel
 
 static inline dim3 grid1(int64_t n, int t = 256) { return dim3((unsigned)ceil_div(n, t)); }
 
+// every body is in one cell per level: at most (depth + 1) n / CELL_CHUNK + ncell chunks
+unsigned cell_chunk_blocks(const Ctx& c, int waves_per_block) {
+  int64_t max_chunks = (int64_t)(c.depth + 1) * ceil_div(c.n, CELL_CHUNK) + c.ncell;
+  return (unsigned)ceil_div(max_chunks, waves_per_block);
+}
+
 // mass, centre of mass and radius of every cell from the sorted bodies
 void cell_moments(Ctx& c, bool with_radius) {
   hipStream_t s = c.stream;
@@ -695,17 +711,17 @@ void cell_moments(Ctx& c, bool with_radius) {
   }
   if (!with_radius) return;
   // radii
-  ensure(c.ws, c.c_split, (size_t)2 * nc + 64);
+  ensure(c.ws, c.c_split, (size_t)nc + 64);
+  ensure(c.ws, c.cell_choff, (size_t)nc + 64);
   int* nchunk = c.c_split.p;
-  int* choff = nchunk + nc + 32;
+  int* choff = c.cell_choff.p;
+  long long* nchunks = (long long*)(c.counters.p + 4);
   hipLaunchKernelGGL(k_rad_chunks, grid1(nc), dim3(256), 0, s, c.c_begin.p, c.c_end.p, nc, nchunk);
-  exclusive_scan(c, nchunk, choff, nc, tot);
+  exclusive_scan(c, nchunk, choff, nc, nchunks);
   zero_fill(c, c.c_rad2bits.p, sizeof(unsigned long long) * nc);
-  // every body is in one cell per level: at most (depth + 1) n / RAD_CH + ncell chunks
-  int64_t max_chunks = (int64_t)(c.depth + 1) * ceil_div(c.n, RAD_CH) + nc;
-  unsigned grid = (unsigned)ceil_div(max_chunks, RAD_T / 64);
-  hipLaunchKernelGGL(k_radius, dim3(grid), dim3(RAD_T), 0, s, c.c_begin.p, c.c_end.p, choff, tot, nc, c.sx.p,
-                     c.sy.p, c.sz.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.c_rad2bits.p);
+  hipLaunchKernelGGL(k_radius, dim3(cell_chunk_blocks(c, RAD_T / 64)), dim3(RAD_T), 0, s, c.c_begin.p,
+                     c.c_end.p, choff, nchunks, nc, c.sx.p, c.sy.p, c.sz.p, c.c_cx.p, c.c_cy.p, c.c_cz.p,
+                     c.c_rad2bits.p);
   hipLaunchKernelGGL(k_radius_final, grid1(nc), dim3(256), 0, s, c.c_rad2bits.p, nc, c.c_rad.p);
 }
 
@@ -809,7 +825,7 @@ void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
   c.lvl_first.assign(1, 0);
   c.lvl_count.assign(1, nsys);
   int64_t total_cells = nsys;
-  ensure(c.ws, c.counters, 256);
+  ensure(c.ws, c.counters, 512);  // the full size at once: counters[4..5] must outlive this call
   long long* tot = (long long*)c.counters.p;
   int* nleaf_dev = c.counters.p + 2;  // read back with the level totals
   zero_fill(c, nleaf_dev, sizeof(int));
@@ -820,7 +836,7 @@ void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
     int* split = c.c_split.p;
     int* nch = split + (size_t)9 * count;
     int* choff = nch + count;
-    hipLaunchKernelGGL(k_split_level, grid1(count), dim3(256), 0, s, first, count, level,
+    hipLaunchKernelGGL(k_split_level, grid1((int64_t)count * 8), dim3(256), 0, s, first, count, level,
                        c.prm.n_leaf, c.key[0].p, c.c_begin.p, c.c_end.p, split, nch, nleaf_dev);
     HIPCHK(hipGetLastError());
     exclusive_scan(c, nch, choff, count, tot);

@@ -373,7 +373,7 @@ __global__ void k_fcell(int ncell, const int* off, const int* src, const double*
 }
 
 // near_i = sum_{j near, j != i} m_j / d^2, partners in ascending id, bodies in
-// sorted order, one running sum per body (k_fmin adds the far part).
+// sorted order, one running sum per body (k_fleaf adds the far part).
 // One wavefront per sink leaf, a lane per sink body; each source leaf is
 // staged in LDS (one coalesced load, the next one fetched while the current
 // one is summed) and read by all lanes as broadcasts.
@@ -441,38 +441,60 @@ __global__ void __launch_bounds__(64 * NF_WAVES) k_near_f(int nleaves, const int
   }
 }
 
-// minimum of f over each cell of one level (deepest level first).  A leaf
-// first completes its bodies' estimates, f_i = (F summed from the root down to
-// the leaf) + near_i, in that order (f holds near_i on entry).
-__global__ void k_fmin(int first, int count, const int* cb, const int* ce, const int* c0, const int* nch,
-                       const int* parent, const double* F, double* f, double* fmin) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= count) return;
-  int c = first + t;
-  double m;
-  if (nch[c] == 0) {
-    int path[FMM_MAX_LEVEL + 2];
-    int len = 0;
-    for (int q = c; q >= 0; q = parent[q]) path[len++] = q;
-    double far = 0.0;
-    for (int k = len - 1; k >= 0; k--) far = far + F[path[k]];
-    m = INFINITY;
-    for (int i = cb[c]; i < ce[c]; i++) {
-      double v = far + f[i];
-      f[i] = v;
-      if (v < m) m = v;
-    }
-  } else {
-    m = fmin[c0[c]];
-    for (int k = 1; k < nch[c]; k++)
-      if (fmin[c0[c] + k] < m) m = fmin[c0[c] + k];
+// f_i = (F summed from the root down to the leaf) + near_i, in that order, for
+// the bodies of every leaf (f holds near_i on entry); one thread per leaf
+__global__ void k_fleaf(int nleaves, const int* leaves, const int* cb, const int* ce, const int* parent,
+                        const double* F, double* f) {
+  int li = blockIdx.x * blockDim.x + threadIdx.x;
+  if (li >= nleaves) return;
+  int c = leaves[li];
+  int path[FMM_MAX_LEVEL + 2];
+  int len = 0;
+  for (int q = c; q >= 0; q = parent[q]) path[len++] = q;
+  double far = 0.0;
+  for (int k = len - 1; k >= 0; k--) far = far + F[path[k]];
+  for (int i = cb[c]; i < ce[c]; i++) f[i] = far + f[i];
+}
+
+// fmin_c = min of f over the cell's bodies (the same as the minimum over its
+// children), a wavefront per chunk of CELL_CHUNK bodies; f >= 0, so the bit
+// patterns order as the values and the chunks combine by an integer atomicMin
+// (fmin starts at +inf)
+constexpr int FM_T = 256;
+__global__ void __launch_bounds__(FM_T) k_cell_min(const int* cb, const int* ce, const int* choff,
+                                                   const long long* nchunks, int ncell, const double* f,
+                                                   unsigned long long* fmin_bits) {
+  int blk = blockIdx.x * (FM_T / 64) + (threadIdx.x >> 6);
+  int lane = threadIdx.x & 63;
+  if (blk >= (int)*nchunks) return;
+  int lo = 0, hi = ncell - 1;  // cell owning this chunk: last c with choff[c] <= blk
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (choff[mid] <= blk)
+      lo = mid;
+    else
+      hi = mid - 1;
   }
-  fmin[c] = m;
+  int c = lo;
+  int64_t b = cb[c] + (int64_t)(blk - choff[c]) * CELL_CHUNK;
+  int64_t e = b + CELL_CHUNK < ce[c] ? b + CELL_CHUNK : ce[c];
+  double m = INFINITY;
+  for (int64_t i = b + lane; i < e; i += 64) m = f[i] < m ? f[i] : m;
+  for (int o = 32; o > 0; o >>= 1) {
+    double other = __shfl_xor(m, o, 64);
+    m = other < m ? other : m;
+  }
+  if (lane == 0) atomicMin(&fmin_bits[c], (unsigned long long)__double_as_longlong(m));
+}
+
+__global__ void k_fill_inf(unsigned long long* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0x7ff0000000000000ull;
 }
 
 // The far sums F_B (list grouped on the second side stream, with the third
-// set of sort scratch) run beside the near sums on the caller's stream; the
-// join comes before the cell minima, which add the two.
+// set of sort scratch) run beside the near sums on the caller's stream; after
+// the join the leaves add the two, then the cell minima are taken.
 void estimate_walk(Ctx& c, const std::function<void()>& beside) {
   hipStream_t s = c.stream;
   int nc = (int)c.ncell;
@@ -496,11 +518,12 @@ void estimate_walk(Ctx& c, const std::function<void()>& beside) {
                        c.c_begin.p, c.c_end.p, c.est_near.off.p, c.est_near.src.p, c.pm.p, c.fpart.p);
   }
   stream_wait(c.fork[7], c.side2, s);
-  for (int level = c.depth; level >= 0; level--) {
-    int first = c.lvl_first[level], count = c.lvl_count[level];
-    hipLaunchKernelGGL(k_fmin, dim3((count + 127) / 128), dim3(128), 0, s, first, count, c.c_begin.p,
-                       c.c_end.p, c.c_child0.p, c.c_nchild.p, c.c_parent.p, c.fcell.p, c.fpart.p, c.fmin.p);
-  }
+  hipLaunchKernelGGL(k_fleaf, dim3((unsigned)ceil_div(c.nleaf, 128)), dim3(128), 0, s, (int)c.nleaf, c.leaves.p,
+                     c.c_begin.p, c.c_end.p, c.c_parent.p, c.fcell.p, c.fpart.p);
+  unsigned long long* fmin_bits = (unsigned long long*)c.fmin.p;
+  hipLaunchKernelGGL(k_fill_inf, dim3((nc + 255) / 256), dim3(256), 0, s, fmin_bits, nc);
+  hipLaunchKernelGGL(k_cell_min, dim3(cell_chunk_blocks(c, FM_T / 64)), dim3(FM_T), 0, s, c.c_begin.p, c.c_end.p,
+                     c.cell_choff.p, (const long long*)(c.counters.p + 4), nc, c.fpart.p, fmin_bits);
   HIPCHK(hipGetLastError());
 }
 

@@ -236,7 +236,9 @@ def test_errors_of_the_other_entry_points(fmm):
 MIXED_MEDIAN_BOUND = 1e-6
 
 
-@pytest.mark.parametrize("root_levels", [0, 3])
+# root_levels = 22 (deeper than any tree): every M2L pair takes the FP64 path over
+# the device-built list of sinks, none the FP32 kernel
+@pytest.mark.parametrize("root_levels", [0, 3, 22])
 def test_mixed_precision_bounded_difference(fmm, root_levels):
     cfg = W.CONFIGS["plummer_4k"]
     pos, _, mass = W.plummer(cfg["n"], cfg["seed"])
