@@ -742,7 +742,7 @@ void fmm_destroy(fmm_ctx* ctx) {
     rel(c.idx[k]);
     rel(c.front[k]);
   }
-  rel(c.sx); rel(c.sy); rel(c.sz); rel(c.sm); rel(c.pm); rel(c.pkb); rel(c.scale); rel(c.nmult); rel(c.fpart); rel(c.leaf_of); rel(c.leaves); rel(c.nearbuf); rel(c.loc64); rel(c.root_sinks); rel(c.madj); rel(c.ladj); rel(c.fwd_acc); rel(c.fwd_pot); rel(c.gsort); rel(c.asort); rel(c.sys_off); rel(c.skey[0]); rel(c.skey[1]); rel(c.spos[0]); rel(c.spos[1]); rel(c.sort_hist); rel(c.sort_hist2); rel(c.scan_tmp2); rel(c.sort_hist3); rel(c.scan_tmp3); rel(c.cell_choff);
+  rel(c.sx); rel(c.sy); rel(c.sz); rel(c.sm); rel(c.pm); rel(c.pkb); rel(c.scale); rel(c.nmult); rel(c.fpart); rel(c.leaf_of); rel(c.leaves); rel(c.nearbuf); rel(c.loc64); rel(c.root_sinks); rel(c.madj); rel(c.ladj); rel(c.fwd_acc); rel(c.fwd_pot); rel(c.gsort); rel(c.asort); rel(c.sys_off); rel(c.skey[0]); rel(c.skey[1]); rel(c.spos[0]); rel(c.spos[1]); rel(c.sort_hist); rel(c.sort_hist2); rel(c.scan_tmp2); rel(c.sort_hist3); rel(c.scan_tmp3); rel(c.cell_choff); rel(c.c_geo);
   rel(c.bbox_part); rel(c.rootbox); rel(c.c_level); rel(c.c_begin); rel(c.c_end); rel(c.c_parent);
   rel(c.c_child0); rel(c.c_nchild); rel(c.c_split); rel(c.c_mass); rel(c.c_sx); rel(c.c_sy);
   rel(c.c_sz); rel(c.c_cx); rel(c.c_cy); rel(c.c_cz); rel(c.c_rad); rel(c.c_rad2bits); rel(c.mult);

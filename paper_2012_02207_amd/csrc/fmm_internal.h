@@ -141,6 +141,7 @@ struct Ctx {
   // minima of the estimate walk them): first chunk of each cell; the total
   // stays on the device at counters[4..5]
   dbuf<int> cell_choff;
+  dbuf<double4> c_geo;  // (cx, cy, cz, rad) per cell, packed for the walks
   dbuf<double> loc;   // ncell x ncoef x 2
   dbuf<double> loc64; // mixed precision: FP64 M2L of the root-level pairs, added to loc
   dbuf<int> root_sinks;  // mixed precision: the sinks that have root-level pairs

@@ -667,10 +667,15 @@ __global__ void __launch_bounds__(RAD_T) k_radius(const int* cb, const int* ce, 
   if (lane == 0) atomicMax(&r2bits[c], (unsigned long long)__double_as_longlong(best));
 }
 
-__global__ void k_radius_final(const unsigned long long* r2bits, int ncell, double* rad) {
+// radius from the squared maximum; also the packed (centre, radius) record
+// the walks read
+__global__ void k_radius_final(const unsigned long long* r2bits, int ncell, const double* cx, const double* cy,
+                               const double* cz, double* rad, double4* geo) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncell) return;
-  rad[c] = sqrt(__longlong_as_double((long long)r2bits[c]));
+  double r = sqrt(__longlong_as_double((long long)r2bits[c]));
+  rad[c] = r;
+  geo[c] = make_double4(cx[c], cy[c], cz[c], r);
 }
 
 __global__ void k_leaf_of(const int* cb, const int* ce, const int* nch, int ncell, int* leaf_of) {
@@ -722,7 +727,9 @@ void cell_moments(Ctx& c, bool with_radius) {
   hipLaunchKernelGGL(k_radius, dim3(cell_chunk_blocks(c, RAD_T / 64)), dim3(RAD_T), 0, s, c.c_begin.p,
                      c.c_end.p, choff, nchunks, nc, c.sx.p, c.sy.p, c.sz.p, c.c_cx.p, c.c_cy.p, c.c_cz.p,
                      c.c_rad2bits.p);
-  hipLaunchKernelGGL(k_radius_final, grid1(nc), dim3(256), 0, s, c.c_rad2bits.p, nc, c.c_rad.p);
+  ensure(c.ws, c.c_geo, (size_t)nc);
+  hipLaunchKernelGGL(k_radius_final, grid1(nc), dim3(256), 0, s, c.c_rad2bits.p, nc, c.c_cx.p, c.c_cy.p,
+                     c.c_cz.p, c.c_rad.p, c.c_geo.p);
 }
 
 // Positions and masses changed, tree topology, order and lists kept: the

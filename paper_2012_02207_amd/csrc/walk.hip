@@ -28,16 +28,17 @@ namespace fmm {
 
 struct CellView {
   const int *nch, *c0;
-  const double *rad, *cx, *cy, *cz, *mass, *pkb, *fmin;
+  const double4* geo;  // (centre x, y, z, radius) per cell, one 32-byte record
+  const double *mass, *pkb, *fmin;
   int p;
   double theta, err_tol;
   int geometric;
 };
 
-__device__ __forceinline__ double com_r2(const CellView& v, int a, int b) {
-  double dx = v.cx[b] - v.cx[a];
-  double dy = v.cy[b] - v.cy[a];
-  double dz = v.cz[b] - v.cz[a];
+__device__ __forceinline__ double com_r2(const double4& a, const double4& b) {
+  double dx = b.x - a.x;
+  double dy = b.y - a.y;
+  double dz = b.z - a.z;
   return (dx * dx + dy * dy) + dz * dz;
 }
 
@@ -45,8 +46,7 @@ __device__ __forceinline__ double com_r2(const CellView& v, int a, int b) {
 // lists (k ascending), each term (C(p,k) P_{k,A}) r_B^{p-k}, with C(p,k) P_{k,A}
 // formed once per cell by the upward pass
 template <int P>
-__device__ double mac_lhs(const CellView& v, int A, int B, double r, double r2) {
-  double rA = v.rad[A], rB = v.rad[B];
+__device__ double mac_lhs(const CellView& v, int A, double rA, double rB, double r, double r2) {
   double rp = r;
 #pragma unroll
   for (int i = 2; i <= P; i++) rp = rp * r;
@@ -68,18 +68,18 @@ __device__ double mac_lhs(const CellView& v, int A, int B, double r, double r2) 
 }
 
 template <int KIND, int P>
-__device__ bool accept(const CellView& v, int A, int B) {
-  double r2 = com_r2(v, A, B);
+__device__ bool accept(const CellView& v, int A, int B, const double4& gA, const double4& gB) {
+  double r2 = com_r2(gA, gB);
   double r = sqrt(r2);
-  double rA = v.rad[A], rB = v.rad[B];
+  double rA = gA.w, rB = gB.w;
   if constexpr (KIND == 0) {
     return (rA + rB) < v.theta * r;
   } else {
     if (!((rA + rB) < v.theta * r)) return false;
     if (v.geometric) return true;
     if (rA + rB == 0.0) return true;
-    double lab = mac_lhs<P>(v, A, B, r, r2);
-    double lba = mac_lhs<P>(v, B, A, r, r2);
+    double lab = mac_lhs<P>(v, A, rA, rB, r, r2);
+    double lba = mac_lhs<P>(v, B, rB, rA, r, r2);
     return (lab < v.err_tol * v.fmin[B]) && (lba < v.err_tol * v.fmin[A]);
   }
 }
@@ -156,14 +156,17 @@ __global__ void __launch_bounds__(WALK_T) k_walk(CellView v, int step, const int
           mode = 1;
           nkids = kA * (kA + 1) / 2;
         }
-      } else if (accept<KIND, P>(v, A, B)) {
-        nacc = 2;
-      } else if (kA == 0 && kB == 0) {
-        nnear = 2;
       } else {
-        bool splitB = (kA == 0) || (v.rad[B] > v.rad[A] && kB != 0);
-        mode = splitB ? 3 : 2;
-        nkids = splitB ? kB : kA;
+        double4 gA = v.geo[A], gB = v.geo[B];
+        if (accept<KIND, P>(v, A, B, gA, gB)) {
+          nacc = 2;
+        } else if (kA == 0 && kB == 0) {
+          nnear = 2;
+        } else {
+          bool splitB = (kA == 0) || (gB.w > gA.w && kB != 0);
+          mode = splitB ? 3 : 2;
+          nkids = splitB ? kB : kA;
+        }
       }
     }
     int ek, ea, en;
@@ -286,10 +289,7 @@ static void run_walk(Ctx& c, CellList& acc, CellList& nearl, bool group,
   CellView v{};
   v.nch = c.c_nchild.p;
   v.c0 = c.c_child0.p;
-  v.rad = c.c_rad.p;
-  v.cx = c.c_cx.p;
-  v.cy = c.c_cy.p;
-  v.cz = c.c_cz.p;
+  v.geo = c.c_geo.p;
   v.mass = c.c_mass.p;
   v.pkb = c.pkb.p;
   v.fmin = c.fmin.p;
