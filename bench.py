@@ -58,11 +58,11 @@ P2P_FLOPS = 20   # per directed body pair: acc + pot, softened, rsqrt counted on
 # (fetch x2.0, write x1.0).  Keyed by (kernel, workload, precision); valid only
 # while the kernel's source file has the recorded SHA-1 (else reported as null).
 MEASURED_TRAFFIC = {
-    ("k_m2l_fp32", "plummer_1m", "mixed"): (533.5e6, "paper_2012_02207_amd/csrc/m2l_mixed.hip",
+    ("k_m2l_fp32", "plummer_1m", "mixed"): (534.4e6, "paper_2012_02207_amd/csrc/m2l_mixed.hip",
                                              "6294f0e874e137e68672e07330b08135c48962e8"),
-    ("k_leaf_group<true> (mixed P2P)", "plummer_1m", "mixed"): (177.4e6,
+    ("k_leaf_group<true> (mixed P2P)", "plummer_1m", "mixed"): (194.3e6,
                                                                 "paper_2012_02207_amd/csrc/local.hip",
-                                                                "abe2e1e5227e5b242eecacc4a4cd4a7d3defb90b"),
+                                                                "0703b22073d36a2476cbee895870d67241e8d2dc"),
 }
 
 
