@@ -119,7 +119,10 @@ void evaluate(Ctx& c, double* acc, double* pot, bool group) {
     launch_m2l_mixed_root(c, c.loc64.p);
   }
   if (c.have_events) HIPCHK(hipEventRecord(c.ev[4], s));
-  zero_fill(c, c.loc.p, nl * sizeof(double));
+  // the M2L kernels write every sink they cover (zeros where there is no
+  // pair); in mixed precision the root-level cells are not covered by the FP32
+  // kernel and start at zero here
+  if (mixed) zero_fill(c, c.loc.p, (size_t)mixed_first_lo(c) * ncoef(c.p) * 2 * sizeof(double));
   if (mixed)
     launch_m2l_mixed_lo(c);
   else

@@ -162,7 +162,10 @@ __device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, con
     }
     e = lo;
   }
-  if (b == e) return;
+  if (b == e) {  // no pair: the sink's expansion starts at zero (never a listed sink)
+    for (int k = lane; k < NC * 2; k += 64) loc[(size_t)B * NC * 2 + k] = 0.0;
+    return;
+  }
   // per-order sums, one LDS slot per lane: acc[64 n]
 #pragma unroll
   for (int t = 0; t <= P; t++) acc[64 * t] = 0.0;

@@ -178,8 +178,11 @@ __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per
   if (blk >= nblk || B >= ncell) return;
   int e = off[B + 1];
   int b = split_point(src, off[B], e, first_lo);
-  if (b == e) return;
   int lane = threadIdx.x & 63;
+  if (b == e) {  // no FP32 pair: the sink's expansion starts at zero
+    for (int k = lane; k < NC * 2; k += 64) loc[(size_t)B * NC * 2 + k] = 0.0;
+    return;
+  }
   __shared__ double accs[MX_WAVES][P + 1][64];
   double* acc = &accs[wv][0][0] + lane;
 #pragma unroll
@@ -308,8 +311,8 @@ __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per
       reduce_lanes<2 * n + 1>(w, &acc[64 * n], lane);
     });
   }
-  // back to standard coefficients: L_n^0 += Lt n! / rho_B^n,
-  // L_n^m += Lt sqrt((n-m)!(n+m)!/2) / rho_B^n; real-basis entry j of order n
+  // back to standard coefficients: L_n^0 = Lt n! / rho_B^n,
+  // L_n^m = Lt sqrt((n-m)!(n+m)!/2) / rho_B^n; real-basis entry j of order n
   // is held by lane reduce_owner(2n+1, j) (the cross-lane sum in fmm_device.h)
   double* out = loc + (size_t)B * NC * 2;
   double isB = 1.0 / sB, pw = 1.0;
@@ -321,7 +324,8 @@ __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per
       int m = (j + 1) >> 1;
       bool im = j > 0 && !(j & 1);
       double f = (m == 0 ? 1.0 : sqrt(0.5)) * sqrt(fmm_fact_dev(n - m) * fmm_fact_dev(n + m)) * pw;
-      out[2 * cidx(n, m) + (im ? 1 : 0)] += acc[64 * n] * f;
+      out[2 * cidx(n, m) + (im ? 1 : 0)] = acc[64 * n] * f;
+      if (j == 0) out[2 * cidx(n, 0) + 1] = 0.0;
     }
     pw *= isB;
   });
