@@ -81,6 +81,12 @@ typedef struct {
   int64_t n_est_far;      /* directed accepted pairs of the estimate walk */
   int64_t n_est_near;     /* directed leaf pairs of the estimate walk     */
   int64_t n_m2l_fp32;     /* M2L pairs evaluated in FP32 (mixed mode)     */
+  /* stage times: tree (keys, sort, cells, radii, leaf list); upward (P2M, M2M,
+   * P_k, on a side stream beside the estimate); estimate (its walk, list
+   * grouping, far and near sums, cell minima); walk (acceptance walk and the
+   * grouping of the M2L list); m2l (from there to the join: the M2L kernels
+   * beside the near field); local (root-level add, L2L, final L2P and sum);
+   * p2p (the near-field kernel on its side stream); total (the whole call) */
   double ms_tree, ms_upward, ms_estimate, ms_walk, ms_m2l, ms_local, ms_p2p, ms_total;
   size_t workspace_bytes; /* device memory held by the context            */
   int64_t nsys;           /* independent systems of the call (1 for fmm_forces) */
