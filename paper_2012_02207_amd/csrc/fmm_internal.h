@@ -155,7 +155,12 @@ struct Ctx {
 
   // walks
   dbuf<int2> front[2];
-  dbuf<int> counters;  // device counters
+  // device counters (ints), by offset: [0..1] scan total (long long) of the
+  // tree's level loop; [2] leaves counted by the level loop; [4..5] number of
+  // body chunks of the cells (long long, read by the radius and cell-minimum
+  // kernels); [32] input check; [40..41] near-field body pairs; [48..49]
+  // FP32 M2L pairs (stats); [64] sinks with root-level pairs; [256..] walk
+  dbuf<int> counters;
   CellList est_far, est_near, m2l, p2p;
   int64_t n_p2p_pairs = 0;
 
