@@ -332,12 +332,13 @@ __device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, con
 
 // All sinks (one wavefront each, in XCD-contiguous ranges: neighbouring sinks
 // share sources), or, with LIST, the sinks[0 .. *nsinks) in a grid-stride loop.
-// Two waves per SIMD (256 registers each, a few spilled): measured faster than
-// one wave with everything in registers.  The per-order sums live in LDS and
-// the sink index is wave-uniform (its data in SGPRs), which keeps the spills
-// small.
+// Up to p = 10, two waves per SIMD (256 registers each, a few spilled at p =
+// 10): measured faster than one wave with everything in registers.  Higher
+// orders would spill heavily at that budget and take one wave.  The per-order
+// sums live in LDS and the sink index is wave-uniform (its data in SGPRs),
+// which keeps the spills small.
 template <int P, bool LIST>
-__global__ void __launch_bounds__(64 * M2L_WAVES) __attribute__((amdgpu_waves_per_eu(2))) k_m2l_fp64(int ncell, int first_lo, const int* __restrict__ sinks,
+__global__ void __launch_bounds__(64 * M2L_WAVES) __attribute__((amdgpu_waves_per_eu(P <= 10 ? 2 : 1))) k_m2l_fp64(int ncell, int first_lo, const int* __restrict__ sinks,
                                                              const int* __restrict__ nsinks,
                                                              const int* __restrict__ off,
                                                              const int* __restrict__ src,

@@ -149,11 +149,13 @@ __device__ __forceinline__ int split_point(const int* src, int b, int e, int fir
   return lo;
 }
 
-// One wavefront per sink, a source per lane.  Three waves per SIMD (at most
-// 168 VGPRs); the FP64 per-order sums live in LDS (a slot per lane), not in
-// registers, which would spill at that budget.
+// One wavefront per sink, a source per lane.  Up to p = 10, three waves per
+// SIMD (at most 168 VGPRs); higher orders need more registers and take two
+// (p = 11, 12) or one.
+// The FP64 per-order sums live in LDS (a slot per lane), not in registers,
+// which would spill at that budget.
 template <int P>
-__global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per_eu(3))) k_m2l_fp32(int ncell, int first_lo,
+__global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per_eu(P <= 10 ? 3 : P <= 12 ? 2 : 1))) k_m2l_fp32(int ncell, int first_lo,
                                                             const int* __restrict__ off,
                                                             const int* __restrict__ src,
                                                             const double* __restrict__ cx,
