@@ -58,9 +58,9 @@ P2P_FLOPS = 20   # per directed body pair: acc + pot, softened, rsqrt counted on
 # (fetch x2.0, write x1.0).  Keyed by (kernel, workload, precision); valid only
 # while the kernel's source file has the recorded SHA-1 (else reported as null).
 MEASURED_TRAFFIC = {
-    ("k_m2l_fp32", "plummer_1m", "mixed"): (460.0e6, "paper_2012_02207_amd/csrc/m2l_mixed.hip",
-                                             "8234034ec15e6abbfbb19446ddf3cead09ef734d"),
-    ("k_leaf_group<true> (mixed P2P)", "plummer_1m", "mixed"): (194.9e6,
+    ("k_m2l_fp32", "plummer_1m", "mixed"): (460.7e6, "paper_2012_02207_amd/csrc/m2l_mixed.hip",
+                                             "604ece7d31e031f2f39453a8a5b50b736ca45910"),
+    ("k_leaf_group<true> (mixed P2P)", "plummer_1m", "mixed"): (194.7e6,
                                                                 "paper_2012_02207_amd/csrc/local.hip",
                                                                 "0703b22073d36a2476cbee895870d67241e8d2dc"),
 }
