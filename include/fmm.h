@@ -135,14 +135,22 @@ fmm_status fmm_create(fmm_ctx** out, const fmm_params* prm);
 fmm_status fmm_set_params(fmm_ctx* ctx, const fmm_params* prm);
 
 /* Tree and upward pass only (keys, sort, cells, P2M, M2M, P_k): planning and
- * parity export.  pos/mass: device, n >= 1. */
+ * parity export.  Section 2.1 (octree, P2M at the leaves, M2M to the root),
+ * section 2.2 (moment equation) and section 2.3 (the per-order norms P_n and
+ * the cell sizes the acceptance test uses).  pos/mass: device, n >= 1.
+ * FMM_EUNSUPPORTED if the context's p has no compiled kernel. */
 fmm_status fmm_build(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass,
                      void* stream /* hipStream_t, NULL = default stream */);
 
-/* One full force evaluation: rebuilds the tree from pos, then estimate, walk,
- * M2L, L2L, L2P and P2P.  p and err_tol override the context's parameters for
- * this call.  acc (n x 3) and pot (n) are device buffers in the caller's body
- * order and are overwritten.  n == 1 gives acc = 0, pot = 0. */
+/* One full force evaluation: the flow of section 2.1 (tree, P2M, M2M, dual-tree
+ * walk, M2L, L2L, L2P and the direct near field), the scalar-force estimate and
+ * the error-controlled acceptance test of section 2.3, and the rotated M2L of
+ * section 2.4.  Rebuilds the tree from pos.  p (1..30) and err_tol (> 0)
+ * override the context's parameters for this call; eps_soft >= 0 softens the
+ * near field.  acc (n x 3) and pot (n) are device buffers in the caller's body
+ * order and are overwritten.  n == 1 gives acc = 0, pot = 0.  FMM_EINVAL for
+ * bad arguments (before any launch); FMM_EUNSUPPORTED for an order without a
+ * compiled kernel or for lists too long for the int32 CSR arrays. */
 fmm_status fmm_forces(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass,
                       double eps_soft, int p, double err_tol, double* acc, double* pot,
                       void* stream);
@@ -232,11 +240,17 @@ fmm_status fmm_autotune(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets, cons
                         const double* mass, double eps_soft, int p, double err_tol, double* acc,
                         double* pot, void* stream, int* chosen_n_leaf);
 
-/* Counts and per-stage times of the last call (synchronises its stream). */
+/* Counts and per-stage times of the last call (synchronises its stream): the
+ * cell and interaction-list sizes of the walk (section 2.1) and the interaction
+ * counts behind the force-error/cost trade-off of section 4.1.  out: host.
+ * FMM_EINVAL for NULL arguments. */
 fmm_status fmm_stats(fmm_ctx* ctx, fmm_stats_t* out /* host */);
 
-/* Copies an array of the last call into host memory (synchronises).  bytes
- * must be at least the size listed beside the selector. */
+/* Copies an array of the last call into host memory (synchronises): the tree
+ * and cells of section 2.1, the moments of section 2.2, the norms P_k, scalar
+ * forces and interaction lists of section 2.3, the local expansions.  bytes
+ * must be at least the size listed beside the selector (FMM_EINVAL otherwise);
+ * FMM_ENOTBUILT if no call has produced the array yet. */
 fmm_status fmm_export(fmm_ctx* ctx, int what, void* host_buf, size_t bytes);
 
 /* Caps the context's device workspace (0 = no cap); exceeding it -> FMM_ENOMEM. */

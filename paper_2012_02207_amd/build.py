@@ -14,8 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfmm_hip.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "tree.hip", "upward.hip", "walk.hip", "m2l.hip", "m2l_mixed.hip", "local.hip",
-           "adjoint.hip"]
+SOURCES = ["api.hip", "tree.hip", "upward.hip", "walk.hip", "m2l.hip", "m2l_hi.hip", "m2l_mixed.hip",
+           "local.hip", "adjoint.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -82,6 +82,7 @@ __global__ void k_jerk_gather(int64_t n, const int* perm, const double* vel, con
 // M_n^m = sum_i q_i Y_n^m + d_z Y_{n-1}^m + (d_x - i d_y)/2 Y_{n-1}^{m+1}
 //                         - (d_x + i d_y)/2 Y_{n-1}^{m-1}     (at x_i - z)
 constexpr int PA_T = 64, PA_LDS = 2048;  // doubles of harmonics per batch
+constexpr int PA_PMAX = 30;                // highest order (swap tables exist up to 30)
 
 __global__ void __launch_bounds__(PA_T) k_p2m_adj(int p, const int* leaves, int nleaves, const int* cb,
                                                   const int* ce, const double4* pm, const double4* gs,
@@ -99,7 +100,7 @@ __global__ void __launch_bounds__(PA_T) k_p2m_adj(int p, const int* leaves, int 
   int t = threadIdx.x;
   double x0 = cx[c], y0 = cy[c], z0 = cz[c];
   int b = cb[c], e = ce[c];
-  constexpr int MAXK = (ncoef(FMM_GPU_PMAX) + PA_T - 1) / PA_T;
+  constexpr int MAXK = (ncoef(PA_PMAX) + PA_T - 1) / PA_T;
   double acr[MAXK], aci[MAXK];
   for (int u = 0; u < MAXK; u++) acr[u] = aci[u] = 0.0;
   for (int i0 = b; i0 < e; i0 += batch) {

@@ -166,6 +166,9 @@ static fmm_status guarded(fmm_ctx* ctx, F&& f) {
   } catch (const oom_error&) {
     if (ctx) ctx->c.err = "device workspace allocation failed or exceeded the cap";
     return FMM_ENOMEM;
+  } catch (const unsupported_error& e) {
+    if (ctx) ctx->c.err = e.what;
+    return FMM_EUNSUPPORTED;
   } catch (const std::bad_alloc&) {
     if (ctx) ctx->c.err = "host allocation failed";
     return FMM_ENOMEM;
@@ -199,13 +202,20 @@ fmm_status fmm_create(fmm_ctx** out, const fmm_params* prm) {
   if (!ctx) return FMM_ENOMEM;
   ctx->c.prm = p;
   st = guarded(ctx, [&]() {
-    HIPCHK(hipGetDevice(&ctx->c.device));
-    HIPCHK(hipHostMalloc((void**)&ctx->c.hbuf, 128 * sizeof(long long), hipHostMallocDefault));
-    for (auto& e : ctx->c.ev) HIPCHK(hipEventCreate(&e));
-    for (auto& e : ctx->c.fork) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    HIPCHK(hipStreamCreateWithFlags(&ctx->c.side, hipStreamNonBlocking));
-    HIPCHK(hipStreamCreateWithFlags(&ctx->c.side2, hipStreamNonBlocking));
-    HIPCHK(hipStreamCreateWithFlags(&ctx->c.cap, hipStreamNonBlocking));
+    for (Ctx* c : {&ctx->c}) {
+      HIPCHK(hipGetDevice(&c->device));
+      HIPCHK(hipHostMalloc((void**)&c->hbuf, 128 * sizeof(long long), hipHostMallocDefault));
+      for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+      for (auto& e : c->fork) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+      HIPCHK(hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking));
+      HIPCHK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    }
+    // the kernels' constant tables, once per device
+    upload_up_tables();
+    upload_m2l_tables();
+    upload_mx_tables();
+    upload_hi_tables();
     return FMM_OK;
   });
   if (st != FMM_OK) {
@@ -221,6 +231,7 @@ fmm_status fmm_set_params(fmm_ctx* ctx, const fmm_params* prm) {
   fmm_status st = validate_params(prm);
   if (st != FMM_OK) return st;
   ctx->c.prm = *prm;
+  ctx->c.graph_valid = false;  // a captured graph holds the old precision and root split
   return FMM_OK;
 }
 
@@ -267,7 +278,6 @@ fmm_status fmm_build(fmm_ctx* ctx, int64_t n, const double* pos, const double* m
   fmm_status st = common_checks(ctx, n, pos, mass);
   if (st != FMM_OK) return st;
   Ctx& c = ctx->c;
-  if (c.prm.p > FMM_GPU_PMAX) return FMM_EUNSUPPORTED;
   return guarded(ctx, [&]() {
     c.stream = (hipStream_t)stream;
     c.err.clear();
@@ -283,18 +293,17 @@ fmm_status fmm_build(fmm_ctx* ctx, int64_t n, const double* pos, const double* m
   });
 }
 
-static fmm_status forces_impl(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets, int64_t n,
-                              const double* pos, const double* mass, double eps_soft, int p,
-                              double err_tol, double* acc, double* pot, void* stream) {
+// one evaluation on the context state c (the caller's, or the allocation-free
+// one); errors are reported through ctx
+static fmm_status forces_on(fmm_ctx* ctx, Ctx& c, int64_t nsys, const int64_t* offsets, int64_t n,
+                            const double* pos, const double* mass, double eps_soft, int p,
+                            double err_tol, double* acc, double* pot, void* stream) {
   fmm_status st = common_checks(ctx, n, pos, mass);
   if (st != FMM_OK) return st;
   if (!acc || !pot) return FMM_EINVAL;
   if (!(eps_soft >= 0) || !std::isfinite(eps_soft)) return FMM_EINVAL;
   if (p < 1 || p > 30) return FMM_EINVAL;
   if (!(err_tol > 0) || !std::isfinite(err_tol)) return FMM_EINVAL;
-  Ctx& c = ctx->c;
-  if (c.prm.precision != FMM_DIRECT && p > FMM_GPU_PMAX) return FMM_EUNSUPPORTED;
-  if (c.prm.precision == FMM_MIXED && !mixed_supported(p)) return FMM_EUNSUPPORTED;
   return guarded(ctx, [&]() {
     c.stream = (hipStream_t)stream;
     c.err.clear();
@@ -323,6 +332,13 @@ static fmm_status forces_impl(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets
     HIPCHK(hipEventRecord(c.ev[8], c.stream));
     return FMM_OK;
   });
+}
+
+static fmm_status forces_impl(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets, int64_t n,
+                              const double* pos, const double* mass, double eps_soft, int p,
+                              double err_tol, double* acc, double* pot, void* stream) {
+  if (!ctx) return FMM_EINVAL;
+  return forces_on(ctx, ctx->c, nsys, offsets, n, pos, mass, eps_soft, p, err_tol, acc, pot, stream);
 }
 
 fmm_status fmm_forces(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass, double eps_soft,
@@ -580,7 +596,7 @@ fmm_status fmm_adjoint(fmm_ctx* ctx, int64_t n, const double* pos, const double*
                        double* gmass, void* stream) {
   if (!ctx || !gacc || !gpos || !gmass) return FMM_EINVAL;
   Ctx& c = ctx->c;
-  if (p < 1 || p > FMM_GPU_PMAX) return p < 1 || p > 30 ? FMM_EINVAL : FMM_EUNSUPPORTED;
+  if (p < 1 || p > 30) return FMM_EINVAL;
   fmm_params saved = c.prm;
   c.prm.precision = FMM_FP64;  // the gradient is formed in FP64
   fmm_status st = guarded(ctx, [&]() {
@@ -606,7 +622,7 @@ fmm_status fmm_jerk(fmm_ctx* ctx, int64_t n, const double* pos, const double* ve
                     void* stream) {
   if (!ctx || !vel || !jerk) return FMM_EINVAL;
   Ctx& c = ctx->c;
-  if (p < 1 || p > FMM_GPU_PMAX) return p < 1 || p > 30 ? FMM_EINVAL : FMM_EUNSUPPORTED;
+  if (p < 1 || p > 30) return FMM_EINVAL;
   fmm_params saved = c.prm;
   c.prm.precision = FMM_FP64;
   int64_t off[2] = {0, n};

@@ -17,9 +17,10 @@
 #include <vector>
 
 #include "../../include/fmm.h"
+#include "fmm_limits.h"
 
 #define FMM_MAX_LEVEL 21
-#define FMM_GPU_PMAX 16  // orders with a compiled M2L kernel
+#define FMM_GPU_PMAX 16  // orders with a register-resident (unrolled) M2L kernel; higher: m2l_hi.hip
 
 namespace fmm {
 
@@ -53,6 +54,10 @@ struct Workspace {
 };
 
 struct oom_error {};
+// a valid request beyond what the data structures can index (FMM_EUNSUPPORTED)
+struct unsupported_error {
+  const char* what;
+};
 
 template <class T>
 void ensure(Workspace& w, dbuf<T>& b, size_t n, bool keep = false, hipStream_t s = nullptr) {
@@ -160,6 +165,7 @@ struct Ctx {
   // body chunks of the cells (long long, read by the radius and cell-minimum
   // kernels); [32] input check; [40..41] near-field body pairs; [48..49]
   // FP32 M2L pairs (stats); [64] sinks with root-level pairs; [256..] walk
+  // (64-bit counters at even int offsets)
   dbuf<int> counters;
   CellList est_far, est_near, m2l, p2p;
   int64_t n_p2p_pairs = 0;
@@ -253,6 +259,13 @@ bool check_inputs_dev(Ctx& c, const double* pos, const double* mass, int64_t n);
 
 // M2L launchers (one per compiled order)
 void launch_m2l_fp64(Ctx& c);
+// constant tables of the kernels, uploaded once per device at context creation
+void upload_up_tables();
+void upload_m2l_tables();
+void upload_mx_tables();
+void upload_hi_tables();
+// generic-order FP64 M2L (any p <= 30; m2l_hi.hip), over every sink or the listed ones
+void launch_m2l_hi(Ctx& c, int first_lo, const double* mult, double* loc, const int* sinks, const int* nsinks);
 void launch_m2l_fp64_range(Ctx& c, int first_lo);
 void launch_m2l_fp64_buffers(Ctx& c, int first_lo, const double* mult, double* loc);
 void launch_m2l_fp64_sinks(Ctx& c, int first_lo, const double* mult, double* loc, const int* sinks,

@@ -17,16 +17,18 @@ namespace fmm {
 // coefficient) sums.
 constexpr int L2L_T = 256;
 
+// G: children per pass (their harmonics share LDS with the parent's expansion;
+// 8 = all at once, fewer at the orders where eight do not fit)
 __global__ void __launch_bounds__(L2L_T) k_l2l(int p, int first, int count, const int* c0,
                                               const int* nch, const double* cx, const double* cy,
-                                              const double* cz, double* loc) {
+                                              const double* cz, double* loc, int G) {
   extern __shared__ double lds[];
   int P = first + blockIdx.x;
   if (blockIdx.x >= count || nch[P] == 0) return;
   int nc = ncoef(p), S = (p + 1) * (p + 1);
   int k0 = c0[P], kn = nch[P];
   double2* Lx = (double2*)lds;  // [S]
-  double2* Yc = Lx + S;         // [child][S]
+  double2* Yc = Lx + S;         // [child of the pass][S]
   int t = threadIdx.x;
   const double* Lp = loc + (size_t)P * nc * 2;
   for (int u = t; u < S; u += L2L_T) {
@@ -41,57 +43,61 @@ __global__ void __launch_bounds__(L2L_T) k_l2l(int p, int first, int count, cons
     }
     Lx[u] = make_double2(a, b);
   }
-  for (int u = t; u < kn * (p + 1); u += L2L_T) {  // column m of child j's harmonics
-    int j = u / (p + 1), m = u - j * (p + 1);
-    int ch = k0 + j;
-    double x = cx[ch] - cx[P], y = cy[ch] - cy[P], z = cz[ch] - cz[P];
-    double r2 = fma(x, x, fma(y, y, z * z));
-    double pr = 1.0, pi = 0.0;
-    for (int n = 1; n <= m; n++) {
-      double inv = -1.0 / (double)(2 * n);
-      double tr = fma(x, pr, -y * pi), ti = fma(x, pi, y * pr);
-      pr = tr * inv;
-      pi = ti * inv;
-    }
-    double2* Y = Yc + j * S;
-    double sg = (m & 1) ? -1.0 : 1.0;
-    // conj(Y_n^m) at +m; conj(Y_n^-m) = (-1)^m Y_n^m at -m
-    Y[m * m + m + m] = make_double2(pr, -pi);
-    if (m > 0) Y[m * m] = make_double2(sg * pr, sg * pi);
-    double ar2 = 0.0, ai2 = 0.0, ar1 = pr, ai1 = pi;
-    for (int n = m + 1; n <= p; n++) {
-      double k = (double)(2 * n - 1) * z, inv = 1.0 / (double)((n + m) * (n - m));
-      double vr = fma(k, ar1, -r2 * ar2) * inv, vi = fma(k, ai1, -r2 * ai2) * inv;
-      Y[n * n + n + m] = make_double2(vr, -vi);
-      if (m > 0) Y[n * n + n - m] = make_double2(sg * vr, sg * vi);
-      ar2 = ar1;
-      ai2 = ai1;
-      ar1 = vr;
-      ai1 = vi;
-    }
-  }
-  __syncthreads();
-  for (int u = t; u < kn * nc; u += L2L_T) {
-    int j = u / nc, q = u - j * nc;
-    int jn = 0;
-    while (cidx(jn + 1, 0) <= q) jn++;
-    int i = q - cidx(jn, 0);
-    const double2* Y = Yc + j * S;
-    double sr = 0.0, si = 0.0;
-    for (int k = 0; k <= p - jn; k++) {
-      int n = jn + k;
-      const double2* Ln = Lx + n * n + n + i - k;
-      const double2* Yk = Y + k * k;
-#pragma unroll 4
-      for (int r = 0; r <= 2 * k; r++) {  // l = r - k
-        double2 a = Ln[r], b = Yk[r];
-        sr = fma(a.x, b.x, fma(-a.y, b.y, sr));
-        si = fma(a.x, b.y, fma(a.y, b.x, si));
+  for (int j0 = 0; j0 < kn; j0 += G) {
+    int gn = min(G, kn - j0);
+    if (j0 > 0) __syncthreads();  // the previous pass has read its harmonics
+    for (int u = t; u < gn * (p + 1); u += L2L_T) {  // column m of child j's harmonics
+      int j = u / (p + 1), m = u - j * (p + 1);
+      int ch = k0 + j0 + j;
+      double x = cx[ch] - cx[P], y = cy[ch] - cy[P], z = cz[ch] - cz[P];
+      double r2 = fma(x, x, fma(y, y, z * z));
+      double pr = 1.0, pi = 0.0;
+      for (int n = 1; n <= m; n++) {
+        double inv = -1.0 / (double)(2 * n);
+        double tr = fma(x, pr, -y * pi), ti = fma(x, pi, y * pr);
+        pr = tr * inv;
+        pi = ti * inv;
+      }
+      double2* Y = Yc + j * S;
+      double sg = (m & 1) ? -1.0 : 1.0;
+      // conj(Y_n^m) at +m; conj(Y_n^-m) = (-1)^m Y_n^m at -m
+      Y[m * m + m + m] = make_double2(pr, -pi);
+      if (m > 0) Y[m * m] = make_double2(sg * pr, sg * pi);
+      double ar2 = 0.0, ai2 = 0.0, ar1 = pr, ai1 = pi;
+      for (int n = m + 1; n <= p; n++) {
+        double k = (double)(2 * n - 1) * z, inv = 1.0 / (double)((n + m) * (n - m));
+        double vr = fma(k, ar1, -r2 * ar2) * inv, vi = fma(k, ai1, -r2 * ai2) * inv;
+        Y[n * n + n + m] = make_double2(vr, -vi);
+        if (m > 0) Y[n * n + n - m] = make_double2(sg * vr, sg * vi);
+        ar2 = ar1;
+        ai2 = ai1;
+        ar1 = vr;
+        ai1 = vi;
       }
     }
-    double* Lc = loc + (size_t)(k0 + j) * nc * 2;
-    Lc[2 * q] += sr;
-    Lc[2 * q + 1] += si;
+    __syncthreads();
+    for (int u = t; u < gn * nc; u += L2L_T) {
+      int j = u / nc, q = u - j * nc;
+      int jn = 0;
+      while (cidx(jn + 1, 0) <= q) jn++;
+      int i = q - cidx(jn, 0);
+      const double2* Y = Yc + j * S;
+      double sr = 0.0, si = 0.0;
+      for (int k = 0; k <= p - jn; k++) {
+        int n = jn + k;
+        const double2* Ln = Lx + n * n + n + i - k;
+        const double2* Yk = Y + k * k;
+#pragma unroll 4
+        for (int r = 0; r <= 2 * k; r++) {  // l = r - k
+          double2 a = Ln[r], b = Yk[r];
+          sr = fma(a.x, b.x, fma(-a.y, b.y, sr));
+          si = fma(a.x, b.y, fma(a.y, b.x, si));
+        }
+      }
+      double* Lc = loc + (size_t)(k0 + j0 + j) * nc * 2;
+      Lc[2 * q] += sr;
+      Lc[2 * q + 1] += si;
+    }
   }
 }
 
@@ -402,11 +408,13 @@ void launch_far_final(Ctx& c, double* acc, double* pot) {
 void launch_l2l(Ctx& c) { launch_l2l_buf(c, c.loc.p); }
 
 void launch_l2l_buf(Ctx& c, double* loc) {
-  size_t lds = sizeof(double2) * 9 * (size_t)(c.p + 1) * (c.p + 1);
+  size_t S = (size_t)(c.p + 1) * (c.p + 1);
+  int G = sizeof(double2) * 9 * S <= 64 * 1024 ? 8 : 1;  // children per pass within 64 KB of LDS
+  size_t lds = sizeof(double2) * (1 + G) * S;
   for (int level = 0; level < c.depth; level++) {  // parents at this level, children one below
     int first = c.lvl_first[level], count = c.lvl_count[level];
     hipLaunchKernelGGL(k_l2l, dim3(count), dim3(L2L_T), lds, c.stream, c.p, first, count, c.c_child0.p,
-                       c.c_nchild.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, loc);
+                       c.c_nchild.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, loc, G);
   }
   HIPCHK(hipGetLastError());
 }

@@ -32,7 +32,7 @@ constexpr int SWAP_DOUBLES = swoff(FMM_GPU_PMAX + 1);
 
 static __constant__ double c_cswap[8192];
 static __constant__ double c_fact_m2l[2 * FMM_GPU_PMAX + 2];
-static bool g_m2l_tables = false;
+static bool g_m2l_tables[64] = {};  // per device
 
 template <int I, int E, class F>
 __device__ __forceinline__ void static_for(F&& f) {
@@ -411,8 +411,15 @@ void launch_m2l_fp64_range(Ctx& c, int first_lo) {
   launch_m2l_fp64_buffers(c, first_lo, c.mult.p, c.loc.p);
 }
 
-static void upload_m2l_tables() {
-  if (g_m2l_tables) return;
+static bool& m2l_tables_flag() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  return g_m2l_tables[dev & 63];
+}
+
+void upload_m2l_tables() {
+  bool& done = m2l_tables_flag();
+  if (done) return;
   // compact the dense tables to their structural non-zeros (row-major)
   static_assert(CSWAP_DOUBLES <= 8192, "compacted swap table");
   std::vector<double> cs;
@@ -422,11 +429,12 @@ static void upload_m2l_tables() {
         if (swap_nz(n, i, j)) cs.push_back(fmm_swap_table[swoff(n) + i * (2 * n + 1) + j]);
   HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_cswap), cs.data(), sizeof(double) * cs.size()));
   HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_fact_m2l), fmm_fact_table, sizeof(double) * (2 * FMM_GPU_PMAX + 2)));
-  g_m2l_tables = true;
+  done = true;
 }
 
 // the same over other expansion buffers (same tree and list)
 void launch_m2l_fp64_buffers(Ctx& c, int first_lo, const double* mult, double* loc) {
+  if (c.p > FMM_GPU_PMAX) return launch_m2l_hi(c, first_lo, mult, loc, nullptr, nullptr);
   upload_m2l_tables();
   if (!dispatch<1>(c, first_lo, mult, loc, nullptr, nullptr))
     throw hip_error{hipErrorInvalidValue, "M2L order not compiled"};
@@ -437,6 +445,7 @@ void launch_m2l_fp64_buffers(Ctx& c, int first_lo, const double* mult, double* l
 // listed sink is written, the others are left untouched
 void launch_m2l_fp64_sinks(Ctx& c, int first_lo, const double* mult, double* loc, const int* sinks,
                            const int* nsinks) {
+  if (c.p > FMM_GPU_PMAX) return launch_m2l_hi(c, first_lo, mult, loc, sinks, nsinks);
   upload_m2l_tables();
   if (!dispatch<1>(c, first_lo, mult, loc, sinks, nsinks))
     throw hip_error{hipErrorInvalidValue, "M2L order not compiled"};

@@ -132,7 +132,7 @@ __device__ __forceinline__ void zrot(float* v, float c1, float s1) {
 
 constexpr int MX_CSWAP = mx::cswoff(FMM_GPU_PMAX + 1);
 static __constant__ float c_cswap32[MX_CSWAP];
-static bool g_mx_tables = false;
+static bool g_mx_tables[64] = {};  // per device
 constexpr int MX_WAVES = 4;
 
 // first source of [b, e) whose id is >= first_lo (ids are breadth first, so the
@@ -382,8 +382,10 @@ bool mixed_supported(int p) { return p >= 1 && p <= FMM_GPU_PMAX; }
 
 void launch_m2l_fp64_range(Ctx& c, int first_lo);
 
-void launch_m2l_mixed_lo(Ctx& c) {
-  if (!g_mx_tables) {
+void upload_mx_tables() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (!g_mx_tables[dev & 63]) {
     // orthogonal swap matrices G W_n G^-1 in FP32, structural non-zeros only
     std::vector<float> cs;
     for (int n = 0; n <= FMM_GPU_PMAX; n++)
@@ -394,8 +396,12 @@ void launch_m2l_mixed_lo(Ctx& c) {
             cs.push_back((float)(w * mx::gnorm(n, mx::rb_m(i)) / mx::gnorm(n, mx::rb_m(j))));
           }
     HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_cswap32), cs.data(), sizeof(float) * cs.size()));
-    g_mx_tables = true;
+    g_mx_tables[dev & 63] = true;
   }
+}
+
+void launch_m2l_mixed_lo(Ctx& c) {
+  upload_mx_tables();
   int nc = (int)c.ncell;
   int first_lo = mixed_first_lo(c);
   if (first_lo >= nc) {
@@ -426,6 +432,9 @@ void launch_normalize32(Ctx& c) {
 
 // first cell below the root levels (ids are breadth first)
 int mixed_first_lo(Ctx& c) {
+  // orders without an FP32 kernel: every M2L pair in FP64 (the near field
+  // stays FP32)
+  if (!mixed_supported(c.p)) return (int)c.ncell;
   int K = c.prm.root_levels;
   return K <= c.depth ? c.lvl_first[K] : (int)c.ncell;
 }

@@ -77,20 +77,21 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_apply(const int* in, int* out, 
 
 void exclusive_scan(Ctx& c, const int* in, int* out, int64_t n, long long* total_dev) {
   // recursive three-phase scan; scratch from c.scan_tmp
-  std::vector<int64_t> sizes;
+  int64_t sizes[16];  // block counts of the recursion levels (SCAN_TILE^16 exceeds any n)
+  int nlev = 0;
   int64_t m = n;
   while (m > SCAN_TILE) {
     m = ceil_div(m, SCAN_TILE);
-    sizes.push_back(m);
+    sizes[nlev++] = m;
   }
   size_t need = 0;
-  for (auto s : sizes) need += 2 * (size_t)s + 64;
+  for (int l = 0; l < nlev; l++) need += 2 * (size_t)sizes[l] + 64;
   ensure(c.ws, c.scan_tmp, need + 64);
   if (n == 0) {
     if (total_dev) HIPCHK(hipMemsetAsync(total_dev, 0, sizeof(long long), c.stream));
     return;
   }
-  if (sizes.empty()) {
+  if (nlev == 0) {
     hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(SCAN_T), 0, c.stream, in, out, n, nullptr,
                        total_dev, (int64_t)1);
     HIPCHK(hipGetLastError());
@@ -774,12 +775,16 @@ void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
     if (c.sys_off.p != before) c.sys_off_uploaded.clear();
   }
   {
-    std::vector<int> h(c.h_sys_off.begin(), c.h_sys_off.end());
-    if (h.empty()) h = {0, (int)n};
-    if (h != c.sys_off_uploaded) {  // the device copy is reused while the split is unchanged
-      HIPCHK(hipMemcpyAsync(c.sys_off.p, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    // the device copy is reused while the split is unchanged (no host
+    // allocation while it is: the comparison runs over the stored vectors)
+    if (c.h_sys_off.empty()) c.h_sys_off.assign({0, n});
+    bool same = c.sys_off_uploaded.size() == c.h_sys_off.size();
+    for (size_t k = 0; same && k < c.h_sys_off.size(); k++) same = c.sys_off_uploaded[k] == (int)c.h_sys_off[k];
+    if (!same) {
+      c.sys_off_uploaded.assign(c.h_sys_off.begin(), c.h_sys_off.end());
+      HIPCHK(hipMemcpyAsync(c.sys_off.p, c.sys_off_uploaded.data(), c.sys_off_uploaded.size() * sizeof(int),
+                            hipMemcpyHostToDevice, s));
       HIPCHK(hipStreamSynchronize(s));
-      c.sys_off_uploaded = h;
     }
   }
   if (nsys == 1) {

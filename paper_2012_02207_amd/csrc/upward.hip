@@ -19,7 +19,7 @@ namespace fmm {
 
 static __constant__ double c_fact[2 * FMM_TABLE_PMAX + 2];
 static __constant__ double c_binom[FMM_TABLE_PMAX + 1][FMM_TABLE_PMAX + 1];
-static bool g_up_tables = false;
+static bool g_up_tables[64] = {};  // per device
 
 // Column m of the regular harmonics of (x, y, z) in the exact rounding
 // sequence of the full recurrence (the same arithmetic as regular_exact): the
@@ -208,6 +208,90 @@ __global__ void __launch_bounds__(M2M_T) k_m2m(int p, int first, int count, cons
 
 size_t m2m_lds_bytes(int p) { return sizeof(double2) * 2 * 8 * (size_t)(p + 1) * (p + 1); }
 
+// The same M2M with one child at a time in LDS (harmonics and moments of that
+// child only), for the orders whose eight children do not fit: each lane
+// carries its coefficients' sums from child to child, so every sum runs in
+// the same order (children in octant order, then k, then l) and rounds
+// exactly as in k_m2m.
+constexpr int M2M_SMAXK = (ncoef(FMM_TABLE_PMAX) + M2M_T - 1) / M2M_T;
+
+__global__ void __launch_bounds__(M2M_T) k_m2m_stream(int p, int first, int count, const int* c0,
+                                                       const int* nch, const double* cx, const double* cy,
+                                                       const double* cz, double* mult) {
+  extern __shared__ double lds[];
+  int c = first + blockIdx.x;
+  if (blockIdx.x >= count || nch[c] == 0) return;
+  int nc = ncoef(p);
+  int S = (p + 1) * (p + 1);
+  int k0 = c0[c], kn = nch[c];
+  double2* Y = (double2*)lds;  // [S] harmonics of the current child
+  double2* Mx = Y + S;         // [S] its moments, both signs of q
+  int t = threadIdx.x;
+  double sr[M2M_SMAXK], si[M2M_SMAXK];
+  for (int q = 0; q < M2M_SMAXK; q++) sr[q] = si[q] = 0.0;
+  for (int j = 0; j < kn; j++) {
+    int ch = k0 + j;
+    for (int m = t; m <= p; m += M2M_T) {
+      double sg = (m & 1) ? -1.0 : 1.0;
+      regular_column_exact(p, m, cx[ch] - cx[c], cy[ch] - cy[c], cz[ch] - cz[c],
+                           [&](int n, double vr, double vi) {
+                             Y[n * n + n + m] = make_double2(vr, vi);
+                             if (m > 0) Y[n * n + n - m] = make_double2(sg * vr, -sg * vi);
+                           });
+    }
+    const double* cm = mult + (size_t)ch * nc * 2;
+    for (int r = t; r < S; r += M2M_T) {
+      int n = 0;
+      while ((n + 1) * (n + 1) <= r) n++;
+      int q = r - n * n - n;
+      int aq = q < 0 ? -q : q;
+      double a = cm[2 * cidx(n, aq)], bb = cm[2 * cidx(n, aq) + 1];
+      if (q < 0) {
+        double sg = (aq & 1) ? -1.0 : 1.0;
+        a = sg * a;
+        bb = -sg * bb;
+      }
+      Mx[r] = make_double2(a, bb);
+    }
+    __syncthreads();
+    for (int q = 0; q < M2M_SMAXK; q++) {
+      int u = t + M2M_T * q;
+      if (u >= nc) break;
+      int n, m;
+      coef_nm(u, n, m);
+      double ar = sr[q], ai = si[q];
+      for (int k = 0; k <= n; k++) {
+        int jj = n - k;
+        int lo = max(-k, m - jj), hi = min(k, m + jj);
+        const double2* Yk = Y + k * k + k + lo;
+        const double2* Mj = Mx + jj * jj + jj + m - lo;
+        int cnt = hi - lo + 1;
+        for (int r = 0; r < cnt; r++) {  // l = lo + r
+          double2 a = Yk[r], bq = Mj[-r];
+          double tr = a.x * bq.x - a.y * bq.y;
+          double ti = a.x * bq.y + a.y * bq.x;
+          ar = ar + tr;
+          ai = ai + ti;
+        }
+      }
+      sr[q] = ar;
+      si[q] = ai;
+    }
+    __syncthreads();
+  }
+  double* out = mult + (size_t)c * nc * 2;
+  for (int q = 0; q < M2M_SMAXK; q++) {
+    int u = t + M2M_T * q;
+    if (u < nc) {
+      out[2 * u] = sr[q];
+      out[2 * u + 1] = si[q];
+    }
+  }
+}
+
+// the eight-children layout up to this order (74 KB of LDS at p = 16)
+constexpr int M2M_ALL_CHILDREN_PMAX = 16;
+
 // P_k = sqrt( (k!)^2 |M_k^0|^2 + sum_{m=1..k} 2 (k-m)!(k+m)! |M_k^m|^2 ), and the
 // product C(p, k) P_k used by the acceptance test
 __global__ void k_pk(int p, int ncell, const double* mult, double* pk, double* pkb) {
@@ -230,18 +314,27 @@ __global__ void k_pk(int p, int ncell, const double* mult, double* pk, double* p
 void m2m_levels(Ctx& c, double* mult) {
   for (int level = c.depth - 1; level >= 0; level--) {
     int first = c.lvl_first[level], count = c.lvl_count[level];
-    hipLaunchKernelGGL(k_m2m, dim3(count), dim3(M2M_T), m2m_lds_bytes(c.p), c.stream, c.p, first, count,
-                       c.c_child0.p, c.c_nchild.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, mult);
+    if (c.p <= M2M_ALL_CHILDREN_PMAX)
+      hipLaunchKernelGGL(k_m2m, dim3(count), dim3(M2M_T), m2m_lds_bytes(c.p), c.stream, c.p, first, count,
+                         c.c_child0.p, c.c_nchild.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, mult);
+    else
+      hipLaunchKernelGGL(k_m2m_stream, dim3(count), dim3(M2M_T), m2m_lds_bytes(c.p) / 8, c.stream, c.p, first,
+                         count, c.c_child0.p, c.c_nchild.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, mult);
     HIPCHK(hipGetLastError());
   }
 }
 
+void upload_up_tables() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (g_up_tables[dev & 63]) return;
+  HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_fact), fmm_fact_table, sizeof(fmm_fact_table)));
+  HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_binom), fmm_binom_table, sizeof(fmm_binom_table)));
+  g_up_tables[dev & 63] = true;
+}
+
 void upward_pass(Ctx& c) {
-  if (!g_up_tables) {
-    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_fact), fmm_fact_table, sizeof(fmm_fact_table)));
-    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_binom), fmm_binom_table, sizeof(fmm_binom_table)));
-    g_up_tables = true;
-  }
+  upload_up_tables();
   int p = c.p, nc = (int)c.ncell;
   ensure(c.ws, c.mult, (size_t)nc * ncoef(p) * 2);
   ensure(c.ws, c.pk, (size_t)nc * (p + 1));

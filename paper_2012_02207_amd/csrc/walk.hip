@@ -19,6 +19,7 @@
 #include <functional>
 
 #include <algorithm>
+#include <climits>
 
 #include "fmm_device.h"
 #include "fmm_tables.h"
@@ -44,26 +45,32 @@ __device__ __forceinline__ double com_r2(const double4& a, const double4& b) {
 
 // E_{A->B} M_A / r^2 with M_A cancelled; sums in the order the definition
 // lists (k ascending), each term (C(p,k) P_{k,A}) r_B^{p-k}, with C(p,k) P_{k,A}
-// formed once per cell by the upward pass
+// formed once per cell by the upward pass.  P = 0: the order is the run-time
+// v.p (orders without an unrolled instance), with the same operations in the
+// same order.
 template <int P>
 __device__ double mac_lhs(const CellView& v, int A, double rA, double rB, double r, double r2) {
+  constexpr int PM = P > 0 ? P : FMM_TABLE_PMAX;
+  const int p = P > 0 ? P : v.p;
   double rp = r;
 #pragma unroll
-  for (int i = 2; i <= P; i++) rp = rp * r;
+  for (int i = 2; i <= PM; i++)
+    if (i <= p) rp = rp * r;
   double mx = rA > rB ? rA : rB;
   double pref = (8.0 * mx) / (rA + rB);
-  double pw[P + 1];
+  double pw[PM + 1];
   pw[0] = 1.0;
   double powB = 1.0;
 #pragma unroll
-  for (int j = 1; j <= P; j++) {
+  for (int j = 1; j <= PM; j++) {
     powB = powB * rB;
     pw[j] = powB;
   }
-  const double* PA = v.pkb + (size_t)A * (P + 1);
+  const double* PA = v.pkb + (size_t)A * (p + 1);
   double SA = 0.0;
 #pragma unroll
-  for (int k = 0; k <= P; k++) SA = SA + PA[k] * pw[P - k];
+  for (int k = 0; k <= PM; k++)
+    if (k <= p) SA = SA + PA[k] * pw[p - k];
   return (pref * (SA / rp)) / r2;
 }
 
@@ -96,9 +103,11 @@ __device__ __forceinline__ int wave_incl_scan(int x) {
 
 constexpr int WALK_T = 512;  // threads per workgroup of the walk kernels
 
-// One workgroup-aggregated allocation of `cnt` slots from counter *ctr: a
-// wave scan, the wave totals combined through LDS, one atomic per workgroup.
-__device__ __forceinline__ long long block_alloc(int cnt, int* ctr, int& excl, int* sh) {
+// One workgroup-aggregated allocation of `cnt` slots from the 64-bit counter
+// *ctr: a wave scan, the wave totals combined through LDS, one atomic per
+// workgroup.
+__device__ __forceinline__ long long block_alloc(int cnt, unsigned long long* ctr, int& excl, int* sh,
+                                                 long long* shb) {
   int incl = wave_incl_scan(cnt);
   int wv = threadIdx.x >> 6;
   if (lane_id() == 63) sh[wv] = incl;
@@ -110,35 +119,43 @@ __device__ __forceinline__ long long block_alloc(int cnt, int* ctr, int& excl, i
       sh[w] = run;
       run += t;
     }
-    sh[WALK_T / 64] = run > 0 ? atomicAdd(ctr, run) : 0;
+    *shb = run > 0 ? (long long)atomicAdd(ctr, (unsigned long long)run) : 0;
   }
   __syncthreads();
   excl = incl - cnt + sh[wv];
-  long long base = sh[WALK_T / 64];
+  long long base = *shb;
   __syncthreads();
   return base;
 }
 
-// Device counters of a walk (ints, each on its own cache line): three
-// rotating frontier sizes, the totals of accepted and near-field entries, and
-// the largest frontier seen.  Step k reads its frontier size from slot k % 3,
-// appends to slot (k+1) % 3 and clears slot (k+2) % 3 for the step after, so
-// consecutive steps need no host round trip.
+// Device counters of a walk (64-bit, each on its own cache line, at the int
+// offsets below): three rotating frontier sizes, the totals of accepted and
+// near-field entries, and the largest frontier seen.  Step k reads its
+// frontier size from slot k % 3, appends to slot (k+1) % 3 and clears slot
+// (k+2) % 3 for the step after, so consecutive steps need no host round trip.
+// 64-bit totals cannot wrap; the host rejects lists longer than the int32
+// CSR arrays can index (walk_list_fits).
 constexpr int WC_FRONT = 0, WC_ACC = 96, WC_NEAR = 128, WC_MAXF = 160, WC_INTS = 192;
 constexpr int WALK_BLOCKS = 1024;  // persistent grid; blocks stride over the frontier
 
+__device__ __forceinline__ unsigned long long* wc64(int* ctr, int off) {
+  return reinterpret_cast<unsigned long long*>(ctr + off);
+}
+
 template <int KIND, int P>
 __global__ void __launch_bounds__(WALK_T) k_walk(CellView v, int step, const int2* fin, int fin_cap,
-                                              int2* fout, int fcap, int* ctr, uint64_t* acc_list,
-                                              int acap, uint64_t* near_list, int ncap, int bits) {
-  int nin_all = ctr[WC_FRONT + 32 * (step % 3)];
+                                              int2* fout, long long fcap, int* ctr, uint64_t* acc_list,
+                                              long long acap, uint64_t* near_list, long long ncap,
+                                              int bits) {
+  long long nin_all = (long long)*wc64(ctr, WC_FRONT + 32 * (step % 3));
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctr[WC_FRONT + 32 * ((step + 2) % 3)] = 0;
-    atomicMax(&ctr[WC_MAXF], nin_all);
+    *wc64(ctr, WC_FRONT + 32 * ((step + 2) % 3)) = 0ull;
+    atomicMax(wc64(ctr, WC_MAXF), (unsigned long long)nin_all);
   }
-  int nin = min(nin_all, fin_cap);  // an overflowed frontier is redone by the host
-  int* fctr = &ctr[WC_FRONT + 32 * ((step + 1) % 3)];
-  __shared__ int sh[WALK_T / 64 + 1];
+  int nin = (int)min(nin_all, (long long)fin_cap);  // an overflowed frontier is redone by the host
+  unsigned long long* fctr = wc64(ctr, WC_FRONT + 32 * ((step + 1) % 3));
+  __shared__ int sh[WALK_T / 64];
+  __shared__ long long shb;
   for (int base = blockIdx.x * WALK_T; base < nin; base += gridDim.x * WALK_T) {
     int t = base + threadIdx.x;
     bool live = t < nin;
@@ -170,9 +187,9 @@ __global__ void __launch_bounds__(WALK_T) k_walk(CellView v, int step, const int
       }
     }
     int ek, ea, en;
-    long long bk = block_alloc(nkids, fctr, ek, sh);
-    long long ba = block_alloc(nacc, &ctr[WC_ACC], ea, sh);
-    long long bn = block_alloc(nnear, &ctr[WC_NEAR], en, sh);
+    long long bk = block_alloc(nkids, fctr, ek, sh, &shb);
+    long long ba = block_alloc(nacc, wc64(ctr, WC_ACC), ea, sh, &shb);
+    long long bn = block_alloc(nnear, wc64(ctr, WC_NEAR), en, sh, &shb);
     if (!live) continue;
     long long o = bk + ek;
     if (mode == 1) {
@@ -214,7 +231,7 @@ __global__ void __launch_bounds__(WALK_T) k_walk(CellView v, int step, const int
 __global__ void k_seed(int2* f, int nsys, int* ctr) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s < nsys) f[s] = make_int2(s, s);
-  if (s < WC_INTS) ctr[s] = s == WC_FRONT ? nsys : 0;
+  if (s < WC_INTS) ctr[s] = s == WC_FRONT ? nsys : 0;  // low half of the 64-bit frontier size
 }
 
 // ---- grouping by sink, sorted by source ----------------------------------
@@ -305,11 +322,13 @@ static void run_walk(Ctx& c, CellList& acc, CellList& nearl, bool group,
   ensure(c.ws, c.counters, 512);
   int* ctr = c.counters.p + 256;
   int bits = list_bits(c.ncell);
-  int* h = (int*)c.hbuf;
+  long long* h = c.hbuf;  // the counters, read back as 64-bit values
+  auto H = [&](int off) { return h[off / 2]; };
   // A pair's step count is at most the sum of its cells' levels plus one, so
   // 2 depth + 2 steps drain the frontier; the host checks once at the end.
   int steps = 2 * c.depth + 2;
-  int nacc = 0, nnear = 0;
+  long long nacc = 0, nnear = 0;
+  auto fcap_of = [&](const dbuf<int2>& f) { return (int)std::min<size_t>(f.cap, (size_t)INT_MAX); };
   for (int attempt = 0;; attempt++) {
     int sblocks = (int)ceil_div(std::max(c.nsys, WC_INTS), 256);
     hipLaunchKernelGGL(k_seed, dim3((unsigned)sblocks), dim3(256), 0, s, c.front[0].p, c.nsys, ctr);
@@ -318,23 +337,25 @@ static void run_walk(Ctx& c, CellList& acc, CellList& nearl, bool group,
     while (!done) {
       for (int e = 0; e < steps; e++, step++)
         hipLaunchKernelGGL((k_walk<KIND, P>), dim3(WALK_BLOCKS), dim3(WALK_T), 0, s, v, step,
-                           c.front[step & 1].p, (int)c.front[step & 1].cap, c.front[1 - (step & 1)].p,
-                           (int)c.front[1 - (step & 1)].cap, ctr, acc.raw.p, (int)acc.raw.cap,
-                           nearl.raw.p, (int)nearl.raw.cap, bits);
+                           c.front[step & 1].p, fcap_of(c.front[step & 1]), c.front[1 - (step & 1)].p,
+                           (long long)fcap_of(c.front[1 - (step & 1)]), ctr, acc.raw.p,
+                           (long long)acc.raw.cap, nearl.raw.p, (long long)nearl.raw.cap, bits);
       HIPCHK(hipGetLastError());
       if (beside && attempt == 0 && step == steps) beside();
       HIPCHK(hipMemcpyAsync(h, ctr, WC_INTS * sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      done = h[WC_FRONT + 32 * (step % 3)] == 0;  // frontier of the next step is empty
-      if (h[WC_MAXF] > (int)std::min(c.front[0].cap, c.front[1].cap)) break;  // overflowed: redo
+      done = H(WC_FRONT + 32 * (step % 3)) == 0;  // frontier of the next step is empty
+      if (H(WC_MAXF) > std::min(fcap_of(c.front[0]), fcap_of(c.front[1]))) break;  // overflowed: redo
     }
-    nacc = h[WC_ACC];
-    nnear = h[WC_NEAR];
+    nacc = H(WC_ACC);
+    nnear = H(WC_NEAR);
+    long long need_f = H(WC_MAXF);
+    if (!walk_list_fits(nacc) || !walk_list_fits(nnear) || !walk_list_fits(need_f))
+      throw unsupported_error{"interaction list or walk frontier longer than 2^31 - 64 entries"};
     bool again = false;
-    size_t need_f = (size_t)h[WC_MAXF];
-    if (need_f > std::min(c.front[0].cap, c.front[1].cap)) {
-      ensure(c.ws, c.front[0], need_f * 2);
-      ensure(c.ws, c.front[1], need_f * 2);
+    if (need_f > std::min(fcap_of(c.front[0]), fcap_of(c.front[1]))) {
+      ensure(c.ws, c.front[0], (size_t)need_f * 2);
+      ensure(c.ws, c.front[1], (size_t)need_f * 2);
       again = true;
     }
     if ((size_t)nacc + 2 > acc.raw.cap) {
@@ -530,7 +551,9 @@ void estimate_walk(Ctx& c, const std::function<void()>& beside) {
 template <int P>
 static bool mac_dispatch(Ctx& c) {
   if constexpr (P > FMM_GPU_PMAX) {
-    return false;
+    if (c.p > FMM_TABLE_PMAX) return false;
+    run_walk<1, 0>(c, c.m2l, c.p2p, false);  // higher orders: run-time p
+    return true;
   } else {
     if (c.p == P) {
       run_walk<1, P>(c, c.m2l, c.p2p, false);  // grouped by the caller (group_list)

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.mark.parametrize("eps_soft,p,tol", [(0.0, 10, 1e-7), (0.01, 8, 1e-6)])
+@pytest.mark.parametrize("eps_soft,p,tol", [(0.0, 10, 1e-7), (0.01, 8, 1e-6), (0.0, 20, 1e-7)])
 def test_jerk_matches_direct_sum(eps_soft, p, tol):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")

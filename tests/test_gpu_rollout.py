@@ -29,7 +29,7 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
 
-@pytest.mark.parametrize("eps_soft,p,tol", [(0.0, 10, 1e-7), (0.01, 8, 1e-6)])
+@pytest.mark.parametrize("eps_soft,p,tol", [(0.0, 10, 1e-7), (0.01, 8, 1e-6), (0.0, 20, 1e-7)])
 def test_force_adjoint_matches_direct_sum(fmm, eps_soft, p, tol):
     pos, _, mass = W.plummer(4096, 123)
     rng = np.random.default_rng(4)
