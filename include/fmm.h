@@ -206,6 +206,33 @@ fmm_status fmm_jerk(fmm_ctx* ctx, int64_t n, const double* pos, const double* ve
                     double eps_soft, int p, double err_tol, double* acc, double* pot, double* jerk,
                     void* stream);
 
+/* Limits of fmm_forces_noalloc: the largest body count, and the size of the
+ * static device scratch it works in (one per device, held until the process
+ * ends). */
+#define FMM_NOALLOC_MAX_N 65536
+#define FMM_NOALLOC_SCRATCH_BYTES (128u << 20)
+
+/* fmm_forces for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Every
+ * scratch buffer of the evaluation (sort state, cells, expansions, interaction
+ * lists, partial sums, counters) is carved from the library's static device
+ * array of FMM_NOALLOC_SCRATCH_BYTES instead of the context's workspace: the
+ * call performs no hipMalloc, hipFree or other allocation.  fmm_create, on the
+ * same device, set up everything it needs (the scratch's device address, the
+ * kernels' constant tables, the context's streams, events and pinned host
+ * words).  Arguments, outputs and results are those of fmm_forces with the
+ * context's parameters.  Errors: n above FMM_NOALLOC_MAX_N, or another device
+ * current than at fmm_create -> FMM_EINVAL; an input whose tree, expansions
+ * and lists do not fit the scratch -> FMM_ENOMEM (fmm_last_error says so);
+ * otherwise as fmm_forces.  All calls on one device share that device's
+ * scratch, which keeps the last call's contents (each call initialises what
+ * it reads): calls that overlap on one device, from any context or host
+ * thread, race and must be serialised by the caller.  fmm_stats and
+ * fmm_export describe the last call of the other entry points. */
+fmm_status fmm_forces_noalloc(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass,
+                              double eps_soft, int p, double err_tol, double* acc, double* pot,
+                              void* stream);
+
 /* Largest number of systems one fmm_forces_batch call accepts. */
 #define FMM_MAX_SYSTEMS 65536
 

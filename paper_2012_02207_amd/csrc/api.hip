@@ -14,6 +14,7 @@
 
 struct fmm_ctx {
   fmm::Ctx c;
+  fmm::Ctx* na = nullptr;  // state of fmm_forces_noalloc (buffers in the static scratch)
 };
 
 namespace fmm {
@@ -23,6 +24,12 @@ void check(hipError_t e, const char* what) {
 }
 
 void* ws_alloc(Workspace& w, size_t bytes) {
+  if (w.arena) {  // carve from the fixed region: no allocation
+    size_t at = (w.arena_used + 255) & ~(size_t)255;
+    if (at + bytes > w.arena_cap) throw oom_error{};
+    w.arena_used = at + bytes;
+    return w.arena + at;
+  }
   if (w.limit && w.bytes + bytes > w.limit) throw oom_error{};
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, bytes ? bytes : 1);
@@ -36,8 +43,29 @@ void* ws_alloc(Workspace& w, size_t bytes) {
 }
 
 void ws_free(Workspace& w, void* p, size_t bytes) {
+  if (w.arena) return;  // the region outlives the call; its epoch ends with it
   (void)hipFree(p);
   w.bytes -= bytes;
+}
+
+// ---- device scratch of the allocation-free entry point ----------------------
+// One static array per device, held until the process ends.  In host code the
+// name `scratch` is a host-side stand-in, not a device address: its device
+// address is taken once per device with hipGetSymbolAddress (with that device
+// current) and only that address is ever handed to kernels or copies.
+static __device__ __align__(256) unsigned char scratch[FMM_NOALLOC_SCRATCH_BYTES];
+static void* g_scratch_dev[64] = {};  // device address of `scratch`, per device
+static std::mutex g_scratch_mu;
+
+static void* scratch_address(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (dev < 0 || dev >= 64) throw unsupported_error{"device ordinal above 63"};
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_dev[dev] = ptr;
+  }
+  return g_scratch_dev[dev];
 }
 
 // zeroing by a kernel (not hipMemsetAsync), so the sequences stay capturable
@@ -200,9 +228,14 @@ fmm_status fmm_create(fmm_ctx** out, const fmm_params* prm) {
   if (st != FMM_OK) return st;
   fmm_ctx* ctx = new (std::nothrow) fmm_ctx();
   if (!ctx) return FMM_ENOMEM;
+  ctx->na = new (std::nothrow) Ctx();
+  if (!ctx->na) {
+    delete ctx;
+    return FMM_ENOMEM;
+  }
   ctx->c.prm = p;
   st = guarded(ctx, [&]() {
-    for (Ctx* c : {&ctx->c}) {
+    for (Ctx* c : {&ctx->c, ctx->na}) {
       HIPCHK(hipGetDevice(&c->device));
       HIPCHK(hipHostMalloc((void**)&c->hbuf, 128 * sizeof(long long), hipHostMallocDefault));
       for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
@@ -211,11 +244,22 @@ fmm_status fmm_create(fmm_ctx** out, const fmm_params* prm) {
       HIPCHK(hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking));
       HIPCHK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
     }
-    // the kernels' constant tables, once per device
+    // everything the allocation-free entry point needs is set up here: the
+    // kernels' constant tables, the scratch address on this device, and host
+    // containers sized so that its calls do not grow them
     upload_up_tables();
     upload_m2l_tables();
     upload_mx_tables();
     upload_hi_tables();
+    Ctx& na = *ctx->na;
+    na.ws.arena = (char*)scratch_address(na.device);
+    na.ws.arena_cap = FMM_NOALLOC_SCRATCH_BYTES;
+    na.ws.epoch = 1;
+    na.h_sys_off.reserve(4);
+    na.sys_off_uploaded.reserve(4);
+    na.lvl_first.reserve(FMM_MAX_LEVEL + 8);
+    na.lvl_count.reserve(FMM_MAX_LEVEL + 8);
+    ctx->c.err.reserve(256);
     return FMM_OK;
   });
   if (st != FMM_OK) {
@@ -345,6 +389,33 @@ fmm_status fmm_forces(fmm_ctx* ctx, int64_t n, const double* pos, const double* 
                       int p, double err_tol, double* acc, double* pot, void* stream) {
   int64_t off[2] = {0, n};
   return forces_impl(ctx, 1, off, n, pos, mass, eps_soft, p, err_tol, acc, pot, stream);
+}
+
+fmm_status fmm_forces_noalloc(fmm_ctx* ctx, int64_t n, const double* pos, const double* mass,
+                              double eps_soft, int p, double err_tol, double* acc, double* pot,
+                              void* stream) {
+  if (!ctx || !ctx->na) return FMM_EINVAL;
+  if (n > FMM_NOALLOC_MAX_N) {
+    ctx->c.err = "fmm_forces_noalloc: n exceeds FMM_NOALLOC_MAX_N";
+    return FMM_EINVAL;
+  }
+  Ctx& a = *ctx->na;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != a.device) {
+    (void)hipGetLastError();
+    ctx->c.err = "fmm_forces_noalloc: called with another device current than at fmm_create";
+    return FMM_EINVAL;
+  }
+  a.prm = ctx->c.prm;
+  a.ws.arena_used = 0;  // a new epoch: the buffers of earlier calls are gone
+  a.ws.epoch++;
+  if (a.ws.epoch == 0) a.ws.epoch = 1;
+  a.sys_off_uploaded.clear();
+  a.graph_valid = false;
+  int64_t off[2] = {0, n};
+  fmm_status st = forces_on(ctx, a, 1, off, n, pos, mass, eps_soft, p, err_tol, acc, pot, stream);
+  if (st == FMM_ENOMEM) ctx->c.err = "fmm_forces_noalloc: the static scratch is too small for this input";
+  return st;
 }
 
 fmm_status fmm_forces_batch(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets, const double* pos,
@@ -781,6 +852,19 @@ void fmm_destroy(fmm_ctx* ctx) {
     if (e) (void)hipEventDestroy(e);
   for (auto& e : c.fork)
     if (e) (void)hipEventDestroy(e);
+  if (Ctx* na = ctx->na) {  // its buffers live in the static scratch: nothing to free there
+    if (na->hbuf) (void)hipHostFree(na->hbuf);
+    for (hipStream_t* st : {&na->side, &na->side2, &na->cap})
+      if (*st) {
+        (void)hipStreamSynchronize(*st);
+        (void)hipStreamDestroy(*st);
+      }
+    for (auto& e : na->ev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& e : na->fork)
+      if (e) (void)hipEventDestroy(e);
+    delete na;
+  }
   delete ctx;
 }
 

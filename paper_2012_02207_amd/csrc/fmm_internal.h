@@ -39,7 +39,8 @@ void check(hipError_t e, const char* what);
 template <class T>
 struct dbuf {
   T* p = nullptr;
-  size_t cap = 0;  // elements
+  size_t cap = 0;      // elements
+  unsigned epoch = 0;  // workspace epoch the allocation belongs to
 };
 
 struct Workspace;
@@ -48,9 +49,17 @@ struct Workspace;
 void* ws_alloc(Workspace& w, size_t bytes);
 void ws_free(Workspace& w, void* p, size_t bytes);
 
+// Device workspace of a context.  Normally every buffer is its own hipMalloc.
+// In arena mode (the allocation-free entry point) buffers are carved from a
+// fixed region that the context does not own: nothing is allocated or freed,
+// and each call starts a new epoch, so buffers of earlier calls count as
+// absent and are carved again from the start of the region.
 struct Workspace {
   size_t bytes = 0;
   size_t limit = 0;  // 0 = unlimited
+  char* arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
+  unsigned epoch = 0;
 };
 
 struct oom_error {};
@@ -61,21 +70,23 @@ struct unsupported_error {
 
 template <class T>
 void ensure(Workspace& w, dbuf<T>& b, size_t n, bool keep = false, hipStream_t s = nullptr) {
-  if (n <= b.cap) return;
+  bool live = b.p && b.epoch == w.epoch;
+  if (live && n <= b.cap) return;
   size_t ncap = n + n / 4 + 64;
   T* np = (T*)ws_alloc(w, ncap * sizeof(T));
-  if (keep && b.p && b.cap) HIPCHK(hipMemcpyAsync(np, b.p, b.cap * sizeof(T), hipMemcpyDeviceToDevice, s));
-  if (b.p) {
+  if (keep && live && b.cap) HIPCHK(hipMemcpyAsync(np, b.p, b.cap * sizeof(T), hipMemcpyDeviceToDevice, s));
+  if (live) {
     if (keep) HIPCHK(hipStreamSynchronize(s));
     ws_free(w, b.p, b.cap * sizeof(T));
   }
   b.p = np;
   b.cap = ncap;
+  b.epoch = w.epoch;
 }
 
 template <class T>
 void release(Workspace& w, dbuf<T>& b) {
-  if (b.p) ws_free(w, b.p, b.cap * sizeof(T));
+  if (b.p && b.epoch == w.epoch) ws_free(w, b.p, b.cap * sizeof(T));
   b.p = nullptr;
   b.cap = 0;
 }

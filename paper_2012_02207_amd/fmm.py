@@ -25,10 +25,13 @@ EXPORTS = dict(keys=(0, np.uint64), perm=(1, np.int32), cell_level=(2, np.int32)
                m2l=(18, np.int32), p2p=(19, np.int32), local=(20, np.float64),
                rootbox=(21, np.float64))
 SYMBOLS = ["fmm_default_params", "fmm_create", "fmm_set_params", "fmm_build", "fmm_forces",
-           "fmm_forces_batch", "fmm_forces_frozen",
+           "fmm_forces_noalloc", "fmm_forces_batch", "fmm_forces_frozen",
            "fmm_forces_frozen_graph", "fmm_autotune", "fmm_adjoint", "fmm_jerk",
            "fmm_stats", "fmm_export", "fmm_set_workspace_limit",
            "fmm_direct", "fmm_strerror", "fmm_last_error", "fmm_destroy"]
+
+
+NOALLOC_MAX_N = 65536  # FMM_NOALLOC_MAX_N of include/fmm.h
 
 
 class FmmError(RuntimeError):
@@ -73,6 +76,7 @@ def load_library():
     lib.fmm_set_params.argtypes = [P, C.POINTER(Params)]
     lib.fmm_build.argtypes = [P, C.c_int64, P, P, P]
     lib.fmm_forces.argtypes = [P, C.c_int64, P, P, C.c_double, C.c_int, C.c_double, P, P, P]
+    lib.fmm_forces_noalloc.argtypes = [P, C.c_int64, P, P, C.c_double, C.c_int, C.c_double, P, P, P]
     lib.fmm_forces_batch.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), P, P, C.c_double, C.c_int,
                                      C.c_double, P, P, P]
     lib.fmm_autotune.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), P, P, C.c_double, C.c_int,
@@ -90,7 +94,7 @@ def load_library():
     lib.fmm_last_error.argtypes = [P]
     lib.fmm_last_error.restype = C.c_char_p
     lib.fmm_destroy.argtypes = [P]
-    for f in ("fmm_create", "fmm_set_params", "fmm_build", "fmm_forces", "fmm_forces_batch",
+    for f in ("fmm_create", "fmm_set_params", "fmm_build", "fmm_forces", "fmm_forces_noalloc", "fmm_forces_batch",
               "fmm_forces_frozen", "fmm_forces_frozen_graph", "fmm_autotune", "fmm_adjoint", "fmm_jerk", "fmm_stats", "fmm_export", "fmm_set_workspace_limit",
               "fmm_direct"):
         getattr(lib, f).restype = C.c_int
@@ -181,8 +185,10 @@ class FMM:
                                         _dev_ptr(mass, torch.float64, (n,), "mass"), _stream()))
         self.n = n
 
-    def forces(self, pos, mass, eps_soft=0.0, p=None, err_tol=None, out=None):
-        """acc (n, 3) and pot (n,) as new (or given) float64 device tensors."""
+    def forces(self, pos, mass, eps_soft=0.0, p=None, err_tol=None, out=None, noalloc=False):
+        """acc (n, 3) and pot (n,) as new (or given) float64 device tensors.
+        noalloc=True calls fmm_forces_noalloc (scratch in the library's static
+        device array; n <= NOALLOC_MAX_N)."""
         torch = _torch()
         n = mass.shape[0]
         pp = _dev_ptr(pos, torch.float64, (n, 3), "pos")
@@ -192,13 +198,15 @@ class FMM:
             pot = torch.empty((n,), dtype=torch.float64, device=pos.device)
         else:
             acc, pot = out
-        self._check(self._lib.fmm_forces(
+        fn = self._lib.fmm_forces_noalloc if noalloc else self._lib.fmm_forces
+        self._check(fn(
             self._h, n, pp, mp, float(eps_soft), int(self.params.p if p is None else p),
             float(self.params.err_tol if err_tol is None else err_tol),
             _dev_ptr(acc, torch.float64, (n, 3), "acc"), _dev_ptr(pot, torch.float64, (n,), "pot"),
             _stream()))
-        self.n = n
-        self.last_p = int(self.params.p if p is None else p)
+        if not noalloc:  # the allocation-free call leaves the context's exports alone
+            self.n = n
+            self.last_p = int(self.params.p if p is None else p)
         return acc, pot
 
     def forces_batch(self, pos, mass, offsets, eps_soft=0.0, p=None, err_tol=None, out=None):
