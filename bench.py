@@ -10,7 +10,11 @@ line.  Also reports:
   * the roofline of the dominant kernel (achieved algorithmic FLOP/s against
     the MI355X peak of its precision), timed with HIP events on the stream the
     library launches on, averaged over the timed steps;
-  * the CPU oracle timed on a bounded sample of the same workload.
+  * the CPU oracle on the same host: one full evaluation of the same
+    workload, and the 4096-body configuration with all threads and with one.
+The timed calls run back to back; the per-kernel durations (HIP events the
+library records around its kernels, read by fmm_stats) come from a second pass
+of the same calls, each followed by a stats read.
 """
 import argparse
 import json
@@ -80,33 +84,77 @@ def measured_traffic(kernel, workload, precision):
     return nbytes if cur == sha else None
 
 
-def cpu_baseline(pos, mass, p, err_tol, n_leaf, frac, seed=5):
-    """The CPU oracle on a bounded sample: tree, upward pass, estimate and walk
-    in full; evaluation (M2L, L2L, L2P, P2P) for a random `frac` of the leaves,
-    its time scaled by the inverse leaf fraction."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+_ORACLE_C1_SNIPPET = r"""
+import json, sys, time
+sys.path.insert(0, {root!r})
+import oracle
+from paper_2012_02207_amd import workloads as W
+cfg = W.CONFIGS["plummer_4k"]
+pos, _, mass = W.plummer(cfg["n"], cfg["seed"])
+o = oracle.Oracle()
+o.run(pos, mass, p=cfg["p"], err_tol=cfg["err_tol"], n_leaf=64)
+ts = []
+for _ in range(3):
+    t0 = time.perf_counter()
+    o.run(pos, mass, p=cfg["p"], err_tol=cfg["err_tol"], n_leaf=64)
+    ts.append(time.perf_counter() - t0)
+print(json.dumps({{"median_s": sorted(ts)[1], "threads": oracle.threads()}}))
+"""
+
+
+def _oracle_c1_single_thread():
+    """The 4096-body configuration in a child process pinned to one OpenMP
+    thread (median of 3 runs)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", _ORACLE_C1_SNIPPET.format(root=ROOT)], env=env,
+                       capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline(pos, mass, p, err_tol, n_leaf, workload):
+    """The CPU oracle, untuned, on this host: one full force evaluation of the
+    benchmark's workload (all stages, every body), plus the 4096-body
+    configuration (p = 6, epsilon = 1e-6) timed as the median of 3 runs with
+    all threads and with one thread."""
     import oracle
+    from paper_2012_02207_amd import workloads as W
     n = len(mass)
     o = oracle.Oracle()
     t0 = time.perf_counter()
-    o.run(pos, mass, p=p, err_tol=err_tol, n_leaf=n_leaf, stage="walk")
-    t_walk = time.perf_counter() - t0
-    nch, b, e, perm = o.get("cell_nchild"), o.get("cell_begin"), o.get("cell_end"), o.get("perm")
-    leaves = np.nonzero(nch == 0)[0]
-    rng = np.random.default_rng(seed)
-    picked = rng.choice(leaves, max(1, int(round(frac * len(leaves)))), replace=False)
-    mask = np.zeros(n, np.uint8)
-    for c in picked:
-        mask[perm[b[c]:e[c]]] = 1
-    t0 = time.perf_counter()
-    o.run(pos, mass, p=p, err_tol=err_tol, n_leaf=n_leaf, eval_mask=mask)
-    t_all = time.perf_counter() - t0
-    t_eval = max(t_all - t_walk, 0.0)
-    scale = len(leaves) / len(picked)
-    t_full = t_walk + t_eval * scale
+    o.run(pos, mass, p=p, err_tol=err_tol, n_leaf=n_leaf)
+    t_full = time.perf_counter() - t0
+    cfg = W.CONFIGS["plummer_4k"]
+    p4, _, m4 = W.plummer(cfg["n"], cfg["seed"])
+    o4 = oracle.Oracle()
+    o4.run(p4, m4, p=cfg["p"], err_tol=cfg["err_tol"], n_leaf=64)  # first touch
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        o4.run(p4, m4, p=cfg["p"], err_tol=cfg["err_tol"], n_leaf=64)
+        ts.append(time.perf_counter() - t0)
+    single = _oracle_c1_single_thread()
     return {"value": 1.0 / t_full, "unit": "force evals/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"N={n}: tree+upward+estimate+walk in full ({t_walk:.1f} s), evaluation of "
-                      f"{len(picked)} of {len(leaves)} random leaves ({t_eval:.1f} s) scaled "
-                      f"x{scale:.1f}; estimated {t_full:.1f} s per evaluation"}
+            "sample": f"one full oracle force evaluation of the {workload} workload (N={n}, p={p}, "
+                      f"eps={err_tol:g}, every stage and body): {t_full:.1f} s",
+            "host": {"nproc": os.cpu_count(), "cpu_model": _cpu_model(),
+                     "omp_threads": oracle.threads()},
+            "plummer_4k": {"median_of_3_s": float(np.median(ts)), "threads": oracle.threads(),
+                           "single_thread_median_of_3_s": single["median_s"] if single else None}}
 
 
 def run_ensemble(args):
@@ -167,14 +215,16 @@ def run_ensemble(args):
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-        st = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
             step()
-            if batched:
-                st.append(f.stats())
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
+        st = []
+        if batched:  # stage and kernel times from a second pass, a stats read after each call
+            for _ in range(args.steps):
+                step()
+                st.append(f.stats())
         med, p99 = errors(acc)
         f.close()
         return {"ms": 1e3 * dt, "cluster_evals_per_s": len(clusters) / dt, "particle_evals_per_s": n / dt,
@@ -372,7 +422,6 @@ def main():
     ap.add_argument("--n-leaf", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="ensemble: keep --n-leaf for batched forms")
-    ap.add_argument("--cpu-frac", type=float, default=1.0 / 64)
     ap.add_argument("--err-sinks", type=int, default=4096)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 5 times (calibrates byte counters)")
@@ -421,17 +470,27 @@ def main():
         for _ in range(args.warmup):
             f.forces(dpos, dmass, out=(acc, pot))
         torch.cuda.synchronize()
-        stage_ms = []
+        # timed region: back-to-back calls, nothing read in between
         t0 = time.perf_counter()
         for _ in range(args.steps):
             f.forces(dpos, dmass, out=(acc, pot))
-            stage_ms.append(f.stats())      # per-call HIP-event stage times (syncs the stream)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        # the same calls again, each followed by fmm_stats (a stream sync and
+        # read-back of the library's HIP events: stage times and the per-launch
+        # durations of the M2L and near-field kernels)
+        stage_ms = []
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            f.forces(dpos, dmass, out=(acc, pot))
+            stage_ms.append(f.stats())
+        torch.cuda.synchronize()
+        dt_inst = time.perf_counter() - t1
         a = acc[dsinks.long()]
         rel = (torch.linalg.norm(a - ad, dim=1) / torch.linalg.norm(ad, dim=1)).cpu().numpy()
         f.close()
-        return {"ms": 1e3 * dt / args.steps, "stages": stage_ms, "acc": acc, "rel": rel}
+        return {"ms": 1e3 * dt / args.steps, "ms_instrumented": 1e3 * dt_inst / args.steps,
+                "stages": stage_ms, "acc": acc, "rel": rel}
 
     res = {pr: run(pr) for pr in args.precisions}
     main_pr = args.precisions[-1]
@@ -483,6 +542,7 @@ def main():
     forms = {}
     for pr, r in res.items():
         forms[pr] = {"evals_per_s": 1e3 / r["ms"], "ms_per_eval": r["ms"],
+                     "ms_per_eval_with_stats_read": r["ms_instrumented"],
                      "median_err_vs_direct": float(np.median(r["rel"])),
                      "p99_err_vs_direct": float(np.percentile(r["rel"], 99))}
     if "fp64" in res and "mixed" in res:
@@ -520,7 +580,7 @@ def main():
         "kernels": other,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(pos, mass, p, err_tol, args.n_leaf, args.cpu_frac)
+        out["cpu_baseline"] = cpu_baseline(pos, mass, p, err_tol, args.n_leaf, args.workload)
     print(json.dumps(out))
 
 
