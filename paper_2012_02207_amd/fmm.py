@@ -175,6 +175,21 @@ class FMM:
         if st != FMM_OK:
             raise FmmError(st, self._lib.fmm_last_error(self._h).decode())
 
+    def set_params(self, **kw):
+        """Replaces parameters for later calls (fmm_set_params): any of p, err_tol,
+        theta, theta_est, n_leaf, precision ("fp64"/"mixed"/"direct"), mac,
+        check_inputs, root_levels."""
+        conv = {"precision": lambda v: PRECISION[v], "mac": lambda v: MAC[v],
+                "check_inputs": lambda v: int(bool(v))}
+        new = Params()
+        C.pointer(new)[0] = self.params
+        for k, v in kw.items():
+            if not hasattr(new, k):
+                raise ValueError(f"unknown parameter {k}")
+            setattr(new, k, conv.get(k, lambda x: x)(v))
+        self._check(self._lib.fmm_set_params(self._h, C.byref(new)))
+        self.params = new
+
     def set_workspace_limit(self, nbytes):
         self._check(self._lib.fmm_set_workspace_limit(self._h, int(nbytes)))
 
