@@ -11,6 +11,8 @@
 // mass; size = largest distance of a body from it (section 2.3, "sizes").
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <climits>
 #include <cmath>
 
 #include "fmm_device.h"
@@ -500,66 +502,137 @@ __device__ inline int octant_lower_bound(const uint64_t* key, int b, int e, int 
   return lo;
 }
 
-// children of every cell of one level: eight lanes per cell, lane o finding
-// the first body of octant o by its own binary search (the searches run side
-// by side instead of one after another); cells that stay leaves are counted in
-// *nleaf (one atomic per wavefront)
-__global__ void k_split_level(int first, int count, int level, int n_leaf, const uint64_t* key,
-                              const int* cb, const int* ce, int* split, int* nch, int* nleaf) {
-  int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int t = (int)(T >> 3), o = (int)(T & 7);
-  bool ok = t < count;  // the 8 lanes of a cell agree
-  int cnt = 0;
-  bool splits = false;
-  int bound = 0, e = 0;
-  if (ok) {
-    int c = first + t;
-    int b = cb[c];
-    e = ce[c];
-    splits = e - b > n_leaf && level < FMM_MAX_LEVEL;
-    if (splits) {
-      int shift = 3 * (FMM_MAX_LEVEL - (level + 1));
-      bound = o == 0 ? b : octant_lower_bound(key, b, e, o, shift);
-    }
+// ---- the level loop on the device -----------------------------------------
+// Level l's cells are [lvl[2l], lvl[2l] + lvl[2l+1]) (first id, count), kept on
+// the device: every launch of a level reads its count there and the emit of
+// level l writes level l + 1's entry, so the host enqueues a batch of levels
+// without waiting and reads the table once at the end.  The cell arrays have
+// a fixed capacity; a level whose children would not fit sets the overflow
+// flag and ends the tree (the host grows the arrays and builds again).
+constexpr int LV_T = 256, LV_NB = 256, LV_SPLIT_BLOCKS = 512;
+constexpr int LV_TABLE = 128, LV_OVERFLOW = 180;  // int offsets in the device counters
+
+__global__ void k_lv_init(int nsys, int* lvl, int* nleaf, int* overflow) {
+  int t = threadIdx.x;
+  if (t < 2 * (FMM_MAX_LEVEL + 2)) lvl[t] = t == 1 ? nsys : 0;
+  if (t == 0) {
+    *nleaf = 0;
+    *overflow = 0;
   }
-  // octant o spans [bound_o, bound_{o+1}); bound_8 = e
-  int next = __shfl_down(bound, 1, 8);
-  if (o == 7) next = e;
-  int nonempty = splits && next > bound ? 1 : 0;
-  cnt = nonempty;
-  for (int m = 1; m < 8; m <<= 1) cnt += __shfl_xor(cnt, m, 8);
-  if (ok && splits) {
-    split[9 * t + o] = bound;
-    if (o == 7) split[9 * t + 8] = e;
-  }
-  if (ok && o == 0) nch[t] = cnt;
-  unsigned long long leaves = __ballot(ok && o == 0 && cnt == 0);
-  if ((threadIdx.x & 63) == 0 && leaves) atomicAdd(nleaf, (int)__popcll(leaves));
 }
 
-__global__ void k_emit_children(int first, int count, int level, int next_first, const int* split,
-                                const int* nch, const int* choff, int* c_level, int* c_begin,
-                                int* c_end, int* c_parent, int* c_child0, int* c_nchild) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= count) return;
-  int c = first + t;
-  int k = nch[t];
-  c_nchild[c] = k;
-  if (k == 0) {
-    c_child0[c] = -1;
-    return;
-  }
-  int id = next_first + choff[t];
-  c_child0[c] = id;
-  for (int o = 0; o < 8; o++) {
-    int s0 = split[9 * t + o], s1 = split[9 * t + o + 1];
-    if (s1 > s0) {
-      c_level[id] = level + 1;
-      c_begin[id] = s0;
-      c_end[id] = s1;
-      c_parent[id] = c;
-      id++;
+// Children of every cell of the level: eight lanes per cell, lane o finding
+// the first body of octant o by its own binary search (the searches run side
+// by side instead of one after another); cells that stay leaves are counted in
+// *nleaf (one atomic per wavefront).  Grid-stride over the device count.
+__global__ void __launch_bounds__(LV_T) k_split_lv(int level, const int* lvl, int n_leaf, const uint64_t* key,
+                                                    const int* cb, const int* ce, int* split, int* nch,
+                                                    int* nleaf) {
+  int first = lvl[2 * level], count = lvl[2 * level + 1];
+  int64_t total = (int64_t)count * 8;
+  for (int64_t T0 = (int64_t)blockIdx.x * LV_T; T0 < total; T0 += (int64_t)gridDim.x * LV_T) {
+    int64_t T = T0 + threadIdx.x;
+    int t = (int)(T >> 3), o = (int)(T & 7);
+    bool ok = t < count;  // the 8 lanes of a cell agree
+    bool splits = false;
+    int bound = 0, e = 0;
+    if (ok) {
+      int c = first + t;
+      int b = cb[c];
+      e = ce[c];
+      splits = e - b > n_leaf && level < FMM_MAX_LEVEL;
+      if (splits) {
+        int shift = 3 * (FMM_MAX_LEVEL - (level + 1));
+        bound = o == 0 ? b : octant_lower_bound(key, b, e, o, shift);
+      }
     }
+    int next = __shfl_down(bound, 1, 8);
+    if (o == 7) next = e;
+    int cnt = splits && next > bound ? 1 : 0;
+    for (int m = 1; m < 8; m <<= 1) cnt += __shfl_xor(cnt, m, 8);
+    if (ok && splits) {
+      split[9 * (int64_t)t + o] = bound;
+      if (o == 7) split[9 * (int64_t)t + 8] = e;
+    }
+    if (ok && o == 0) nch[t] = cnt;
+    unsigned long long leaves = __ballot(ok && o == 0 && cnt == 0);
+    if ((threadIdx.x & 63) == 0 && leaves) atomicAdd(nleaf, (int)__popcll(leaves));
+  }
+}
+
+__device__ inline int block_sum(int v, int* sh) {
+  int tot;
+  block_excl_scan(v, sh, tot);
+  return tot;
+}
+
+// children counts of a level summed over LV_NB contiguous ranges
+__global__ void __launch_bounds__(LV_T) k_lv_bsum(int level, const int* lvl, const int* nch, int* bsum) {
+  __shared__ int sh[SCAN_T];
+  int count = lvl[2 * level + 1];
+  int chunk = (count + LV_NB - 1) / LV_NB;
+  int b0 = min(count, blockIdx.x * chunk), b1 = min(count, b0 + chunk);
+  int v = 0;
+  for (int t = b0 + threadIdx.x; t < b1; t += LV_T) v += nch[t];
+  int tot = block_sum(v, sh);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// child ids by a scan of the counts (the range's offset from the block sums),
+// then every cell's children, non-empty octants in octant order; block 0
+// records the next level
+__global__ void __launch_bounds__(LV_T) k_lv_emit(int level, int* lvl, const int* split, const int* nch,
+                                                   const int* bsum, int cap, int* overflow, int* c_level,
+                                                   int* c_begin, int* c_end, int* c_parent, int* c_child0,
+                                                   int* c_nchild) {
+  __shared__ int sh[SCAN_T];
+  int first = lvl[2 * level], count = lvl[2 * level + 1];
+  int next_first = first + count;
+  int chunk = (count + LV_NB - 1) / LV_NB;
+  int b0 = min(count, blockIdx.x * chunk), b1 = min(count, b0 + chunk);
+  int pre = 0, all = 0;
+  for (int k = threadIdx.x; k < LV_NB; k += LV_T) {
+    int v = bsum[k];
+    if (k < (int)blockIdx.x) pre += v;
+    all += v;
+  }
+  pre = block_sum(pre, sh);
+  all = block_sum(all, sh);
+  bool over = (int64_t)next_first + all > cap;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    int nxt = level + 1;
+    if (nxt <= FMM_MAX_LEVEL + 1) {
+      lvl[2 * nxt] = next_first;
+      lvl[2 * nxt + 1] = over ? 0 : all;
+    }
+    if (over) *overflow = 1;
+  }
+  for (int base = b0; base < b1; base += LV_T) {
+    int t = base + threadIdx.x;
+    int k = t < b1 ? nch[t] : 0;
+    int tile;
+    int ex = block_excl_scan(k, sh, tile);
+    if (t < b1) {
+      int c = first + t;
+      c_nchild[c] = over ? 0 : k;
+      if (k == 0 || over) {
+        c_child0[c] = -1;
+      } else {
+        int id = next_first + pre + ex;
+        c_child0[c] = id;
+        for (int o = 0; o < 8; o++) {
+          int s0 = split[9 * (int64_t)t + o], s1 = split[9 * (int64_t)t + o + 1];
+          if (s1 > s0) {
+            c_level[id] = level + 1;
+            c_begin[id] = s0;
+            c_end[id] = s1;
+            c_parent[id] = c;
+            id++;
+          }
+        }
+      }
+    }
+    pre += tile;
   }
 }
 
@@ -821,54 +894,64 @@ void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
                      c.sz.p, c.sm.p, c.pm.p);
   HIPCHK(hipGetLastError());
 
-  // breadth-first levels
+  // breadth-first levels, built on the device (see k_lv_emit)
   size_t cap = (size_t)std::max<int64_t>(1024, 4 * n / std::max(1, c.prm.n_leaf) + 64 + 2 * nsys);
-  auto ensure_cells = [&](size_t need, bool keep) {
-    ensure(c.ws, c.c_level, need, keep, s);
-    ensure(c.ws, c.c_begin, need, keep, s);
-    ensure(c.ws, c.c_end, need, keep, s);
-    ensure(c.ws, c.c_parent, need, keep, s);
-    ensure(c.ws, c.c_child0, need, keep, s);
-    ensure(c.ws, c.c_nchild, need, keep, s);
-  };
-  ensure_cells(cap, false);
-  hipLaunchKernelGGL(k_roots, grid1(nsys), dim3(256), 0, s, nsys, c.sys_off.p, c.c_level.p, c.c_begin.p,
-                     c.c_end.p, c.c_parent.p);
-  c.lvl_first.assign(1, 0);
-  c.lvl_count.assign(1, nsys);
-  int64_t total_cells = nsys;
+  cap = std::max(cap, c.c_level.cap);
   ensure(c.ws, c.counters, 512);  // the full size at once: counters[4..5] must outlive this call
-  long long* tot = (long long*)c.counters.p;
-  int* nleaf_dev = c.counters.p + 2;  // read back with the level totals
-  zero_fill(c, nleaf_dev, sizeof(int));
+  int* nleaf_dev = c.counters.p + 2;
+  int* lvl = c.counters.p + LV_TABLE;
+  int* overflow = c.counters.p + LV_OVERFLOW;
+  constexpr int NLV = FMM_MAX_LEVEL + 2;  // table entries: levels 0..21 and the empty one after
+  constexpr int FIRST_BATCH = 12;         // levels enqueued before the first read-back
   long long nleaf = 0;
-  for (int level = 0;; level++) {
-    int first = c.lvl_first[level], count = c.lvl_count[level];
-    ensure(c.ws, c.c_split, (size_t)count * 11 + 64);
-    int* split = c.c_split.p;
-    int* nch = split + (size_t)9 * count;
-    int* choff = nch + count;
-    hipLaunchKernelGGL(k_split_level, grid1((int64_t)count * 8), dim3(256), 0, s, first, count, level,
-                       c.prm.n_leaf, c.key[0].p, c.c_begin.p, c.c_end.p, split, nch, nleaf_dev);
-    HIPCHK(hipGetLastError());
-    exclusive_scan(c, nch, choff, count, tot);
-    // children of this level, and the leaves so far, in one read-back
-    HIPCHK(hipMemcpyAsync(c.hbuf, tot, 2 * sizeof(long long), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    long long next = c.hbuf[0];
-    nleaf = ((const int*)c.hbuf)[2];
-    if ((size_t)(total_cells + next) > c.c_level.cap) ensure_cells((size_t)(total_cells + next) * 2, true);
-    hipLaunchKernelGGL(k_emit_children, grid1(count), dim3(256), 0, s, first, count, level,
-                       (int)total_cells, split, nch, choff, c.c_level.p, c.c_begin.p, c.c_end.p,
-                       c.c_parent.p, c.c_child0.p, c.c_nchild.p);
-    HIPCHK(hipGetLastError());
-    if (next == 0) break;
-    c.lvl_first.push_back((int)total_cells);
-    c.lvl_count.push_back((int)next);
-    total_cells += next;
+  int depth = 0;
+  for (int attempt = 0;; attempt++) {
+    for (auto* b : {&c.c_level, &c.c_begin, &c.c_end, &c.c_parent, &c.c_child0, &c.c_nchild})
+      ensure(c.ws, *b, cap);
+    cap = std::min({c.c_level.cap, c.c_begin.cap, c.c_end.cap, c.c_parent.cap, c.c_child0.cap,
+                    c.c_nchild.cap, (size_t)INT_MAX / 16});
+    ensure(c.ws, c.c_split, 10 * cap + LV_NB + 64);
+    int* split = c.c_split.p;  // 9 octant bounds per cell of the level
+    int* nch = split + 9 * cap;
+    int* bsum = nch + cap;
+    hipLaunchKernelGGL(k_roots, grid1(nsys), dim3(256), 0, s, nsys, c.sys_off.p, c.c_level.p, c.c_begin.p,
+                       c.c_end.p, c.c_parent.p);
+    hipLaunchKernelGGL(k_lv_init, dim3(1), dim3(64), 0, s, nsys, lvl, nleaf_dev, overflow);
+    int* h = (int*)c.hbuf;  // read-back: the table, then the leaf count and the overflow flag
+    int level = 0;
+    bool more = true;
+    for (int batch_end = FIRST_BATCH; more; batch_end = NLV - 1) {
+      for (; level < batch_end; level++) {
+        hipLaunchKernelGGL(k_split_lv, dim3(LV_SPLIT_BLOCKS), dim3(LV_T), 0, s, level, lvl, c.prm.n_leaf,
+                           c.key[0].p, c.c_begin.p, c.c_end.p, split, nch, nleaf_dev);
+        hipLaunchKernelGGL(k_lv_bsum, dim3(LV_NB), dim3(LV_T), 0, s, level, lvl, nch, bsum);
+        hipLaunchKernelGGL(k_lv_emit, dim3(LV_NB), dim3(LV_T), 0, s, level, lvl, split, nch, bsum, (int)cap,
+                           overflow, c.c_level.p, c.c_begin.p, c.c_end.p, c.c_parent.p, c.c_child0.p,
+                           c.c_nchild.p);
+      }
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(h, lvl, 2 * NLV * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(h + 2 * NLV, nleaf_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(h + 2 * NLV + 1, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      more = level < NLV - 1 && h[2 * level + 1] > 0 && !h[2 * NLV + 1];
+    }
+    if (!h[2 * NLV + 1]) {
+      c.lvl_first.clear();
+      c.lvl_count.clear();
+      for (int l = 0; l < NLV && h[2 * l + 1] > 0; l++) {
+        c.lvl_first.push_back(h[2 * l]);
+        c.lvl_count.push_back(h[2 * l + 1]);
+      }
+      nleaf = h[2 * NLV];
+      depth = (int)c.lvl_first.size() - 1;
+      break;
+    }
+    if (attempt > 8) throw hip_error{hipErrorUnknown, "cell arrays did not converge"};
+    cap *= 2;  // a level did not fit: larger arrays, build again
   }
-  c.ncell = total_cells;
-  c.depth = (int)c.lvl_first.size() - 1;
+  c.ncell = (int64_t)c.lvl_first[depth] + c.lvl_count[depth];
+  c.depth = depth;
   int nc = (int)c.ncell;
 
   cell_moments(c, true);
