@@ -735,6 +735,8 @@ static void upward(orc_ctx* c) {
       orc_regular(p, c->com[3 * cc] - c->com[3 * q], c->com[3 * cc + 1] - c->com[3 * q + 1],
                   c->com[3 * cc + 2] - c->com[3 * q + 2], yr + ch * nc, yi + ch * nc);
     }
+    /* each child's shifted moments summed on their own (k, then l), then the
+     * children added in octant order */
     for (int n = 0; n <= p; n++)
       for (int m = 0; m <= n; m++) {
         double sr = 0.0, si = 0.0;
@@ -742,6 +744,7 @@ static void upward(orc_ctx* c) {
           int64_t cc = c->child0[q] + ch;
           const double* mre = c->mult + (size_t)cc * nc * 2;
           const double* mim = mre + nc;
+          double cr = 0.0, ci = 0.0;
           for (int k = 0; k <= n; k++)
             for (int l = -k; l <= k; l++) {
               int j = n - k, qq = m - l;
@@ -751,9 +754,11 @@ static void upward(orc_ctx* c) {
               cget(mre, mim, j, qq, &br, &bi);
               double tr = ar * br - ai * bi;
               double ti = ar * bi + ai * br;
-              sr = sr + tr;
-              si = si + ti;
+              cr = cr + tr;
+              ci = ci + ti;
             }
+          sr = sr + cr;
+          si = si + ci;
         }
         ore[CIDX(n, m)] = sr;
         oim[CIDX(n, m)] = si;

@@ -132,10 +132,15 @@ __global__ void __launch_bounds__(P2M_T) k_p2m(int p, const int* leaves, int nle
 // M2M, one workgroup per parent.  The children's harmonics Y_k^l(z_c - z_P)
 // and moments M_j^q are laid out in LDS for both signs of their order
 // (entry n(n+1) + m, m = -n..n, the negative orders from the stored ones by
-// the conjugate symmetry, exact), so that the sum of each parent coefficient
-// is a branch-free loop in the defining order: children in octant order,
-// then k, then l ascending; products rounded separately.
+// the conjugate symmetry, exact), so that every sum is a branch-free loop in
+// the defining order.  Each (child, coefficient) pair is a task: the child's
+// shifted moment summed over k, then l ascending, products rounded
+// separately; the parent's coefficient then adds its children's sums in
+// octant order.  A sum is at most p + 1 terms of one child long, not eight
+// children long, so the few parents of the top levels finish quickly.
 constexpr int M2M_T = 128;
+constexpr int M2M_ALL_CHILDREN_PMAX = 16;  // the eight-children layout up to this order
+constexpr int M2M_TASKS = (8 * ncoef(M2M_ALL_CHILDREN_PMAX) + M2M_T - 1) / M2M_T;
 
 __global__ void __launch_bounds__(M2M_T) k_m2m(int p, int first, int count, const int* c0,
                                                 const int* nch, const double* cx, const double* cy,
@@ -177,14 +182,19 @@ __global__ void __launch_bounds__(M2M_T) k_m2m(int p, int first, int count, cons
     Mx[u] = make_double2(a, bb);
   }
   __syncthreads();
-  double* out = mult + (size_t)c * nc * 2;
-  for (int u = t; u < nc; u += M2M_T) {
-    int n, m;
-    coef_nm(u, n, m);
-    double sr = 0.0, si = 0.0;
-    for (int j = 0; j < kn; j++) {
+  // per-child sums, held in registers until every task has read the tables
+  double pr[M2M_TASKS], pi[M2M_TASKS];
+#pragma unroll
+  for (int w = 0; w < M2M_TASKS; w++) {
+    pr[w] = pi[w] = 0.0;
+    int u = t + M2M_T * w;
+    if (u < kn * nc) {
+      int j = u / nc, q = u - j * nc;
+      int n, m;
+      coef_nm(q, n, m);
       const double2* Y = Yx + j * S;
       const double2* M = Mx + j * S;
+      double sr = 0.0, si = 0.0;
       for (int k = 0; k <= n; k++) {
         int jj = n - k;
         int lo = max(-k, m - jj), hi = min(k, m + jj);
@@ -200,19 +210,37 @@ __global__ void __launch_bounds__(M2M_T) k_m2m(int p, int first, int count, cons
           si = si + ti;
         }
       }
+      pr[w] = sr;
+      pi[w] = si;
     }
-    out[2 * u] = sr;
-    out[2 * u + 1] = si;
+  }
+  __syncthreads();
+  double2* part = Yx;  // [child][coefficient], over the harmonics
+#pragma unroll
+  for (int w = 0; w < M2M_TASKS; w++) {
+    int u = t + M2M_T * w;
+    if (u < kn * nc) part[u] = make_double2(pr[w], pi[w]);
+  }
+  __syncthreads();
+  double* out = mult + (size_t)c * nc * 2;
+  for (int q = t; q < nc; q += M2M_T) {
+    double sr = 0.0, si = 0.0;
+    for (int j = 0; j < kn; j++) {
+      double2 v = part[j * nc + q];
+      sr = sr + v.x;
+      si = si + v.y;
+    }
+    out[2 * q] = sr;
+    out[2 * q + 1] = si;
   }
 }
 
 size_t m2m_lds_bytes(int p) { return sizeof(double2) * 2 * 8 * (size_t)(p + 1) * (p + 1); }
 
 // The same M2M with one child at a time in LDS (harmonics and moments of that
-// child only), for the orders whose eight children do not fit: each lane
-// carries its coefficients' sums from child to child, so every sum runs in
-// the same order (children in octant order, then k, then l) and rounds
-// exactly as in k_m2m.
+// child only), for the orders whose eight children do not fit: each lane sums
+// a child's shifted moment (k, then l) and adds it to its running coefficient
+// child by child in octant order, so it rounds exactly as k_m2m.
 constexpr int M2M_SMAXK = (ncoef(FMM_TABLE_PMAX) + M2M_T - 1) / M2M_T;
 
 __global__ void __launch_bounds__(M2M_T) k_m2m_stream(int p, int first, int count, const int* c0,
@@ -259,7 +287,7 @@ __global__ void __launch_bounds__(M2M_T) k_m2m_stream(int p, int first, int coun
       if (u >= nc) break;
       int n, m;
       coef_nm(u, n, m);
-      double ar = sr[q], ai = si[q];
+      double ar = 0.0, ai = 0.0;  // this child's sum, added to the parent's below
       for (int k = 0; k <= n; k++) {
         int jj = n - k;
         int lo = max(-k, m - jj), hi = min(k, m + jj);
@@ -274,8 +302,8 @@ __global__ void __launch_bounds__(M2M_T) k_m2m_stream(int p, int first, int coun
           ai = ai + ti;
         }
       }
-      sr[q] = ar;
-      si[q] = ai;
+      sr[q] = sr[q] + ar;
+      si[q] = si[q] + ai;
     }
     __syncthreads();
   }
@@ -289,8 +317,6 @@ __global__ void __launch_bounds__(M2M_T) k_m2m_stream(int p, int first, int coun
   }
 }
 
-// the eight-children layout up to this order (74 KB of LDS at p = 16)
-constexpr int M2M_ALL_CHILDREN_PMAX = 16;
 
 // P_k = sqrt( (k!)^2 |M_k^0|^2 + sum_{m=1..k} 2 (k-m)!(k+m)! |M_k^m|^2 ), and the
 // product C(p, k) P_k used by the acceptance test

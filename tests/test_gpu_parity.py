@@ -257,10 +257,12 @@ def test_errors_of_the_other_entry_points(fmm):
 # Mixed precision keeps keys, tree, P2M/M2M, the estimate and the acceptance test
 # in FP64, so its interaction lists equal the FP64 ones.  Its forces are compared
 # with the FP64 oracle against a stated bound: median relative difference
-# <= 1e-6 (FP32 round-off of ~6e-8 per operation, amplified by the O(10)
-# operations per M2L coefficient and the cancellation in the force sum), and
-# the median error against the direct sum must stay below epsilon.
-MIXED_MEDIAN_BOUND = 1e-6
+# <= 1.5e-7 and 99th percentile <= 7.5e-7 (FP32 round-off of ~6e-8 per operation,
+# amplified by the O(10) operations per M2L coefficient and the cancellation in
+# the force sum; the observed medians on these inputs are 1.6e-8 .. 3.5e-8 and
+# the 99th percentiles 1.3e-7 .. 1.7e-7, so a regression of a few times fails),
+# and the median error against the direct sum must stay below epsilon.
+MIXED_MEDIAN_BOUND = 1.5e-7
 
 
 # root_levels = 22 (deeper than any tree): every M2L pair takes the FP64 path over
@@ -286,7 +288,7 @@ def test_mixed_precision_bounded_difference(fmm, root_levels):
     rel = np.linalg.norm(acc - oacc, axis=1) / np.linalg.norm(oacc, axis=1)
     relp = np.abs(pot - opot) / np.abs(opot)
     print(f"mixed vs FP64 oracle: median {np.median(rel):.2e} p99 {np.percentile(rel, 99):.2e}")
-    assert np.median(rel) <= MIXED_MEDIAN_BOUND and np.percentile(rel, 99) <= 20 * MIXED_MEDIAN_BOUND
+    assert np.median(rel) <= MIXED_MEDIAN_BOUND and np.percentile(rel, 99) <= 5 * MIXED_MEDIAN_BOUND
     assert np.median(relp) <= MIXED_MEDIAN_BOUND
     ad, _ = oracle.direct(pos, mass)
     err = np.linalg.norm(acc - ad, axis=1) / np.linalg.norm(ad, axis=1)
@@ -305,6 +307,7 @@ def test_mixed_orders(fmm, p):
     rel = np.linalg.norm(acc - oacc, axis=1) / np.linalg.norm(oacc, axis=1)
     print(f"mixed p={p} vs FP64 oracle: median {np.median(rel):.2e} p99 {np.percentile(rel, 99):.2e}")
     assert np.median(rel) <= MIXED_MEDIAN_BOUND, (p, np.median(rel))
+    assert np.percentile(rel, 99) <= 5 * MIXED_MEDIAN_BOUND, (p, np.percentile(rel, 99))
 
 
 def test_mixed_kroupa_mass_spectrum(fmm):
@@ -320,4 +323,4 @@ def test_mixed_kroupa_mass_spectrum(fmm):
     rel = np.linalg.norm(acc - oacc, axis=1) / np.linalg.norm(oacc, axis=1)
     assert np.all(np.isfinite(acc))
     print(f"mixed kroupa vs FP64 oracle: median {np.median(rel):.2e} p99 {np.percentile(rel, 99):.2e}")
-    assert np.median(rel) <= MIXED_MEDIAN_BOUND
+    assert np.median(rel) <= MIXED_MEDIAN_BOUND and np.percentile(rel, 99) <= 5 * MIXED_MEDIAN_BOUND

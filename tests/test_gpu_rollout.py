@@ -105,11 +105,13 @@ def test_frozen_forces_reproduce_and_differentiate(fmm):
         e = torch.zeros_like(P)
         e[k, d] = h
         fd = (L(P + e, M) - L(P - e, M)) / (2 * h)
-        assert abs(fd - gx[k, d]) <= 1e-5 * np.abs(gx).max() + 1e-4 * abs(fd), (k, d, fd, gx[k, d])
+        print(f"frozen x[{k},{d}]: fd {fd:.9e} adjoint {gx[k, d]:.9e} max|g| {np.abs(gx).max():.3e}", flush=True)
+        assert abs(fd - gx[k, d]) <= 1e-6 * np.abs(gx).max() + 1e-5 * abs(fd), (k, d, fd, gx[k, d])
     for k in rng.choice(4096, 4, replace=False):
         e = torch.zeros_like(M)
         e[k] = h * float(mass[k])
         fd = (L(P, M + e) - L(P, M - e)) / (2 * h * float(mass[k]))
+        print(f"frozen m[{k}]: fd {fd:.9e} adjoint {gm[k]:.9e} max|g| {np.abs(gm).max():.3e}", flush=True)
         assert abs(fd - gm[k]) <= 1e-5 * np.abs(gm).max() + 1e-4 * abs(fd), (k, fd, gm[k])
     f.close()
     g.close()
@@ -145,7 +147,8 @@ def test_rollout_gradient_matches_finite_differences(fmm):
         e[k, d] = h
         fd = (loss(P + e, M) - loss(P - e, M)) / (2 * h)
         print(f"x[{k},{d}]: fd {fd:.9e} adjoint {gx[k, d]:.9e}", flush=True)
-        assert abs(fd - gx[k, d]) <= 1e-5 * np.abs(gx).max() + 1e-4 * abs(fd), (k, d, fd, gx[k, d])
+        # observed: |fd - adjoint| <= 3.5e-10, relative 2e-7 at most
+        assert abs(fd - gx[k, d]) <= 1e-7 * np.abs(gx).max() + 1e-5 * abs(fd), (k, d, fd, gx[k, d])
     for k in rng.choice(n, 4, replace=False):
         e = torch.zeros_like(M)
         e[k] = h * float(mass[k])
