@@ -84,6 +84,27 @@ def measured_traffic(kernel, workload, precision):
     return nbytes if cur == sha else None
 
 
+SORT_PASSES = 8          # LSD passes of 8 bits over the 63-bit Morton keys
+SORT_BYTES = 24          # per body and pass: read key (8) + index (4), write both
+GATHER_BYTES = 36 + 64   # per body: read index, position, mass; write SoA x, y, z, m and packed (x, y, z, m)
+
+
+def hbm_rates(stages, n):
+    """Algorithmic HBM rates of the tree stage's bandwidth-bound passes: the
+    stable radix sort of the bodies' keys and the gather into sorted order,
+    from the library's HIP events around them (averaged over the calls)."""
+    out = {}
+    for name, per_body in (("body_sort", SORT_PASSES * SORT_BYTES), ("gather", GATHER_BYTES)):
+        key = "ms_sort" if name == "body_sort" else "ms_gather"
+        ms = float(np.mean([s[key] for s in stages]))
+        nbytes = per_body * n
+        rate = nbytes / (ms * 1e-3) if ms > 0 else 0.0
+        out[name] = {"bytes": nbytes, "bytes_per_body": per_body, "ms": ms, "GB/s": rate / 1e9,
+                     "frac": rate / PEAK_HBM}
+    out["peak_GB/s"] = PEAK_HBM / 1e9
+    return out
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -200,8 +221,10 @@ def run_ensemble(args):
         f = fmm.FMM(p=p, err_tol=err_tol, n_leaf=args.n_leaf, precision=precision,
                     root_levels=args.root_levels)
         tuned = None
-        if batched and not args.no_autotune:  # the batched forms run at the autotuner's n_leaf
-            tuned = f.autotune(dpos, dmass, off)
+        if batched and not args.no_autotune:  # the batched forms run at the autotuner's choices
+            f.autotune(dpos, dmass, off)
+            tuned = {"n_leaf": f.params.n_leaf, "m2l_waves": f.params.m2l_waves,
+                     "p2p_groups": f.params.p2p_groups}
         acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
         pot = torch.empty((n,), dtype=torch.float64, device=dev)
         outs = [(acc[off[i]:off[i + 1]], pot[off[i]:off[i + 1]]) for i in range(len(clusters))]
@@ -229,7 +252,7 @@ def run_ensemble(args):
         f.close()
         return {"ms": 1e3 * dt, "cluster_evals_per_s": len(clusters) / dt, "particle_evals_per_s": n / dt,
                 "median_err_vs_direct": med, "p99_err_vs_direct": p99,
-                "n_leaf": tuned if tuned is not None else args.n_leaf, "stats": st}
+                "n_leaf": tuned["n_leaf"] if tuned is not None else args.n_leaf, "tuned": tuned, "stats": st}
 
     res = {"batched_mixed": run("mixed", True), "batched_fp64": run("fp64", True),
            "sequential_fp64": run("fp64", False), "sequential_mixed": run("mixed", False)}
@@ -239,6 +262,8 @@ def run_ensemble(args):
         against the same sequence replayed as one captured HIP graph."""
         f = fmm.FMM(p=p, err_tol=err_tol, n_leaf=res["batched_mixed"]["n_leaf"], precision="mixed",
                     root_levels=args.root_levels)
+        if res["batched_mixed"]["tuned"] is not None:
+            f.set_params(**res["batched_mixed"]["tuned"])
         acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
         pot = torch.empty((n,), dtype=torch.float64, device=dev)
         f.forces_batch(dpos, dmass, off, out=(acc, pot))
@@ -572,12 +597,13 @@ def main():
                         "max": float(rel.max()), "sinks": int(len(sinks))},
         "forms": forms,
         "stages_ms": {k: round(float(np.mean([s[k] for s in R["stages"]])), 4)
-                      for k in ("ms_tree", "ms_upward", "ms_estimate", "ms_walk", "ms_m2l",
-                                "ms_local", "ms_p2p", "ms_total")},
+                      for k in ("ms_tree", "ms_sort", "ms_gather", "ms_upward", "ms_estimate", "ms_walk",
+                                "ms_walk_steps", "ms_m2l", "ms_local", "ms_p2p", "ms_total")},
         "counts": {k: int(st[k]) for k in ("ncell", "nleaf", "depth", "n_m2l", "n_p2p_cells",
                                            "n_p2p_pairs", "n_est_far", "n_est_near")},
         "roofline": roof,
         "kernels": other,
+        "hbm": hbm_rates(R["stages"], n),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pos, mass, p, err_tol, args.n_leaf, args.workload)

@@ -66,6 +66,10 @@ typedef struct {
   int mac;          /* fmm_mac                                                            */
   int check_inputs; /* 1: reject NaN/Inf positions, negative or NaN masses (FMM_EDATA)    */
   int root_levels;  /* mixed precision: M2L touching a cell above this level stays FP64 */
+  int m2l_waves;    /* mixed precision: wavefronts per sink in the FP32 M2L, 1, 2 or 4 (default 1);
+                       each takes a contiguous part of the sink's list, the parts added in order */
+  int p2p_groups;   /* near field: at most this many lane groups share a sink leaf's sources
+                       (0 = as many as the wavefront holds, the default; else 1..64) */
 } fmm_params;
 
 /* counts and times of the last call (filled by fmm_stats); times in ms between
@@ -91,6 +95,9 @@ typedef struct {
   size_t workspace_bytes; /* device memory held by the context            */
   int64_t nsys;           /* independent systems of the call (1 for fmm_forces) */
   double ms_m2l_kernel;   /* the main M2L kernel alone (FP32 kernel in mixed mode) */
+  double ms_sort;         /* the stable radix sort of the bodies' Morton keys (tree stage) */
+  double ms_gather;       /* the gather of positions and masses into sorted order (tree stage) */
+  double ms_walk_steps;   /* the acceptance walk alone, before its lists are grouped (walk stage) */
 } fmm_stats_t;
 
 /* export selectors for fmm_export (host buffer, element counts from fmm_stats) */
@@ -124,7 +131,8 @@ typedef enum {
 typedef struct fmm_ctx fmm_ctx;
 
 /* Defaults: p = 10, err_tol = 1e-7, theta = 1, theta_est = 1, n_leaf = 64,
- * precision = FMM_FP64, mac = FMM_MAC_ERROR, check_inputs = 0, root_levels = 3. */
+ * precision = FMM_FP64, mac = FMM_MAC_ERROR, check_inputs = 0, root_levels = 3,
+ * m2l_waves = 1, p2p_groups = 0. */
 void fmm_default_params(fmm_params* out /* host */);
 
 /* Creates a context on the current HIP device.  prm (host) may be NULL for the
@@ -133,6 +141,10 @@ fmm_status fmm_create(fmm_ctx** out, const fmm_params* prm);
 
 /* Replaces the parameters used by later calls (validated as in fmm_create). */
 fmm_status fmm_set_params(fmm_ctx* ctx, const fmm_params* prm);
+
+/* Copies the context's current parameters (after fmm_autotune, the tuned
+ * ones) into *out (host).  FMM_EINVAL for NULL arguments. */
+fmm_status fmm_get_params(fmm_ctx* ctx, fmm_params* out);
 
 /* Tree and upward pass only (keys, sort, cells, P2M, M2M, P_k): planning and
  * parity export.  Section 2.1 (octree, P2M at the leaves, M2M to the root),
@@ -253,16 +265,20 @@ fmm_status fmm_forces_batch(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets, 
                             const double* mass, double eps_soft, int p, double err_tol,
                             double* acc, double* pot, void* stream);
 
-/* Autotuner: picks the leaf capacity n_leaf (the balance between the near
- * field and the expansions) for this workload by timing full evaluations of
- * the systems given as for fmm_forces_batch (nsys = 1, offsets = {0, n} for a
- * single system) at n_leaf in {16, 24, 32, 48, 64, 96, 128}: one warm-up and
- * two timed calls each, HIP events on the stream.  The fastest is written to
- * *chosen_n_leaf (host) and set in the context's parameters.  Choices are
- * cached in the process per (device, precision, p, err_tol, log2 of the body
- * count, log2 of the mean system size); a cached workload class returns at
- * once without running anything.  acc and pot receive the last evaluation.
- * Errors as fmm_forces_batch; on error the parameters are unchanged. */
+/* Autotuner (NEXT: batched ensembles): picks, for this workload, the leaf
+ * capacity n_leaf (the balance between the near field and the expansions),
+ * then in mixed precision the FP32 M2L's wavefronts per sink (m2l_waves in
+ * {1, 2, 4}), then the near field's lane groups per sink leaf (p2p_groups in
+ * {0, 4, 2}), one parameter at a time at the best of the ones before, by
+ * timing full evaluations of the systems given as for fmm_forces_batch (nsys =
+ * 1, offsets = {0, n} for a single system): n_leaf in {16, 24, 32, 48, 64, 96,
+ * 128}, one warm-up and two timed calls each, HIP events on the stream.  The
+ * choices are set in the context's parameters (read them with fmm_get_params)
+ * and n_leaf is also written to *chosen_n_leaf (host).  They are cached in the
+ * process per (device, precision, p, err_tol, log2 of the body count, log2 of
+ * the mean system size); a cached workload class returns at once without
+ * running anything.  acc and pot receive the last evaluation.  Errors as
+ * fmm_forces_batch; on error the parameters are unchanged. */
 fmm_status fmm_autotune(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets, const double* pos,
                         const double* mass, double eps_soft, int p, double err_tol, double* acc,
                         double* pot, void* stream, int* chosen_n_leaf);

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -178,6 +179,8 @@ static fmm_status validate_params(const fmm_params* p) {
   if (p->precision < FMM_FP64 || p->precision > FMM_DIRECT) return FMM_EINVAL;
   if (p->mac != FMM_MAC_ERROR && p->mac != FMM_MAC_GEOMETRIC) return FMM_EINVAL;
   if (p->root_levels < 0 || p->root_levels > FMM_MAX_LEVEL + 1) return FMM_EINVAL;
+  if (p->m2l_waves != 1 && p->m2l_waves != 2 && p->m2l_waves != 4) return FMM_EINVAL;
+  if (p->p2p_groups < 0 || p->p2p_groups > 64) return FMM_EINVAL;
   return FMM_OK;
 }
 
@@ -216,6 +219,8 @@ void fmm_default_params(fmm_params* out) {
   out->mac = FMM_MAC_ERROR;
   out->check_inputs = 0;
   out->root_levels = 3;
+  out->m2l_waves = 1;
+  out->p2p_groups = 0;
 }
 
 fmm_status fmm_create(fmm_ctx** out, const fmm_params* prm) {
@@ -370,6 +375,7 @@ static fmm_status forces_on(fmm_ctx* ctx, Ctx& c, int64_t nsys, const int64_t* o
     HIPCHK(hipEventRecord(c.ev[0], c.stream));
     build_and_estimate(c, n, pos, mass);
     mac_walk(c);
+    HIPCHK(hipEventRecord(c.ev[18], c.stream));
     c.walked = true;
     evaluate(c, acc, pot, true);
     c.evaluated = true;
@@ -492,6 +498,9 @@ fmm_status fmm_stats(fmm_ctx* ctx, fmm_stats_t* out) {
         out->ms_p2p = el(6, 7);
         out->ms_total = el(0, 8);
         out->ms_m2l_kernel = el(9, 10);
+        out->ms_sort = el(15, 16);
+        out->ms_gather = el(16, 17);
+        out->ms_walk_steps = el(3, 18);
       } else {
         out->ms_upward = el(1, 2);
         out->ms_total = el(0, 2);
@@ -707,11 +716,15 @@ fmm_status fmm_jerk(fmm_ctx* ctx, int64_t n, const double* pos, const double* ve
   return st;
 }
 
-// ---- autotuner: n_leaf per (device, precision, p, tolerance, size class) ----
+// ---- autotuner: n_leaf, FP32 M2L wavefronts per sink and near-field lane
+// groups per (device, precision, p, tolerance, size class) ----
 namespace {
 using TuneKey = std::tuple<int, int, int, double, int, int>;
+struct TuneChoice {
+  int n_leaf, m2l_waves, p2p_groups;
+};
 std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tune_cache;
+std::map<TuneKey, TuneChoice> g_tune_cache;
 
 int size_class(int64_t v) {
   int c = 0;
@@ -733,19 +746,22 @@ fmm_status fmm_autotune(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets, cons
   Ctx& c = ctx->c;
   int64_t n = offsets[nsys];
   TuneKey key{c.device, c.prm.precision, p, err_tol, size_class(n), size_class(n / nsys)};
+  auto apply = [&](const TuneChoice& t) {
+    c.prm.n_leaf = t.n_leaf;
+    c.prm.m2l_waves = t.m2l_waves;
+    c.prm.p2p_groups = t.p2p_groups;
+    c.graph_valid = false;
+    *chosen_n_leaf = t.n_leaf;
+  };
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      c.prm.n_leaf = it->second;
-      *chosen_n_leaf = it->second;
+      apply(it->second);
       return FMM_OK;
     }
   }
-  static const int cand[] = {16, 24, 32, 48, 64, 96, 128};
   fmm_params saved = c.prm;
-  int best = saved.n_leaf;
-  float best_ms = 1e30f;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   fmm_status st = guarded(ctx, [&]() {
     HIPCHK(hipEventCreate(&e0));
@@ -753,39 +769,86 @@ fmm_status fmm_autotune(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets, cons
     return FMM_OK;
   });
   if (st != FMM_OK) return st;
-  for (int nl : cand) {
-    c.prm.n_leaf = nl;
-    st = forces_impl(ctx, nsys, offsets, n, pos, mass, eps_soft, p, err_tol, acc, pot, stream);  // warm-up
-    if (st != FMM_OK) break;
-    float ms = 0;
-    st = guarded(ctx, [&]() {
+  // one warm-up and two timed evaluations of a configuration; ms < 0 on error
+  auto timed = [&](const TuneChoice& t, float& ms) {
+    c.prm.n_leaf = t.n_leaf;
+    c.prm.m2l_waves = t.m2l_waves;
+    c.prm.p2p_groups = t.p2p_groups;
+    fmm_status s1 = forces_impl(ctx, nsys, offsets, n, pos, mass, eps_soft, p, err_tol, acc, pot, stream);
+    if (s1 != FMM_OK) return s1;
+    s1 = guarded(ctx, [&]() {
       HIPCHK(hipEventRecord(e0, (hipStream_t)stream));
       return FMM_OK;
     });
-    if (st != FMM_OK) break;
-    for (int r = 0; r < 2 && st == FMM_OK; r++)
-      st = forces_impl(ctx, nsys, offsets, n, pos, mass, eps_soft, p, err_tol, acc, pot, stream);
-    if (st != FMM_OK) break;
-    st = guarded(ctx, [&]() {
+    for (int r = 0; r < 2 && s1 == FMM_OK; r++)
+      s1 = forces_impl(ctx, nsys, offsets, n, pos, mass, eps_soft, p, err_tol, acc, pot, stream);
+    if (s1 != FMM_OK) return s1;
+    return guarded(ctx, [&]() {
       HIPCHK(hipEventRecord(e1, (hipStream_t)stream));
       HIPCHK(hipEventSynchronize(e1));
       HIPCHK(hipEventElapsedTime(&ms, e0, e1));
       return FMM_OK;
     });
-    if (st != FMM_OK) break;
+  };
+  // coordinate search: the leaf capacity first (it sets the balance of near
+  // and far field), then the FP32 M2L's wavefronts per sink (mixed precision
+  // only), then the near field's lane groups
+  TuneChoice best{saved.n_leaf, saved.m2l_waves, saved.p2p_groups};
+  float best_ms = 1e30f;
+  static const int cand_leaf[] = {16, 24, 32, 48, 64, 96, 128};
+  static const int cand_waves[] = {1, 2, 4};
+  static const int cand_groups[] = {0, 4, 2};
+  for (int nl : cand_leaf) {
+    TuneChoice t = best;
+    t.n_leaf = nl;
+    float ms = 0;
+    if ((st = timed(t, ms)) != FMM_OK) break;
     if (ms < best_ms) {
       best_ms = ms;
-      best = nl;
+      best = t;
+    }
+  }
+  if (st == FMM_OK && saved.precision == FMM_MIXED && mixed_supported(p)) {
+    TuneChoice base = best;
+    for (int w : cand_waves) {
+      if (w == base.m2l_waves) continue;
+      TuneChoice t = base;
+      t.m2l_waves = w;
+      float ms = 0;
+      if ((st = timed(t, ms)) != FMM_OK) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = t;
+      }
+    }
+  }
+  if (st == FMM_OK) {
+    TuneChoice base = best;
+    for (int g : cand_groups) {
+      if (g == base.p2p_groups) continue;
+      TuneChoice t = base;
+      t.p2p_groups = g;
+      float ms = 0;
+      if ((st = timed(t, ms)) != FMM_OK) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = t;
+      }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c.prm = saved;
   if (st != FMM_OK) return st;
-  c.prm.n_leaf = best;
-  *chosen_n_leaf = best;
+  apply(best);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune_cache[key] = best;
+  return FMM_OK;
+}
+
+fmm_status fmm_get_params(fmm_ctx* ctx, fmm_params* out) {
+  if (!ctx || !out) return FMM_EINVAL;
+  *out = ctx->c.prm;
   return FMM_OK;
 }
 

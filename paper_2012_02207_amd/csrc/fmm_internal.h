@@ -194,8 +194,10 @@ struct Ctx {
   // timing
   // timing events: stage boundaries 0..8 on the caller's stream; 9, 10 around
   // the main M2L kernel; 11..13 the local stage around the join with the
-  // near field; 14 the end of the upward pass on the side stream
-  hipEvent_t ev[16] = {};
+  // near field; 14 the end of the upward pass on the side stream; 15..17 the
+  // body sort (after the keys, after the sort, after the gather); 18 the end
+  // of the acceptance walk (before its lists are grouped)
+  hipEvent_t ev[19] = {};
   // second stream (default priority) for work independent of the caller's
   // stream: the upward pass beside the estimate walk, the near field beside
   // M2L and L2L; forked and joined with the events below

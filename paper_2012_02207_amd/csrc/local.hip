@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(64 * LG_WAVES) __attribute__((amdgpu_waves_per
                                                               const int* __restrict__ srcl,
                                                               const double4* __restrict__ pm,
                                                               double eps2, double4* nearbuf,
-                                                              unsigned long long* npairs) {
+                                                              unsigned long long* npairs, int gmax) {
   __shared__ double4 sbuf[LG_WAVES][64];
   __shared__ double rbuf[LG_WAVES][4][64];
   int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -243,6 +243,7 @@ __global__ void __launch_bounds__(64 * LG_WAVES) __attribute__((amdgpu_waves_per
   for (int i0 = b; i0 < e; i0 += 64) {
     int nB = min(64, e - i0);
     int G = 64 / nB;
+    if (gmax > 0 && G > gmax) G = gmax;  // fewer groups: longer runs per lane, fewer partial sums
     int g = lane / nB, s = lane - g * nB;
     bool act = g < G;
     int i = i0 + s;
@@ -367,12 +368,15 @@ void launch_near_field(Ctx& c) {
   int nblk = (int)((c.nleaf + LG_WAVES - 1) / LG_WAVES);
   unsigned grid = 8u * (unsigned)((nblk + 7) / 8);
   double e2 = c.eps_soft * c.eps_soft;
+  int gmax = c.prm.p2p_groups;
   if (c.prm.precision == FMM_MIXED)
     hipLaunchKernelGGL(k_leaf_group<true>, dim3(grid), dim3(64 * LG_WAVES), 0, c.stream, leaves, (int)c.nleaf,
-                       c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.pm.p, e2, c.nearbuf.p, npairs);
+                       c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.pm.p, e2, c.nearbuf.p, npairs,
+                       gmax);
   else
     hipLaunchKernelGGL(k_leaf_group<false>, dim3(grid), dim3(64 * LG_WAVES), 0, c.stream, leaves, (int)c.nleaf,
-                       c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.pm.p, e2, c.nearbuf.p, npairs);
+                       c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.pm.p, e2, c.nearbuf.p, npairs,
+                       gmax);
   HIPCHK(hipGetLastError());
 }
 

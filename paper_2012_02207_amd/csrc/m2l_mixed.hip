@@ -112,19 +112,32 @@ __device__ __forceinline__ void swap_apply(float* v, const lfloat* sw) {
   static_for<0, D>([&](auto ic) { v[ic] = out[ic]; });
 }
 
+// rotation about z: (C, S)_m <- (C cos ma - S sin ma, C sin ma + S cos ma),
+// with (cos ma, sin ma), m = 1..N, from tables built once per pair by the
+// angle-addition recurrence; sgn = -1 rotates by -a
 template <int N>
-__device__ __forceinline__ void zrot(float* v, float c1, float s1) {
-  float cm = c1, sm = s1;
+__device__ __forceinline__ void zrot_tab(float* v, const float* cm, const float* sm, float sgn) {
   static_for<1, N + 1>([&](auto mc) {
     constexpr int m = mc;
-    if constexpr (m > 1) {
-      float c2 = fmaf(cm, c1, -sm * s1);
-      sm = fmaf(sm, c1, cm * s1);
-      cm = c2;
-    }
+    float c = cm[m], sn = sgn * sm[m];
     float C = v[2 * m - 1], S = v[2 * m];
-    v[2 * m - 1] = fmaf(C, cm, -S * sm);
-    v[2 * m] = fmaf(C, sm, S * cm);
+    v[2 * m - 1] = fmaf(C, c, -S * sn);
+    v[2 * m] = fmaf(C, sn, S * c);
+  });
+}
+
+template <int P>
+__device__ __forceinline__ void angle_table(float c1, float s1, float* cm, float* sm) {
+  cm[0] = 1.f;
+  sm[0] = 0.f;
+  if constexpr (P >= 1) {
+    cm[1] = c1;
+    sm[1] = s1;
+  }
+  static_for<2, P + 1>([&](auto mc) {
+    constexpr int m = mc;
+    cm[m] = fmaf(cm[m - 1], c1, -sm[m - 1] * s1);
+    sm[m] = fmaf(sm[m - 1], c1, cm[m - 1] * s1);
   });
 }
 
@@ -149,11 +162,15 @@ __device__ __forceinline__ int split_point(const int* src, int b, int e, int fir
   return lo;
 }
 
-// One wavefront per sink, a source per lane.  Up to p = 10, three waves per
+// One wavefront per sink (or wps of them, each with a contiguous part of the
+// list), a source per lane.  Up to p = 10, three waves per
 // SIMD (at most 168 VGPRs); higher orders need more registers and take two
 // (p = 11, 12) or one.
 // The FP64 per-order sums live in LDS (a slot per lane), not in registers,
 // which would spill at that budget.
+// The angle multiples cos ma, sin ma of the two z-rotations come from tables
+// built once per pair (rebuilding them in every order's rotation cost ~13% of
+// the kernel's instructions at p = 10).
 template <int P>
 __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per_eu(P <= 10 ? 3 : P <= 12 ? 2 : 1))) k_m2l_fp32(int ncell, int first_lo,
                                                             const int* __restrict__ off,
@@ -163,7 +180,7 @@ __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per
                                                             const double* __restrict__ cz,
                                                             const double* __restrict__ scale,
                                                             const float* __restrict__ nmult,
-                                                            double* __restrict__ loc) {
+                                                            double* __restrict__ loc, int wps) {
   using namespace mx;
   constexpr int NC = ncoef(P);
   constexpr int NR = (P + 1) * (P + 1);
@@ -171,31 +188,48 @@ __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per
   __shared__ float swt[NSW];
   for (int t = threadIdx.x; t < NSW; t += 64 * MX_WAVES) swt[t] = c_cswap32[t];
   __syncthreads();
+  // wps wavefronts per sink: the sink's list, in batches of 64 sources, is
+  // split into wps contiguous parts; each wave sums its part, and the parts
+  // are added in order at the end (through LDS, one barrier)
+  int spb = MX_WAVES / wps;    // sinks per workgroup
   int nlo = ncell - first_lo;  // sinks below the root levels
-  int nblk = (nlo + MX_WAVES - 1) / MX_WAVES;
+  int nblk = (nlo + spb - 1) / spb;
   int per = (nblk + 7) >> 3;
   int blk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: B and its data in SGPRs
-  int B = first_lo + blk * MX_WAVES + wv;
-  if (blk >= nblk || B >= ncell) return;
-  int e = off[B + 1];
-  int b = split_point(src, off[B], e, first_lo);
+  int slot = wv / wps, part = wv - slot * wps;
+  int B = first_lo + blk * spb + slot;
+  if (wps == 1 && (blk >= nblk || B >= ncell)) return;  // (no barrier below for one wave per sink)
+  bool live = blk < nblk && B < ncell;
+  int b = 0, e = 0;
+  if (live) {
+    e = off[B + 1];
+    b = split_point(src, off[B], e, first_lo);
+  }
   int lane = threadIdx.x & 63;
-  if (b == e) {  // no FP32 pair: the sink's expansion starts at zero
+  if (wps == 1 && b == e) {  // no FP32 pair: the sink's expansion starts at zero
     for (int k = lane; k < NC * 2; k += 64) loc[(size_t)B * NC * 2 + k] = 0.0;
     return;
   }
+  int nbat = (e - b + 63) >> 6;
+  int pb = b + 64 * (nbat * part / wps), pe = min(e, b + 64 * (nbat * (part + 1) / wps));
   __shared__ double accs[MX_WAVES][P + 1][64];
   double* acc = &accs[wv][0][0] + lane;
 #pragma unroll
   for (int t = 0; t <= P; t++) acc[64 * t] = 0.0;
-  double bx = cx[B], by = cy[B], bz = cz[B], sB = scale[B];
+  double bx = 0.0, by = 0.0, bz = 0.0, sB = 1.0;
+  if (live) {
+    bx = cx[B];
+    by = cy[B];
+    bz = cz[B];
+    sB = scale[B];
+  }
   const lfloat* sw_it = (const lfloat*)swt;
 
-  for (int base = b; base < e; base += 64) {
+  for (int base = pb; base < pe; base += 64) {
     int k = base + lane;
-    bool act = k < e;
-    int A = act ? src[k] : src[b];
+    bool act = k < pe;
+    int A = act ? src[k] : src[pb];
     // geometry in FP64, rounded once
     double Rx = bx - cx[A], Ry = by - cy[A], Rz = bz - cz[A];
     double rho2 = Rx * Rx + Ry * Ry;
@@ -212,6 +246,11 @@ __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per
       sa = 1.f;
     }
     float cb = (float)(Rz * rinv), sb = (float)(-rho * rinv);
+    float tca[P + 1], tsa[P + 1], tcb[P + 1], tsb[P + 1];
+    angle_table<P>(ca, sa, tca, tsa);
+    angle_table<P>(cb, sb, tcb, tsb);
+    auto rotA = [&](auto nc, float* v, float sgn) { zrot_tab<decltype(nc)::value>(v, tca, tsa, sgn); };
+    auto rotB = [&](auto nc, float* v, float sgn) { zrot_tab<decltype(nc)::value>(v, tcb, tsb, sgn); };
     // an inactive lane (past the end of the list) gets zero factors, so all its
     // outputs are zero
     float tA = (float)(scale[A] * rinv), tB = (float)(sB * rinv), fr = act ? (float)rinv : 0.f;
@@ -238,9 +277,9 @@ __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per
       asm volatile("" : "+v"(Mo));
       float v[2 * kk + 1];
       static_for<0, 2 * kk + 1>([&](auto jc) { v[jc] = Mo[jc]; });
-      zrot<kk>(v, ca, sa);
+      rotA(kc, v, 1.f);
       swap_apply<kk>(v, sw);
-      zrot<kk>(v, cb, sb);
+      rotB(kc, v, 1.f);
       swap_apply<kk>(v, sw);
       // fold into the partial local expansion: orders n <= P - kk
       static_for<0, 2 * kk + 1>([&](auto jc) { v[jc] *= pA[kk]; });
@@ -268,9 +307,9 @@ __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per
       asm volatile("" : "+v"(Mo));
       float* v = Mp + n * n;
       static_for<0, 2 * n + 1>([&](auto jc) { v[jc] = Mo[jc]; });
-      zrot<n>(v, ca, sa);
+      rotA(nc, v, 1.f);
       swap_apply<n>(v, sw);
-      zrot<n>(v, cb, sb);
+      rotB(nc, v, 1.f);
       swap_apply<n>(v, sw);
       static_for<0, 2 * n + 1>([&](auto jc) { v[jc] *= pA[n]; });
     });
@@ -307,11 +346,19 @@ __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per
         }
       });
       swap_apply<n>(w, sw);
-      zrot<n>(w, cb, -sb);
+      rotB(nc, w, -1.f);
       swap_apply<n>(w, sw);
-      zrot<n>(w, ca, -sa);
+      rotA(nc, w, -1.f);
       reduce_lanes<2 * n + 1>(w, &acc[64 * n], lane);
     });
+  }
+  if (wps > 1) {
+    __syncthreads();  // every part's sums are in LDS
+    if (!live || part != 0) return;
+    if (b == e) {
+      for (int k = lane; k < NC * 2; k += 64) loc[(size_t)B * NC * 2 + k] = 0.0;
+      return;
+    }
   }
   // back to standard coefficients: L_n^0 = Lt n! / rho_B^n,
   // L_n^m = Lt sqrt((n-m)!(n+m)!/2) / rho_B^n; real-basis entry j of order n
@@ -326,7 +373,9 @@ __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per
       int m = (j + 1) >> 1;
       bool im = j > 0 && !(j & 1);
       double f = (m == 0 ? 1.0 : sqrt(0.5)) * sqrt(fmm_fact_dev(n - m) * fmm_fact_dev(n + m)) * pw;
-      out[2 * cidx(n, m) + (im ? 1 : 0)] = acc[64 * n] * f;
+      double t = acc[64 * n];
+      for (int k = 1; k < wps; k++) t += accs[wv + k][n][lane];  // the other parts, in order
+      out[2 * cidx(n, m) + (im ? 1 : 0)] = t * f;
       if (j == 0) out[2 * cidx(n, 0) + 1] = 0.0;
     }
     pw *= isB;
@@ -359,10 +408,13 @@ static void launch_p32(Ctx& c, int first_lo) {
   int nc = (int)c.ncell;
   int nlo = nc - first_lo;
   if (nlo <= 0) return;
-  int nblk = (nlo + MX_WAVES - 1) / MX_WAVES;
+  int wps = c.prm.m2l_waves;
+  int spb = MX_WAVES / wps;
+  int nblk = (nlo + spb - 1) / spb;
   unsigned grid = 8u * (unsigned)((nblk + 7) / 8);
   hipLaunchKernelGGL(k_m2l_fp32<P>, dim3(grid), dim3(64 * MX_WAVES), 0, c.stream, nc, first_lo,
-                     c.m2l.off.p, c.m2l.src.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.scale.p, c.nmult.p, c.loc.p);
+                     c.m2l.off.p, c.m2l.src.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.scale.p, c.nmult.p, c.loc.p,
+                     wps);
 }
 
 template <int P>

@@ -871,6 +871,7 @@ void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
   hipLaunchKernelGGL(k_keys, grid1(n), dim3(256), 0, s, pos, n, c.rootbox.p, c.sys_off.p, nsys,
                      c.key[0].p, c.idx[0].p);
   HIPCHK(hipGetLastError());
+  if (c.have_events) HIPCHK(hipEventRecord(c.ev[15], s));
   radix_sort_keys(c, n, 64);
   if (nsys > 1) {
     // stable pass over the system id: (system, key, caller index) order
@@ -890,9 +891,11 @@ void build_tree(Ctx& c, int64_t n, const double* pos, const double* mass) {
     std::swap(c.idx[0], c.idx[1]);
   }
   ensure(c.ws, c.pm, n);
+  if (c.have_events) HIPCHK(hipEventRecord(c.ev[16], s));
   hipLaunchKernelGGL(k_gather, grid1(n), dim3(256), 0, s, pos, mass, c.idx[0].p, n, c.sx.p, c.sy.p,
                      c.sz.p, c.sm.p, c.pm.p);
   HIPCHK(hipGetLastError());
+  if (c.have_events) HIPCHK(hipEventRecord(c.ev[17], s));
 
   // breadth-first levels, built on the device (see k_lv_emit)
   size_t cap = (size_t)std::max<int64_t>(1024, 4 * n / std::max(1, c.prm.n_leaf) + 64 + 2 * nsys);

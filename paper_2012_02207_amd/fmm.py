@@ -24,7 +24,7 @@ EXPORTS = dict(keys=(0, np.uint64), perm=(1, np.int32), cell_level=(2, np.int32)
                fmin=(15, np.float64), est_far=(16, np.int32), est_near=(17, np.int32),
                m2l=(18, np.int32), p2p=(19, np.int32), local=(20, np.float64),
                rootbox=(21, np.float64))
-SYMBOLS = ["fmm_default_params", "fmm_create", "fmm_set_params", "fmm_build", "fmm_forces",
+SYMBOLS = ["fmm_default_params", "fmm_create", "fmm_set_params", "fmm_get_params", "fmm_build", "fmm_forces",
            "fmm_forces_noalloc", "fmm_forces_batch", "fmm_forces_frozen",
            "fmm_forces_frozen_graph", "fmm_autotune", "fmm_adjoint", "fmm_jerk",
            "fmm_stats", "fmm_export", "fmm_set_workspace_limit",
@@ -43,7 +43,8 @@ class FmmError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("p", C.c_int), ("err_tol", C.c_double), ("theta", C.c_double),
                 ("theta_est", C.c_double), ("n_leaf", C.c_int), ("precision", C.c_int),
-                ("mac", C.c_int), ("check_inputs", C.c_int), ("root_levels", C.c_int)]
+                ("mac", C.c_int), ("check_inputs", C.c_int), ("root_levels", C.c_int),
+                ("m2l_waves", C.c_int), ("p2p_groups", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -53,7 +54,8 @@ class Stats(C.Structure):
                 ("ms_tree", C.c_double), ("ms_upward", C.c_double), ("ms_estimate", C.c_double),
                 ("ms_walk", C.c_double), ("ms_m2l", C.c_double), ("ms_local", C.c_double),
                 ("ms_p2p", C.c_double), ("ms_total", C.c_double), ("workspace_bytes", C.c_size_t),
-                ("nsys", C.c_int64), ("ms_m2l_kernel", C.c_double)]
+                ("nsys", C.c_int64), ("ms_m2l_kernel", C.c_double), ("ms_sort", C.c_double),
+                ("ms_gather", C.c_double), ("ms_walk_steps", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -74,6 +76,7 @@ def load_library():
     lib.fmm_default_params.argtypes = [C.POINTER(Params)]
     lib.fmm_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(Params)]
     lib.fmm_set_params.argtypes = [P, C.POINTER(Params)]
+    lib.fmm_get_params.argtypes = [P, C.POINTER(Params)]
     lib.fmm_build.argtypes = [P, C.c_int64, P, P, P]
     lib.fmm_forces.argtypes = [P, C.c_int64, P, P, C.c_double, C.c_int, C.c_double, P, P, P]
     lib.fmm_forces_noalloc.argtypes = [P, C.c_int64, P, P, C.c_double, C.c_int, C.c_double, P, P, P]
@@ -94,7 +97,7 @@ def load_library():
     lib.fmm_last_error.argtypes = [P]
     lib.fmm_last_error.restype = C.c_char_p
     lib.fmm_destroy.argtypes = [P]
-    for f in ("fmm_create", "fmm_set_params", "fmm_build", "fmm_forces", "fmm_forces_noalloc", "fmm_forces_batch",
+    for f in ("fmm_create", "fmm_set_params", "fmm_get_params", "fmm_build", "fmm_forces", "fmm_forces_noalloc", "fmm_forces_batch",
               "fmm_forces_frozen", "fmm_forces_frozen_graph", "fmm_autotune", "fmm_adjoint", "fmm_jerk", "fmm_stats", "fmm_export", "fmm_set_workspace_limit",
               "fmm_direct"):
         getattr(lib, f).restype = C.c_int
@@ -144,7 +147,7 @@ class FMM:
     """A force-evaluation context (owns the device workspace)."""
 
     def __init__(self, p=10, err_tol=1e-7, theta=1.0, theta_est=1.0, n_leaf=64, precision="fp64",
-                 mac="error", check_inputs=False, root_levels=3):
+                 mac="error", check_inputs=False, root_levels=3, m2l_waves=1, p2p_groups=0):
         lib = load_library()
         _torch()
         self._lib = lib
@@ -153,6 +156,7 @@ class FMM:
         self.params.theta_est, self.params.n_leaf = float(theta_est), int(n_leaf)
         self.params.precision, self.params.mac = PRECISION[precision], MAC[mac]
         self.params.check_inputs, self.params.root_levels = int(bool(check_inputs)), int(root_levels)
+        self.params.m2l_waves, self.params.p2p_groups = int(m2l_waves), int(p2p_groups)
         h = C.c_void_p()
         st = lib.fmm_create(C.byref(h), C.byref(self.params))
         if st != FMM_OK:
@@ -178,7 +182,7 @@ class FMM:
     def set_params(self, **kw):
         """Replaces parameters for later calls (fmm_set_params): any of p, err_tol,
         theta, theta_est, n_leaf, precision ("fp64"/"mixed"/"direct"), mac,
-        check_inputs, root_levels."""
+        check_inputs, root_levels, m2l_waves, p2p_groups."""
         conv = {"precision": lambda v: PRECISION[v], "mac": lambda v: MAC[v],
                 "check_inputs": lambda v: int(bool(v))}
         new = Params()
@@ -250,8 +254,10 @@ class FMM:
         return acc, pot
 
     def autotune(self, pos, mass, offsets=None, eps_soft=0.0, p=None, err_tol=None):
-        """Picks n_leaf for this workload (timed on the GPU, cached per workload
-        class in the process); returns the choice, also set in the context."""
+        """Picks n_leaf, then (mixed precision) the FP32 M2L's wavefronts per
+        sink, then the near field's lane groups for this workload (timed on the
+        GPU, cached per workload class in the process); returns n_leaf.  All
+        choices are set in the context and read back into self.params."""
         torch = _torch()
         n = mass.shape[0]
         off = np.ascontiguousarray(np.asarray([0, n] if offsets is None else offsets, dtype=np.int64))
@@ -265,8 +271,14 @@ class FMM:
             float(self.params.err_tol if err_tol is None else err_tol),
             _dev_ptr(acc, torch.float64, (n, 3), "acc"), _dev_ptr(pot, torch.float64, (n,), "pot"),
             _stream(), C.byref(chosen)))
-        self.params.n_leaf = chosen.value
+        self.params = self.get_params()
         return chosen.value
+
+    def get_params(self):
+        """The context's current parameters (fmm_get_params), as a Params struct."""
+        out = Params()
+        self._check(self._lib.fmm_get_params(self._h, C.byref(out)))
+        return out
 
     def forces_frozen(self, pos, mass, eps_soft=0.0, out=None, graph=False):
         """Forces with the tree and lists of the last evaluation kept (see fmm_forces_frozen);

@@ -181,6 +181,8 @@ def test_autotune_picks_a_candidate_and_caches(fmm):
     t0 = time.perf_counter()
     assert f.autotune(_dev(pos), _dev(mass), off) == nl
     assert time.perf_counter() - t0 < 0.5
+    prm = f.get_params()
+    assert prm.n_leaf == nl and prm.m2l_waves == 1 and prm.p2p_groups in (0, 4, 2)
     acc, _ = f.forces_batch(_dev(pos), _dev(mass), off)
     acc = acc.cpu().numpy()
     s = 5  # the 3000-body Plummer system
@@ -189,4 +191,27 @@ def test_autotune_picks_a_candidate_and_caches(fmm):
     oacc, _ = o.run(systems[s][0], systems[s][1], p=6, err_tol=1e-6, n_leaf=nl)
     rel = np.linalg.norm(acc[b:e] - oacc, axis=1) / np.linalg.norm(oacc, axis=1)
     assert np.median(rel) <= 1e-12 and rel.max() <= 1e-9
+    f.close()
+
+
+def test_autotune_mixed_picks_every_knob(fmm):
+    """In mixed precision the autotuner also picks the FP32 M2L's wavefronts
+    per sink and the near field's lane groups; the tuned batch stays within
+    the mixed bound of the per-system oracle."""
+    systems = _systems()
+    pos, mass, off = _concat(systems)
+    print("[gpu] autotune, mixed precision", flush=True)
+    f = fmm.FMM(p=6, err_tol=1e-6, n_leaf=64, precision="mixed", root_levels=2)
+    nl = f.autotune(_dev(pos), _dev(mass), off)
+    prm = f.get_params()
+    assert prm.n_leaf == nl and prm.m2l_waves in (1, 2, 4) and prm.p2p_groups in (0, 4, 2)
+    assert f.params.m2l_waves == prm.m2l_waves
+    acc, _ = f.forces_batch(_dev(pos), _dev(mass), off)
+    acc = acc.cpu().numpy()
+    s = 5
+    b, e = off[s], off[s + 1]
+    o = oracle.Oracle()
+    oacc, _ = o.run(systems[s][0], systems[s][1], p=6, err_tol=1e-6, n_leaf=nl)
+    rel = np.linalg.norm(acc[b:e] - oacc, axis=1) / np.linalg.norm(oacc, axis=1)
+    assert np.median(rel) <= 1.5e-7
     f.close()
