@@ -394,7 +394,9 @@ __global__ void k_normalize32(int p, int ncell, const double* mult, const double
   bool im = jj > 0 && !(jj & 1);
   double g = m == 0 ? fmm_fact_dev(n) : sqrt(2.0 * fmm_fact_dev(n - m) * fmm_fact_dev(n + m));
   double v = mult[(size_t)c * ncoef(p) * 2 + 2 * cidx(n, m) + (im ? 1 : 0)];
-  nmult[t] = (float)(v * g * pow(scale[c], -(double)n));
+  double is = 1.0 / scale[c], pw = 1.0;  // scale^-n by repeated products (as on the local side)
+  for (int k = 0; k < n; k++) pw *= is;
+  nmult[t] = (float)(v * g * pw);
 }
 
 // expansion scale per cell: its radius, or 1 for a point-like cell
