@@ -254,7 +254,6 @@ fmm_status fmm_create(fmm_ctx** out, const fmm_params* prm) {
     // containers sized so that its calls do not grow them
     upload_up_tables();
     upload_m2l_tables();
-    upload_mx_tables();
     upload_hi_tables();
     Ctx& na = *ctx->na;
     na.ws.arena = (char*)scratch_address(na.device);

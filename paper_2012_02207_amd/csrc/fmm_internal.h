@@ -275,7 +275,6 @@ void launch_m2l_fp64(Ctx& c);
 // constant tables of the kernels, uploaded once per device at context creation
 void upload_up_tables();
 void upload_m2l_tables();
-void upload_mx_tables();
 void upload_hi_tables();
 // generic-order FP64 M2L (any p <= 30; m2l_hi.hip), over every sink or the listed ones
 void launch_m2l_hi(Ctx& c, int first_lo, const double* mult, double* loc, const int* sinks, const int* nsinks);

@@ -28,9 +28,7 @@
 namespace fmm {
 
 constexpr int swoff(int n) { return n * (4 * n * n - 1) / 3; }
-constexpr int SWAP_DOUBLES = swoff(FMM_GPU_PMAX + 1);
 
-static __constant__ double c_cswap[8192];
 static __constant__ double c_fact_m2l[2 * FMM_GPU_PMAX + 2];
 static bool g_m2l_tables[64] = {};  // per device
 
@@ -55,44 +53,19 @@ constexpr bool swap_nz(int n, int i, int j) {
   return rb_re(i) == rb_re(j) && (((rb_m(i) + rb_m(j) + n) & 1) == (rb_re(i) ? 0 : 1));
 }
 
-// v (order-n slice, 2n+1 values) <- W_n v
-// Compacted swap table: only the structural non-zeros, row by row, order by
-// order, so that each row's coefficients are contiguous.
-constexpr int swap_nnz_row(int n, int i) {
-  int c = 0;
-  for (int j = 0; j < 2 * n + 1; j++) c += swap_nz(n, i, j) ? 1 : 0;
-  return c;
-}
-constexpr int swap_nnz(int n) {
-  int c = 0;
-  for (int i = 0; i < 2 * n + 1; i++) c += swap_nnz_row(n, i);
-  return c;
-}
-constexpr int cswoff(int n) {  // offset of order n in the compacted table
-  int c = 0;
-  for (int k = 0; k < n; k++) c += swap_nnz(k);
-  return c;
-}
-constexpr int crowoff(int n, int i) {
-  int c = cswoff(n);
-  for (int r = 0; r < i; r++) c += swap_nnz_row(n, r);
-  return c;
-}
-constexpr int CSWAP_DOUBLES = cswoff(FMM_GPU_PMAX + 1);
-
+// position of entry j among the structural non-zeros of row i of W_n (the
+// first one starts each row's sum)
 constexpr int crank(int n, int i, int j) {
   int c = 0;
   for (int t = 0; t < j; t++) c += swap_nz(n, i, t) ? 1 : 0;
   return c;
 }
 
-// LDS pointer type (reads through it are ds_read)
-typedef __attribute__((address_space(3))) double ldouble;
-
-// v (order-n slice, 2n+1 values) <- W_n v, coefficients from the compacted
-// table in LDS (wave-uniform addresses: broadcast reads)
+// v (order-n slice, 2n+1 values) <- W_n v.  The structural non-zeros are
+// compile-time constants (dyadic rationals, most of them exact as the 32-bit
+// literal operand of v_fmac_f64), so no product loads its matrix entry.
 template <int N, class T>
-__device__ __forceinline__ void swap_apply(T* v, const ldouble* sw) {
+__device__ __forceinline__ void swap_apply(T* v) {
   constexpr int D = 2 * N + 1;
   T out[D];
   static_for<0, D>([&](auto ic) {
@@ -101,8 +74,8 @@ __device__ __forceinline__ void swap_apply(T* v, const ldouble* sw) {
     static_for<0, D>([&](auto jc) {
       constexpr int j = jc;
       if constexpr (swap_nz(N, i, j)) {
-        constexpr int q = crowoff(N, i) + crank(N, i, j);
-        T w = (T)sw[q];
+        constexpr double wc = fmm_swap_table[swoff(N) + i * (2 * N + 1) + j];
+        T w = (T)wc;
         if constexpr (crank(N, i, j) == 0)
           s = w * v[j];
         else
@@ -146,7 +119,7 @@ __device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, con
                                               const int* __restrict__ src, const double* __restrict__ cx,
                                               const double* __restrict__ cy, const double* __restrict__ cz,
                                               const double* __restrict__ mult, double* __restrict__ loc,
-                                              const ldouble* swt, double* acc) {
+                                              double* acc) {
   constexpr int NC = ncoef(P);
   int b = off[B], e = off[B + 1];
   if (B >= first_lo) {
@@ -203,10 +176,6 @@ __device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, con
       }
     }
     const double* M = mult + (size_t)A * NC * 2;
-    // An opaque view of the LDS swap table per iteration: without it the
-    // compiler hoists every (loop-invariant) coefficient read out of the
-    // source loop and spills them.
-    const ldouble* sw_it = swt;
     // Source orders k >= K0 reach only output orders n <= P - k < K0: rotate
     // them first and fold them at once into a partial local expansion Lp
     // (orders 0..P-K0), so that only the low orders of the rotated multipole
@@ -219,10 +188,6 @@ __device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, con
     static_for<K0, P + 1>([&](auto kc) {
       constexpr int kk = kc;
       __builtin_amdgcn_sched_barrier(0);
-      // fresh coefficient reads per order block: shared reads between blocks
-      // would keep the coefficients live (and spilled) in between
-      const ldouble* sw = sw_it;
-      asm volatile("" : "+v"(sw));
       double v[2 * kk + 1];
       // an opaque per-order pointer keeps the loads of this order from being
       // merged with (and hoisted along with) those of other orders
@@ -235,9 +200,9 @@ __device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, con
         v[2 * m] = Mo[2 * m + 1];
       });
       zrot<kk>(v, ca, sa);
-      swap_apply<kk>(v, sw);
+      swap_apply<kk>(v);
       zrot<kk>(v, cb, sb);
-      swap_apply<kk>(v, sw);
+      swap_apply<kk>(v);
       static_for<0, P - kk + 1>([&](auto nc) {
         constexpr int n = nc;
         static_for<0, (n < kk ? n : kk) + 1>([&](auto mc) {
@@ -256,8 +221,6 @@ __device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, con
     static_for<0, K0>([&](auto nc) {
       constexpr int n = nc;
       __builtin_amdgcn_sched_barrier(0);
-      const ldouble* sw = sw_it;
-      asm volatile("" : "+v"(sw));
       double* v = Mp + n * n;
       const double* Mo = M + 2 * cidx(n, 0);
       asm volatile("" : "+v"(Mo));
@@ -268,16 +231,14 @@ __device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, con
         v[2 * m] = Mo[2 * m + 1];
       });
       zrot<n>(v, ca, sa);
-      swap_apply<n>(v, sw);
+      swap_apply<n>(v);
       zrot<n>(v, cb, sb);
-      swap_apply<n>(v, sw);
+      swap_apply<n>(v);
     });
     // complete the translation, rotate back and reduce, one output order at a time
     static_for<0, P + 1>([&](auto nc) {
       constexpr int n = nc;
       __builtin_amdgcn_sched_barrier(0);
-      const ldouble* sw = sw_it;
-      asm volatile("" : "+v"(sw));
       double w[2 * n + 1];
       static_for<0, n + 1>([&](auto mc) {
         constexpr int m = mc;
@@ -305,9 +266,9 @@ __device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, con
           w[2 * m] = 0.0;
         }
       });
-      swap_apply<n>(w, sw);
+      swap_apply<n>(w);
       zrot<n>(w, cb, -sb);
-      swap_apply<n>(w, sw);
+      swap_apply<n>(w);
       zrot<n>(w, ca, -sa);
       reduce_lanes<2 * n + 1>(w, &acc[64 * n], lane);
     });
@@ -347,24 +308,20 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) __attribute__((amdgpu_waves_pe
                                                              const double* __restrict__ cz,
                                                              const double* __restrict__ mult,
                                                              double* __restrict__ loc) {
-  constexpr int NSW = cswoff(P + 1);
-  __shared__ double swt[NSW];
-  for (int t = threadIdx.x; t < NSW; t += 64 * M2L_WAVES) swt[t] = c_cswap[t];
-  __syncthreads();
   int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   __shared__ double accs[M2L_WAVES][P + 1][64];
   double* acc = &accs[wv][0][0] + lane;
   if constexpr (LIST) {
     int cnt = *nsinks;
     for (int it = blockIdx.x * M2L_WAVES + wv; it < cnt; it += gridDim.x * M2L_WAVES)
-      m2l_sink_fp64<P>(sinks[it], first_lo, lane, off, src, cx, cy, cz, mult, loc, (const ldouble*)swt, acc);
+      m2l_sink_fp64<P>(sinks[it], first_lo, lane, off, src, cx, cy, cz, mult, loc, acc);
   } else {
     int nblk = (ncell + M2L_WAVES - 1) / M2L_WAVES;
     int per = (nblk + 7) >> 3;
     int blk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     int B = blk * M2L_WAVES + wv;
     if (blk < nblk && B < ncell)
-      m2l_sink_fp64<P>(B, first_lo, lane, off, src, cx, cy, cz, mult, loc, (const ldouble*)swt, acc);
+      m2l_sink_fp64<P>(B, first_lo, lane, off, src, cx, cy, cz, mult, loc, acc);
   }
 }
 
@@ -420,14 +377,6 @@ static bool& m2l_tables_flag() {
 void upload_m2l_tables() {
   bool& done = m2l_tables_flag();
   if (done) return;
-  // compact the dense tables to their structural non-zeros (row-major)
-  static_assert(CSWAP_DOUBLES <= 8192, "compacted swap table");
-  std::vector<double> cs;
-  for (int n = 0; n <= FMM_GPU_PMAX; n++)
-    for (int i = 0; i < 2 * n + 1; i++)
-      for (int j = 0; j < 2 * n + 1; j++)
-        if (swap_nz(n, i, j)) cs.push_back(fmm_swap_table[swoff(n) + i * (2 * n + 1) + j]);
-  HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_cswap), cs.data(), sizeof(double) * cs.size()));
   HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_fact_m2l), fmm_fact_table, sizeof(double) * (2 * FMM_GPU_PMAX + 2)));
   done = true;
 }

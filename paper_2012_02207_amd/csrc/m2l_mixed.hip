@@ -44,26 +44,6 @@ constexpr bool rb_re(int j) { return j == 0 || (j & 1); }
 constexpr bool swap_nz(int n, int i, int j) {
   return rb_re(i) == rb_re(j) && (((rb_m(i) + rb_m(j) + n) & 1) == (rb_re(i) ? 0 : 1));
 }
-constexpr int swap_nnz_row(int n, int i) {
-  int c = 0;
-  for (int j = 0; j < 2 * n + 1; j++) c += swap_nz(n, i, j) ? 1 : 0;
-  return c;
-}
-constexpr int swap_nnz(int n) {
-  int c = 0;
-  for (int i = 0; i < 2 * n + 1; i++) c += swap_nnz_row(n, i);
-  return c;
-}
-constexpr int cswoff(int n) {
-  int c = 0;
-  for (int k = 0; k < n; k++) c += swap_nnz(k);
-  return c;
-}
-constexpr int crowoff(int n, int i) {
-  int c = cswoff(n);
-  for (int r = 0; r < i; r++) c += swap_nnz_row(n, r);
-  return c;
-}
 constexpr int crank(int n, int i, int j) {
   int c = 0;
   for (int t = 0; t < j; t++) c += swap_nz(n, i, t) ? 1 : 0;
@@ -78,19 +58,37 @@ constexpr double csqrt_newton(double x) {
   for (int i = 0; i < 200; i++) r = 0.5 * (r + x / r);
   return r;
 }
-constexpr double gnorm(int n, int m) {
+constexpr double gnorm_eval(int n, int m) {
   return m == 0 ? cfact(n) : csqrt_newton(2.0 * cfact(n - m) * cfact(n + m));
 }
+// evaluated once per translation unit (the swap and translation constants of
+// every kernel read it at compile time)
+struct GnormTable {
+  double v[FMM_GPU_PMAX + 1][FMM_GPU_PMAX + 1];
+};
+constexpr GnormTable make_gnorm_table() {
+  GnormTable t{};
+  for (int n = 0; n <= FMM_GPU_PMAX; n++)
+    for (int m = 0; m <= n; m++) t.v[n][m] = gnorm_eval(n, m);
+  return t;
+}
+inline constexpr GnormTable kGnorm = make_gnorm_table();
+constexpr double gnorm(int n, int m) { return kGnorm.v[n][m]; }
 // translation constant T(n, k, m)
 constexpr double tconst(int n, int k, int m) {
   double s = ((n + m) & 1) ? -1.0 : 1.0;
   return s * cfact(n + k) * gnorm(n, m) / (cfact(n - m) * cfact(n + m) * gnorm(k, m));
 }
 
-typedef __attribute__((address_space(3))) float lfloat;
+// entry (i, j) of the orthogonal swap matrix G W_n G^-1 in FP32 (structural
+// non-zeros only are used): a compile-time constant, so every product takes
+// its matrix entry as an instruction operand instead of a load
+constexpr float swap_w32(int n, int i, int j) {
+  return (float)(fmm_swap_table[swoff(n) + i * (2 * n + 1) + j] * gnorm(n, rb_m(i)) / gnorm(n, rb_m(j)));
+}
 
 template <int N>
-__device__ __forceinline__ void swap_apply(float* v, const lfloat* sw) {
+__device__ __forceinline__ void swap_apply(float* v) {
   constexpr int D = 2 * N + 1;
   float out[D];
   static_for<0, D>([&](auto ic) {
@@ -99,8 +97,7 @@ __device__ __forceinline__ void swap_apply(float* v, const lfloat* sw) {
     static_for<0, D>([&](auto jc) {
       constexpr int j = jc;
       if constexpr (swap_nz(N, i, j)) {
-        constexpr int q = crowoff(N, i) + crank(N, i, j);
-        float w = sw[q];
+        constexpr float w = swap_w32(N, i, j);
         if constexpr (crank(N, i, j) == 0)
           s = w * v[j];
         else
@@ -143,9 +140,6 @@ __device__ __forceinline__ void angle_table(float c1, float s1, float* cm, float
 
 }  // namespace mx
 
-constexpr int MX_CSWAP = mx::cswoff(FMM_GPU_PMAX + 1);
-static __constant__ float c_cswap32[MX_CSWAP];
-static bool g_mx_tables[64] = {};  // per device
 constexpr int MX_WAVES = 4;
 
 // first source of [b, e) whose id is >= first_lo (ids are breadth first, so the
@@ -184,10 +178,6 @@ __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per
   using namespace mx;
   constexpr int NC = ncoef(P);
   constexpr int NR = (P + 1) * (P + 1);
-  constexpr int NSW = cswoff(P + 1);
-  __shared__ float swt[NSW];
-  for (int t = threadIdx.x; t < NSW; t += 64 * MX_WAVES) swt[t] = c_cswap32[t];
-  __syncthreads();
   // wps wavefronts per sink: the sink's list, in batches of 64 sources, is
   // split into wps contiguous parts; each wave sums its part, and the parts
   // are added in order at the end (through LDS, one barrier)
@@ -224,7 +214,6 @@ __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per
     bz = cz[B];
     sB = scale[B];
   }
-  const lfloat* sw_it = (const lfloat*)swt;
 
   for (int base = pb; base < pe; base += 64) {
     int k = base + lane;
@@ -271,16 +260,14 @@ __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per
     static_for<K0, P + 1>([&](auto kc) {
       constexpr int kk = kc;
       __builtin_amdgcn_sched_barrier(0);
-      const lfloat* sw = sw_it;
-      asm volatile("" : "+v"(sw));
       const float* Mo = Mv + kk * kk;
       asm volatile("" : "+v"(Mo));
       float v[2 * kk + 1];
       static_for<0, 2 * kk + 1>([&](auto jc) { v[jc] = Mo[jc]; });
       rotA(kc, v, 1.f);
-      swap_apply<kk>(v, sw);
+      swap_apply<kk>(v);
       rotB(kc, v, 1.f);
-      swap_apply<kk>(v, sw);
+      swap_apply<kk>(v);
       // fold into the partial local expansion: orders n <= P - kk
       static_for<0, 2 * kk + 1>([&](auto jc) { v[jc] *= pA[kk]; });
       static_for<0, P - kk + 1>([&](auto nc) {
@@ -301,23 +288,19 @@ __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per
     static_for<0, K0>([&](auto nc) {
       constexpr int n = nc;
       __builtin_amdgcn_sched_barrier(0);
-      const lfloat* sw = sw_it;
-      asm volatile("" : "+v"(sw));
       const float* Mo = Mv + n * n;
       asm volatile("" : "+v"(Mo));
       float* v = Mp + n * n;
       static_for<0, 2 * n + 1>([&](auto jc) { v[jc] = Mo[jc]; });
       rotA(nc, v, 1.f);
-      swap_apply<n>(v, sw);
+      swap_apply<n>(v);
       rotB(nc, v, 1.f);
-      swap_apply<n>(v, sw);
+      swap_apply<n>(v);
       static_for<0, 2 * n + 1>([&](auto jc) { v[jc] *= pA[n]; });
     });
     static_for<0, P + 1>([&](auto nc) {
       constexpr int n = nc;
       __builtin_amdgcn_sched_barrier(0);
-      const lfloat* sw = sw_it;
-      asm volatile("" : "+v"(sw));
       float w[2 * n + 1];
       static_for<0, n + 1>([&](auto mc) {
         constexpr int m = mc;
@@ -345,9 +328,9 @@ __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per
           w[2 * m] = 0.f;
         }
       });
-      swap_apply<n>(w, sw);
+      swap_apply<n>(w);
       rotB(nc, w, -1.f);
-      swap_apply<n>(w, sw);
+      swap_apply<n>(w);
       rotA(nc, w, -1.f);
       reduce_lanes<2 * n + 1>(w, &acc[64 * n], lane);
     });
@@ -436,26 +419,7 @@ bool mixed_supported(int p) { return p >= 1 && p <= FMM_GPU_PMAX; }
 
 void launch_m2l_fp64_range(Ctx& c, int first_lo);
 
-void upload_mx_tables() {
-  int dev = 0;
-  HIPCHK(hipGetDevice(&dev));
-  if (!g_mx_tables[dev & 63]) {
-    // orthogonal swap matrices G W_n G^-1 in FP32, structural non-zeros only
-    std::vector<float> cs;
-    for (int n = 0; n <= FMM_GPU_PMAX; n++)
-      for (int i = 0; i < 2 * n + 1; i++)
-        for (int j = 0; j < 2 * n + 1; j++)
-          if (mx::swap_nz(n, i, j)) {
-            double w = fmm_swap_table[mx::swoff(n) + i * (2 * n + 1) + j];
-            cs.push_back((float)(w * mx::gnorm(n, mx::rb_m(i)) / mx::gnorm(n, mx::rb_m(j))));
-          }
-    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_cswap32), cs.data(), sizeof(float) * cs.size()));
-    g_mx_tables[dev & 63] = true;
-  }
-}
-
 void launch_m2l_mixed_lo(Ctx& c) {
-  upload_mx_tables();
   int nc = (int)c.ncell;
   int first_lo = mixed_first_lo(c);
   if (first_lo >= nc) {
