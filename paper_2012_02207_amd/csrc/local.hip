@@ -231,8 +231,7 @@ __global__ void __launch_bounds__(64 * LG_WAVES) __attribute__((amdgpu_waves_per
   __shared__ double rbuf[LG_WAVES][4][64];
   int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   int nblk = (nleaves + LG_WAVES - 1) / LG_WAVES;
-  int per = (nblk + 7) >> 3;
-  int blk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  int blk = blockIdx.x;  // consecutive workgroups go to different XCDs: even work per XCD
   int li = blk * LG_WAVES + wv;
   if (blk >= nblk || li >= nleaves) return;
   int B = leaves[li];

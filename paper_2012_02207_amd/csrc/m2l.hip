@@ -291,13 +291,12 @@ __device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, con
   });
 }
 
-// All sinks (one wavefront each, in XCD-contiguous ranges: neighbouring sinks
-// share sources), or, with LIST, the sinks[0 .. *nsinks) in a grid-stride loop.
-// Up to p = 10, two waves per SIMD (256 registers each, a few spilled at p =
-// 10): measured faster than one wave with everything in registers.  Higher
-// orders would spill heavily at that budget and take one wave.  The per-order
-// sums live in LDS and the sink index is wave-uniform (its data in SGPRs),
-// which keeps the spills small.
+// All sinks (one wavefront each; consecutive workgroups, which the hardware
+// hands to the eight XCDs in turn, take consecutive sinks, so that every XCD
+// gets an even share of the work), or, with LIST, the sinks[0 .. *nsinks) in
+// a grid-stride loop.  Up to p = 10, two waves per SIMD (256 registers each).
+// Higher orders take one wave.  The per-order sums live in LDS and the sink
+// index is wave-uniform (its data in SGPRs).
 template <int P, bool LIST>
 __global__ void __launch_bounds__(64 * M2L_WAVES) __attribute__((amdgpu_waves_per_eu(P <= 10 ? 2 : 1))) k_m2l_fp64(int ncell, int first_lo, const int* __restrict__ sinks,
                                                              const int* __restrict__ nsinks,
@@ -317,8 +316,7 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) __attribute__((amdgpu_waves_pe
       m2l_sink_fp64<P>(sinks[it], first_lo, lane, off, src, cx, cy, cz, mult, loc, acc);
   } else {
     int nblk = (ncell + M2L_WAVES - 1) / M2L_WAVES;
-    int per = (nblk + 7) >> 3;
-    int blk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    int blk = blockIdx.x;  // consecutive workgroups go to different XCDs: even work per XCD
     int B = blk * M2L_WAVES + wv;
     if (blk < nblk && B < ncell)
       m2l_sink_fp64<P>(B, first_lo, lane, off, src, cx, cy, cz, mult, loc, acc);

@@ -157,16 +157,16 @@ __device__ __forceinline__ int split_point(const int* src, int b, int e, int fir
 }
 
 // One wavefront per sink (or wps of them, each with a contiguous part of the
-// list), a source per lane.  Up to p = 10, three waves per
-// SIMD (at most 168 VGPRs); higher orders need more registers and take two
-// (p = 11, 12) or one.
+// list), a source per lane.  Up to p = 10, four waves per
+// SIMD (at most 128 VGPRs: a few bytes spill at p = 10, measured faster than
+// three waves without); p = 11 takes three and higher orders two.
 // The FP64 per-order sums live in LDS (a slot per lane), not in registers,
 // which would spill at that budget.
 // The angle multiples cos ma, sin ma of the two z-rotations come from tables
 // built once per pair (rebuilding them in every order's rotation cost ~13% of
 // the kernel's instructions at p = 10).
 template <int P>
-__global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per_eu(P <= 10 ? 3 : P <= 12 ? 2 : 1))) k_m2l_fp32(int ncell, int first_lo,
+__global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per_eu(P <= 10 ? 4 : P <= 11 ? 3 : 2))) k_m2l_fp32(int ncell, int first_lo,
                                                             const int* __restrict__ off,
                                                             const int* __restrict__ src,
                                                             const double* __restrict__ cx,
@@ -184,8 +184,7 @@ __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per
   int spb = MX_WAVES / wps;    // sinks per workgroup
   int nlo = ncell - first_lo;  // sinks below the root levels
   int nblk = (nlo + spb - 1) / spb;
-  int per = (nblk + 7) >> 3;
-  int blk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  int blk = blockIdx.x;  // consecutive workgroups go to different XCDs: even work per XCD
   int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: B and its data in SGPRs
   int slot = wv / wps, part = wv - slot * wps;
   int B = first_lo + blk * spb + slot;

@@ -409,8 +409,7 @@ __global__ void __launch_bounds__(64 * NF_WAVES) k_near_f(int nleaves, const int
   __shared__ double4 sbuf[NF_WAVES][64];
   int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int nblk = (nleaves + NF_WAVES - 1) / NF_WAVES;
-  int per = (nblk + 7) >> 3;
-  int blk = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  int blk = blockIdx.x;  // consecutive workgroups go to different XCDs: even work per XCD
   int li = blk * NF_WAVES + wv;
   if (blk >= nblk || li >= nleaves) return;
   int B = leaves[li];
