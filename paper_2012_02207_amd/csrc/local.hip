@@ -231,7 +231,7 @@ __global__ void __launch_bounds__(64 * LG_WAVES) __attribute__((amdgpu_waves_per
   __shared__ double rbuf[LG_WAVES][4][64];
   int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   int nblk = (nleaves + LG_WAVES - 1) / LG_WAVES;
-  int blk = blockIdx.x;  // consecutive workgroups go to different XCDs: even work per XCD
+  int blk = xcd_block();
   int li = blk * LG_WAVES + wv;
   if (blk >= nblk || li >= nleaves) return;
   int B = leaves[li];
@@ -365,7 +365,7 @@ void launch_near_field(Ctx& c) {
   unsigned long long* npairs = (unsigned long long*)(c.counters.p + 40);
   zero_fill(c, npairs, sizeof(unsigned long long));
   int nblk = (int)((c.nleaf + LG_WAVES - 1) / LG_WAVES);
-  unsigned grid = 8u * (unsigned)((nblk + 7) / 8);
+  unsigned grid = xcd_grid(nblk);
   double e2 = c.eps_soft * c.eps_soft;
   int gmax = c.prm.p2p_groups;
   if (c.prm.precision == FMM_MIXED)

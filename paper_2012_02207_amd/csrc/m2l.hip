@@ -316,7 +316,7 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) __attribute__((amdgpu_waves_pe
       m2l_sink_fp64<P>(sinks[it], first_lo, lane, off, src, cx, cy, cz, mult, loc, acc);
   } else {
     int nblk = (ncell + M2L_WAVES - 1) / M2L_WAVES;
-    int blk = blockIdx.x;  // consecutive workgroups go to different XCDs: even work per XCD
+    int blk = xcd_block();
     int B = blk * M2L_WAVES + wv;
     if (blk < nblk && B < ncell)
       m2l_sink_fp64<P>(B, first_lo, lane, off, src, cx, cy, cz, mult, loc, acc);
@@ -335,7 +335,7 @@ static void launch_p(Ctx& c, int first_lo, const double* mult, double* loc, cons
     return;
   }
   int nblk = (nc + M2L_WAVES - 1) / M2L_WAVES;
-  unsigned grid = 8u * (unsigned)((nblk + 7) / 8);
+  unsigned grid = xcd_grid(nblk);
   hipLaunchKernelGGL((k_m2l_fp64<P, false>), dim3(grid), dim3(64 * M2L_WAVES), 0, c.stream, nc, first_lo,
                      (const int*)nullptr, (const int*)nullptr, c.m2l.off.p, c.m2l.src.p, c.c_cx.p, c.c_cy.p,
                      c.c_cz.p, mult, loc);

@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per
   int spb = MX_WAVES / wps;    // sinks per workgroup
   int nlo = ncell - first_lo;  // sinks below the root levels
   int nblk = (nlo + spb - 1) / spb;
-  int blk = blockIdx.x;  // consecutive workgroups go to different XCDs: even work per XCD
+  int blk = xcd_block();
   int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: B and its data in SGPRs
   int slot = wv / wps, part = wv - slot * wps;
   int B = first_lo + blk * spb + slot;
@@ -395,7 +395,7 @@ static void launch_p32(Ctx& c, int first_lo) {
   int wps = c.prm.m2l_waves;
   int spb = MX_WAVES / wps;
   int nblk = (nlo + spb - 1) / spb;
-  unsigned grid = 8u * (unsigned)((nblk + 7) / 8);
+  unsigned grid = xcd_grid(nblk);
   hipLaunchKernelGGL(k_m2l_fp32<P>, dim3(grid), dim3(64 * MX_WAVES), 0, c.stream, nc, first_lo,
                      c.m2l.off.p, c.m2l.src.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.scale.p, c.nmult.p, c.loc.p,
                      wps);

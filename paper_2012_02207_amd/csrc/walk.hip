@@ -409,7 +409,7 @@ __global__ void __launch_bounds__(64 * NF_WAVES) k_near_f(int nleaves, const int
   __shared__ double4 sbuf[NF_WAVES][64];
   int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int nblk = (nleaves + NF_WAVES - 1) / NF_WAVES;
-  int blk = blockIdx.x;  // consecutive workgroups go to different XCDs: even work per XCD
+  int blk = xcd_block();
   int li = blk * NF_WAVES + wv;
   if (blk >= nblk || li >= nleaves) return;
   int B = leaves[li];
@@ -533,7 +533,7 @@ void estimate_walk(Ctx& c, const std::function<void()>& beside) {
   group_by_sink(c, c.est_near);
   {
     int nblk = (int)ceil_div(c.nleaf, NF_WAVES);
-    unsigned grid = 8u * (unsigned)ceil_div(nblk, 8);
+    unsigned grid = xcd_grid(nblk);
     hipLaunchKernelGGL(k_near_f, dim3(grid), dim3(64 * NF_WAVES), 0, s, (int)c.nleaf, c.leaves.p,
                        c.c_begin.p, c.c_end.p, c.est_near.off.p, c.est_near.src.p, c.pm.p, c.fpart.p);
   }
