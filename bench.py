@@ -62,11 +62,11 @@ P2P_FLOPS = 20   # per directed body pair: acc + pot, softened, rsqrt counted on
 # (fetch x2.0, write x1.0).  Keyed by (kernel, workload, precision); valid only
 # while the kernel's source file has the recorded SHA-1 (else reported as null).
 MEASURED_TRAFFIC = {
-    ("k_m2l_fp32", "plummer_1m", "mixed"): (460.7e6, "paper_2012_02207_amd/csrc/m2l_mixed.hip",
-                                             "604ece7d31e031f2f39453a8a5b50b736ca45910"),
-    ("k_leaf_group<true> (mixed P2P)", "plummer_1m", "mixed"): (194.7e6,
+    ("k_m2l_fp32", "plummer_1m", "mixed"): (1611.1e6, "paper_2012_02207_amd/csrc/m2l_mixed.hip",
+                                             "447ac4c5efdd9d84a9e674680f5622e5406c6082"),
+    ("k_leaf_group<true> (mixed P2P)", "plummer_1m", "mixed"): (666.6e6,
                                                                 "paper_2012_02207_amd/csrc/local.hip",
-                                                                "0703b22073d36a2476cbee895870d67241e8d2dc"),
+                                                                "77c505aed2bd84a3c5b73c748e2af43710044d9f"),
 }
 
 
