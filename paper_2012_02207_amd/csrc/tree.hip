@@ -290,8 +290,8 @@ __global__ void k_keys(const double* pos, int64_t n, const double* rootbox_all, 
 // Stable LSD sort of (63-bit key, int payload), 8-bit digits.  Each block ranks a
 // tile of RS_TILE keys: waves walk their sub-tile in 64-key chunks, computing
 // for every key its rank among equal digits with 8 ballots, so the rank order
-// equals the input order (stability).  Global digit offsets come from an
-// exclusive scan over the digit-major block histograms.
+// equals the input order (stability).  Global digit offsets come from a
+// per-digit scan of the digit-major block histograms (k_rs_rowscan).
 constexpr int RS_T = 256, RS_W = RS_T / 64, RS_I = 16, RS_TILE = RS_T * RS_I;
 
 template <class K>
@@ -309,21 +309,79 @@ __global__ void __launch_bounds__(RS_T) k_rs_hist(const K* key, int64_t n, int s
   hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
+// Per digit, the exclusive prefix of its tile counts over the tiles (one
+// workgroup per digit, the row in runs of 8 x RS_T counts, each thread taking
+// 8 consecutive ones), and the digit's total.  The scatter adds the totals of
+// the smaller digits itself.
+__global__ void __launch_bounds__(RS_T) k_rs_rowscan(const int* __restrict__ hist, int nblocks, int* offs,
+                                                     int* rowtot) {
+  __shared__ int wsum[2][RS_W];
+  int d = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int* row = hist + (int64_t)d * nblocks;
+  int* orow = offs + (int64_t)d * nblocks;
+  int carry = 0;
+  for (int base = 0, it = 0; base < nblocks; base += 8 * RS_T, it ^= 1) {
+    int t0 = base + (int)threadIdx.x * 8;
+    int v[8], sum = 0;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      v[k] = t0 + k < nblocks ? row[t0 + k] : 0;
+      sum += v[k];
+    }
+    int incl = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+      int y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[it][w] = incl;  // alternate buffers: no second barrier per run
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int ww = 0; ww < RS_W; ww++) {
+      if (ww < w) before += wsum[it][ww];
+      total += wsum[it][ww];
+    }
+    int run = carry + before + incl - sum;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      if (t0 + k < nblocks) orow[t0 + k] = run;
+      run += v[k];
+    }
+    carry += total;
+  }
+  if (threadIdx.x == 0) rowtot[d] = carry;
+}
+
 // Ranks as above, then the tile is reordered by digit in LDS and written out
 // with consecutive lanes on consecutive destinations (each digit's run of the
 // tile is contiguous in the output), so the global writes coalesce.
 template <bool VAL, class KI, class KO>
 __global__ void __launch_bounds__(RS_T) k_rs_scatter(const KI* kin, const int* vin, KO* kout, int* vout,
-                                                     int64_t n, int shift, const int* offs, int nblocks) {
+                                                     int64_t n, int shift, const int* offs, const int* rowtot,
+                                                     int nblocks) {
   __shared__ int wcnt[RS_W][256];
   __shared__ int goff[256], lofs[256], wsum[RS_W];
   __shared__ KO sk[RS_TILE];
   __shared__ int sv[VAL ? RS_TILE : 1];
+  for (int t = threadIdx.x; t < RS_W * 256; t += RS_T) (&wcnt[0][0])[t] = 0;
   int w = threadIdx.x >> 6;
   int lane = threadIdx.x & 63;
-  for (int t = threadIdx.x; t < RS_W * 256; t += RS_T) (&wcnt[0][0])[t] = 0;
-  goff[threadIdx.x] = offs[(int64_t)threadIdx.x * nblocks + blockIdx.x];
-  __syncthreads();
+  {
+    // start of this digit in the output: the totals of the smaller digits
+    // (an exclusive scan over the 256 digits, one per thread) plus the counts
+    // of the earlier tiles
+    int tot = rowtot[threadIdx.x];
+    int incl = tot;
+    for (int o = 1; o < 64; o <<= 1) {
+      int y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int before = 0;
+    for (int ww = 0; ww < w; ww++) before += wsum[ww];
+    goff[threadIdx.x] = before + incl - tot + offs[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+    __syncthreads();
+  }
   int64_t tile0 = (int64_t)blockIdx.x * RS_TILE;
   int64_t base = tile0 + (int64_t)w * (RS_TILE / RS_W);
   int tcount = (int)(n - tile0 < RS_TILE ? n - tile0 : RS_TILE);
@@ -395,22 +453,23 @@ __global__ void __launch_bounds__(RS_T) k_rs_scatter(const KI* kin, const int* v
 int radix_sort(Ctx& c, uint64_t* k0, int* v0, uint64_t* k1, int* v1, int64_t n, int nbits) {
   if (n <= 0) return 0;
   int nb = (int)ceil_div(n, RS_TILE);
-  ensure(c.ws, c.sort_hist, (size_t)256 * nb * 2 + 64);
+  ensure(c.ws, c.sort_hist, (size_t)256 * nb * 2 + 256 + 64);
   int* hist = c.sort_hist.p;
   int* offs = hist + (size_t)256 * nb;
+  int* rowtot = offs + (size_t)256 * nb;
   int src = 0;
   uint64_t* kk[2] = {k0, k1};
   int* vv[2] = {v0, v1};
   for (int shift = 0; shift < nbits; shift += 8) {
     hipLaunchKernelGGL(k_rs_hist<uint64_t>, dim3(nb), dim3(RS_T), 0, c.stream, kk[src], n, shift, hist, nb);
     HIPCHK(hipGetLastError());
-    exclusive_scan(c, hist, offs, (int64_t)256 * nb, nullptr);
+    hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(RS_T), 0, c.stream, hist, nb, offs, rowtot);
     if (v0)
       hipLaunchKernelGGL((k_rs_scatter<true, uint64_t, uint64_t>), dim3(nb), dim3(RS_T), 0, c.stream,
-                         kk[src], vv[src], kk[1 - src], vv[1 - src], n, shift, offs, nb);
+                         kk[src], vv[src], kk[1 - src], vv[1 - src], n, shift, offs, rowtot, nb);
     else
       hipLaunchKernelGGL((k_rs_scatter<false, uint64_t, uint64_t>), dim3(nb), dim3(RS_T), 0, c.stream,
-                         kk[src], nullptr, kk[1 - src], nullptr, n, shift, offs, nb);
+                         kk[src], nullptr, kk[1 - src], nullptr, n, shift, offs, rowtot, nb);
     HIPCHK(hipGetLastError());
     src = 1 - src;
   }
@@ -423,23 +482,24 @@ int radix_sort(Ctx& c, uint64_t* k0, int* v0, uint64_t* k1, int* v1, int64_t n, 
 uint32_t* radix_sort_narrow(Ctx& c, const uint64_t* in, uint32_t* b0, uint32_t* b1, int64_t n, int nbits) {
   if (n <= 0) return b0;
   int nb = (int)ceil_div(n, RS_TILE);
-  ensure(c.ws, c.sort_hist, (size_t)256 * nb * 2 + 64);
+  ensure(c.ws, c.sort_hist, (size_t)256 * nb * 2 + 256 + 64);
   int* hist = c.sort_hist.p;
   int* offs = hist + (size_t)256 * nb;
+  int* rowtot = offs + (size_t)256 * nb;
   hipLaunchKernelGGL(k_rs_hist<uint64_t>, dim3(nb), dim3(RS_T), 0, c.stream, in, n, 0, hist, nb);
   HIPCHK(hipGetLastError());
-  exclusive_scan(c, hist, offs, (int64_t)256 * nb, nullptr);
+  hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(RS_T), 0, c.stream, hist, nb, offs, rowtot);
   hipLaunchKernelGGL((k_rs_scatter<false, uint64_t, uint32_t>), dim3(nb), dim3(RS_T), 0, c.stream, in,
-                     nullptr, b0, nullptr, n, 0, offs, nb);
+                     nullptr, b0, nullptr, n, 0, offs, rowtot, nb);
   HIPCHK(hipGetLastError());
   uint32_t* bb[2] = {b0, b1};
   int src = 0;
   for (int shift = 8; shift < nbits; shift += 8) {
     hipLaunchKernelGGL(k_rs_hist<uint32_t>, dim3(nb), dim3(RS_T), 0, c.stream, bb[src], n, shift, hist, nb);
     HIPCHK(hipGetLastError());
-    exclusive_scan(c, hist, offs, (int64_t)256 * nb, nullptr);
+    hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(RS_T), 0, c.stream, hist, nb, offs, rowtot);
     hipLaunchKernelGGL((k_rs_scatter<false, uint32_t, uint32_t>), dim3(nb), dim3(RS_T), 0, c.stream,
-                       bb[src], nullptr, bb[1 - src], nullptr, n, shift, offs, nb);
+                       bb[src], nullptr, bb[1 - src], nullptr, n, shift, offs, rowtot, nb);
     HIPCHK(hipGetLastError());
     src = 1 - src;
   }
