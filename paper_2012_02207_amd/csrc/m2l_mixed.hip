@@ -159,14 +159,15 @@ __device__ __forceinline__ int split_point(const int* src, int b, int e, int fir
 // One wavefront per sink (or wps of them, each with a contiguous part of the
 // list), a source per lane.  Up to p = 10, four waves per
 // SIMD (at most 128 VGPRs: a few bytes spill at p = 10, measured faster than
-// three waves without); p = 11 takes three and higher orders two.
+// three waves without); p = 11, 12 take three (p = 12 in 168 VGPRs, 6% faster
+// than two waves on the 2^22-body workload) and higher orders two.
 // The FP64 per-order sums live in LDS (a slot per lane), not in registers,
 // which would spill at that budget.
 // The angle multiples cos ma, sin ma of the two z-rotations come from tables
 // built once per pair (rebuilding them in every order's rotation cost ~13% of
 // the kernel's instructions at p = 10).
 template <int P>
-__global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per_eu(P <= 10 ? 4 : P <= 11 ? 3 : 2))) k_m2l_fp32(int ncell, int first_lo,
+__global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per_eu(P <= 10 ? 4 : P <= 12 ? 3 : 2))) k_m2l_fp32(int ncell, int first_lo,
                                                             const int* __restrict__ off,
                                                             const int* __restrict__ src,
                                                             const double* __restrict__ cx,
