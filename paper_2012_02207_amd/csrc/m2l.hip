@@ -294,11 +294,12 @@ __device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, con
 // All sinks (one wavefront each; consecutive workgroups, which the hardware
 // hands to the eight XCDs in turn, take consecutive sinks, so that every XCD
 // gets an even share of the work), or, with LIST, the sinks[0 .. *nsinks) in
-// a grid-stride loop.  Up to p = 10, two waves per SIMD (256 registers each).
-// Higher orders take one wave.  The per-order sums live in LDS and the sink
-// index is wave-uniform (its data in SGPRs).
+// a grid-stride loop.  Up to p = 12, two waves per SIMD (256 registers each;
+// at p = 12 84 B spill, and the 2^22-body FP64 evaluation still takes 49.2 ms
+// instead of 55.0 with one wave).  Higher orders take one wave.  The per-order
+// sums live in LDS and the sink index is wave-uniform (its data in SGPRs).
 template <int P, bool LIST>
-__global__ void __launch_bounds__(64 * M2L_WAVES) __attribute__((amdgpu_waves_per_eu(P <= 10 ? 2 : 1))) k_m2l_fp64(int ncell, int first_lo, const int* __restrict__ sinks,
+__global__ void __launch_bounds__(64 * M2L_WAVES) __attribute__((amdgpu_waves_per_eu(P <= 12 ? 2 : 1))) k_m2l_fp64(int ncell, int first_lo, const int* __restrict__ sinks,
                                                              const int* __restrict__ nsinks,
                                                              const int* __restrict__ off,
                                                              const int* __restrict__ src,
