@@ -224,7 +224,7 @@ def run_ensemble(args):
         if batched and not args.no_autotune:  # the batched forms run at the autotuner's choices
             f.autotune(dpos, dmass, off)
             tuned = {"n_leaf": f.params.n_leaf, "m2l_waves": f.params.m2l_waves,
-                     "p2p_groups": f.params.p2p_groups}
+                     "p2p_groups": f.params.p2p_groups, "p2p_start": f.params.p2p_start}
         acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
         pot = torch.empty((n,), dtype=torch.float64, device=dev)
         outs = [(acc[off[i]:off[i + 1]], pot[off[i]:off[i + 1]]) for i in range(len(clusters))]

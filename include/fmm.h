@@ -70,6 +70,9 @@ typedef struct {
                        each takes a contiguous part of the sink's list, the parts added in order */
   int p2p_groups;   /* near field: at most this many lane groups share a sink leaf's sources
                        (0 = as many as the wavefront holds, the default; else 1..64) */
+  int p2p_start;    /* after a tree build: 0 = the near field starts once its own list is
+                       grouped (default); 1 = only after the M2L list is grouped as well, so
+                       that a long near field does not hold the chip while that grouping waits */
 } fmm_params;
 
 /* counts and times of the last call (filled by fmm_stats); times in ms between
@@ -132,7 +135,7 @@ typedef struct fmm_ctx fmm_ctx;
 
 /* Defaults: p = 10, err_tol = 1e-7, theta = 1, theta_est = 1, n_leaf = 64,
  * precision = FMM_FP64, mac = FMM_MAC_ERROR, check_inputs = 0, root_levels = 3,
- * m2l_waves = 1, p2p_groups = 0. */
+ * m2l_waves = 1, p2p_groups = 0, p2p_start = 0. */
 void fmm_default_params(fmm_params* out /* host */);
 
 /* Creates a context on the current HIP device.  prm (host) may be NULL for the
@@ -265,7 +268,8 @@ fmm_status fmm_forces_batch(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets, 
                             const double* mass, double eps_soft, int p, double err_tol,
                             double* acc, double* pot, void* stream);
 
-/* Autotuner (NEXT: batched ensembles): picks, for this workload, the leaf
+/* Autotuner (NEXT: batched ensembles): picks, for this workload, when the
+ * near field starts (p2p_start in {0, 1}, at the given n_leaf), the leaf
  * capacity n_leaf (the balance between the near field and the expansions),
  * then in mixed precision the FP32 M2L's wavefronts per sink (m2l_waves in
  * {1, 2, 4}), then the near field's lane groups per sink leaf (p2p_groups in

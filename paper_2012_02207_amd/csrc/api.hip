@@ -118,7 +118,8 @@ __global__ void k_count_low_pairs(const int* off, const int* src, int ncell, int
 // kernel, so the order of the two M2L parts does not change the result.
 // group: the lists come straight from the walk; the near-field list is
 // grouped on the side stream (with its own sort scratch) while the M2L list is
-// grouped on the caller's stream.
+// grouped on the caller's stream; with p2p_start = 1 the near field waits for
+// both groupings.
 void evaluate(Ctx& c, double* acc, double* pot, bool group) {
   hipStream_t s = c.stream;
   int nc = (int)c.ncell;
@@ -137,6 +138,7 @@ void evaluate(Ctx& c, double* acc, double* pot, bool group) {
     if (group) {
       SideScratch alt(c, 2);
       group_list(c, c.p2p);
+      if (c.prm.p2p_start == 1) stream_wait(c.fork[8], s, c.side);
     }
     if (c.have_events) HIPCHK(hipEventRecord(c.ev[6], c.side));
     launch_near_field(c);
@@ -181,6 +183,7 @@ static fmm_status validate_params(const fmm_params* p) {
   if (p->root_levels < 0 || p->root_levels > FMM_MAX_LEVEL + 1) return FMM_EINVAL;
   if (p->m2l_waves != 1 && p->m2l_waves != 2 && p->m2l_waves != 4) return FMM_EINVAL;
   if (p->p2p_groups < 0 || p->p2p_groups > 64) return FMM_EINVAL;
+  if (p->p2p_start != 0 && p->p2p_start != 1) return FMM_EINVAL;
   return FMM_OK;
 }
 
@@ -221,6 +224,7 @@ void fmm_default_params(fmm_params* out) {
   out->root_levels = 3;
   out->m2l_waves = 1;
   out->p2p_groups = 0;
+  out->p2p_start = 0;
 }
 
 fmm_status fmm_create(fmm_ctx** out, const fmm_params* prm) {
@@ -715,12 +719,12 @@ fmm_status fmm_jerk(fmm_ctx* ctx, int64_t n, const double* pos, const double* ve
   return st;
 }
 
-// ---- autotuner: n_leaf, FP32 M2L wavefronts per sink and near-field lane
-// groups per (device, precision, p, tolerance, size class) ----
+// ---- autotuner: near-field start, n_leaf, FP32 M2L wavefronts per sink and
+// near-field lane groups per (device, precision, p, tolerance, size class) ----
 namespace {
 using TuneKey = std::tuple<int, int, int, double, int, int>;
 struct TuneChoice {
-  int n_leaf, m2l_waves, p2p_groups;
+  int n_leaf, m2l_waves, p2p_groups, p2p_start;
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneChoice> g_tune_cache;
@@ -749,6 +753,7 @@ fmm_status fmm_autotune(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets, cons
     c.prm.n_leaf = t.n_leaf;
     c.prm.m2l_waves = t.m2l_waves;
     c.prm.p2p_groups = t.p2p_groups;
+    c.prm.p2p_start = t.p2p_start;
     c.graph_valid = false;
     *chosen_n_leaf = t.n_leaf;
   };
@@ -773,6 +778,7 @@ fmm_status fmm_autotune(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets, cons
     c.prm.n_leaf = t.n_leaf;
     c.prm.m2l_waves = t.m2l_waves;
     c.prm.p2p_groups = t.p2p_groups;
+    c.prm.p2p_start = t.p2p_start;
     fmm_status s1 = forces_impl(ctx, nsys, offsets, n, pos, mass, eps_soft, p, err_tol, acc, pot, stream);
     if (s1 != FMM_OK) return s1;
     s1 = guarded(ctx, [&]() {
@@ -789,15 +795,29 @@ fmm_status fmm_autotune(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets, cons
       return FMM_OK;
     });
   };
-  // coordinate search: the leaf capacity first (it sets the balance of near
-  // and far field), then the FP32 M2L's wavefronts per sink (mixed precision
-  // only), then the near field's lane groups
-  TuneChoice best{saved.n_leaf, saved.m2l_waves, saved.p2p_groups};
+  // coordinate search: the near field's start (at the given leaf capacity,
+  // so that the capacity is then chosen under the better schedule), the leaf
+  // capacity (it sets the balance of near and far field), then the FP32 M2L's
+  // wavefronts per sink (mixed precision only), then the near field's lane
+  // groups
+  TuneChoice best{saved.n_leaf, saved.m2l_waves, saved.p2p_groups, saved.p2p_start};
   float best_ms = 1e30f;
+  static const int cand_start[] = {0, 1};
   static const int cand_leaf[] = {16, 24, 32, 48, 64, 96, 128};
   static const int cand_waves[] = {1, 2, 4};
   static const int cand_groups[] = {0, 4, 2};
+  for (int ps : cand_start) {
+    TuneChoice t = best;
+    t.p2p_start = ps;
+    float ms = 0;
+    if ((st = timed(t, ms)) != FMM_OK) break;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
+  }
   for (int nl : cand_leaf) {
+    if (st != FMM_OK) break;
     TuneChoice t = best;
     t.n_leaf = nl;
     float ms = 0;

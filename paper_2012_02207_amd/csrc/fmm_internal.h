@@ -202,7 +202,7 @@ struct Ctx {
   // stream: the upward pass beside the estimate walk, the near field beside
   // M2L and L2L; forked and joined with the events below
   hipStream_t side = nullptr, side2 = nullptr;  // side2: root-level FP64 M2L
-  hipEvent_t fork[8] = {};
+  hipEvent_t fork[9] = {};
   dbuf<double4> nearbuf;  // near-field (acc, pot) per sorted body
 
   // replay of the frozen-tree evaluation as a HIP graph (captured per set of

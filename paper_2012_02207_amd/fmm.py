@@ -44,7 +44,8 @@ class Params(C.Structure):
     _fields_ = [("p", C.c_int), ("err_tol", C.c_double), ("theta", C.c_double),
                 ("theta_est", C.c_double), ("n_leaf", C.c_int), ("precision", C.c_int),
                 ("mac", C.c_int), ("check_inputs", C.c_int), ("root_levels", C.c_int),
-                ("m2l_waves", C.c_int), ("p2p_groups", C.c_int)]
+                ("m2l_waves", C.c_int), ("p2p_groups", C.c_int),
+                ("p2p_start", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -147,7 +148,8 @@ class FMM:
     """A force-evaluation context (owns the device workspace)."""
 
     def __init__(self, p=10, err_tol=1e-7, theta=1.0, theta_est=1.0, n_leaf=64, precision="fp64",
-                 mac="error", check_inputs=False, root_levels=3, m2l_waves=1, p2p_groups=0):
+                 mac="error", check_inputs=False, root_levels=3, m2l_waves=1, p2p_groups=0,
+                 p2p_start=0):
         lib = load_library()
         _torch()
         self._lib = lib
@@ -157,6 +159,7 @@ class FMM:
         self.params.precision, self.params.mac = PRECISION[precision], MAC[mac]
         self.params.check_inputs, self.params.root_levels = int(bool(check_inputs)), int(root_levels)
         self.params.m2l_waves, self.params.p2p_groups = int(m2l_waves), int(p2p_groups)
+        self.params.p2p_start = int(p2p_start)
         h = C.c_void_p()
         st = lib.fmm_create(C.byref(h), C.byref(self.params))
         if st != FMM_OK:
@@ -182,7 +185,7 @@ class FMM:
     def set_params(self, **kw):
         """Replaces parameters for later calls (fmm_set_params): any of p, err_tol,
         theta, theta_est, n_leaf, precision ("fp64"/"mixed"/"direct"), mac,
-        check_inputs, root_levels, m2l_waves, p2p_groups."""
+        check_inputs, root_levels, m2l_waves, p2p_groups, p2p_start."""
         conv = {"precision": lambda v: PRECISION[v], "mac": lambda v: MAC[v],
                 "check_inputs": lambda v: int(bool(v))}
         new = Params()

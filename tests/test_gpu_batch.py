@@ -183,6 +183,7 @@ def test_autotune_picks_a_candidate_and_caches(fmm):
     assert time.perf_counter() - t0 < 0.5
     prm = f.get_params()
     assert prm.n_leaf == nl and prm.m2l_waves == 1 and prm.p2p_groups in (0, 4, 2)
+    assert prm.p2p_start in (0, 1)
     acc, _ = f.forces_batch(_dev(pos), _dev(mass), off)
     acc = acc.cpu().numpy()
     s = 5  # the 3000-body Plummer system
@@ -205,7 +206,8 @@ def test_autotune_mixed_picks_every_knob(fmm):
     nl = f.autotune(_dev(pos), _dev(mass), off)
     prm = f.get_params()
     assert prm.n_leaf == nl and prm.m2l_waves in (1, 2, 4) and prm.p2p_groups in (0, 4, 2)
-    assert f.params.m2l_waves == prm.m2l_waves
+    assert prm.p2p_start in (0, 1)
+    assert f.params.m2l_waves == prm.m2l_waves and f.params.p2p_start == prm.p2p_start
     acc, _ = f.forces_batch(_dev(pos), _dev(mass), off)
     acc = acc.cpu().numpy()
     s = 5

@@ -326,22 +326,31 @@ def test_mixed_kroupa_mass_spectrum(fmm):
     assert np.median(rel) <= MIXED_MEDIAN_BOUND and np.percentile(rel, 99) <= 5 * MIXED_MEDIAN_BOUND
 
 
-@pytest.mark.parametrize("m2l_waves,p2p_groups", [(2, 0), (4, 0), (1, 2), (4, 1)])
-def test_tuning_knobs(fmm, m2l_waves, p2p_groups):
+@pytest.mark.parametrize("m2l_waves,p2p_groups,p2p_start",
+                         [(2, 0, 0), (4, 0, 1), (1, 2, 0), (4, 1, 1)])
+def test_tuning_knobs(fmm, m2l_waves, p2p_groups, p2p_start):
     """The autotuner's knobs change only the work split: wavefronts per sink
     in the FP32 M2L (the list cut into contiguous parts, the parts added in
-    order) and lane groups per sink leaf in the near field.  Mixed precision
-    stays within its bound of the FP64 oracle, the FP64 form within 1e-12,
-    and the lists are those of the oracle."""
+    order) and lane groups per sink leaf in the near field; the near field's
+    start changes only the schedule (its result is that of the default
+    start, bit for bit).  Mixed precision stays within its bound of the FP64
+    oracle, the FP64 form within 1e-12, and the lists are those of the
+    oracle."""
     pos, _, mass = W.plummer(3000, 301)
-    print(f"[gpu] knobs m2l_waves={m2l_waves} p2p_groups={p2p_groups}", flush=True)
+    print(f"[gpu] knobs m2l_waves={m2l_waves} p2p_groups={p2p_groups} p2p_start={p2p_start}",
+          flush=True)
     o = oracle.Oracle()
     oacc, _ = o.run(pos, mass, p=8, err_tol=1e-6, n_leaf=32)
     for precision in ("mixed", "fp64"):
         f = fmm.FMM(p=8, err_tol=1e-6, n_leaf=32, precision=precision, root_levels=2,
-                    m2l_waves=m2l_waves, p2p_groups=p2p_groups)
+                    m2l_waves=m2l_waves, p2p_groups=p2p_groups, p2p_start=p2p_start)
         acc, _ = f.forces(_dev(pos), _dev(mass))
         acc = acc.cpu().numpy()
+        if p2p_start:
+            f.set_params(p2p_start=0)
+            a0, _ = f.forces(_dev(pos), _dev(mass))
+            assert np.array_equal(acc, a0.cpu().numpy())
+            f.set_params(p2p_start=p2p_start)
         assert np.array_equal(_sorted_pairs(f.export("m2l")), _sorted_pairs(o.get("m2l")))
         rel = np.linalg.norm(acc - oacc, axis=1) / np.linalg.norm(oacc, axis=1)
         bound = MIXED_MEDIAN_BOUND if precision == "mixed" else 1e-12
@@ -353,3 +362,5 @@ def test_tuning_knobs(fmm, m2l_waves, p2p_groups):
         fmm.FMM(m2l_waves=3)
     with pytest.raises(fmm.FmmError):
         fmm.FMM(p2p_groups=65)
+    with pytest.raises(fmm.FmmError):
+        fmm.FMM(p2p_start=2)
