@@ -235,24 +235,148 @@ __device__ __forceinline__ double rsqrt_fp64(double x) {
   return y;
 }
 
+// Near field of the gradient and jerk operators, one wavefront per sink leaf
+// (the layout of the forward near field): the leaf's bodies are replicated
+// over G = 64 / n_B lane groups, group g takes every G-th body of each source
+// leaf, whose positions and source records are staged in LDS by one coalesced
+// load per chunk (the next chunk is fetched into registers while the current
+// one is summed), and the G partial sums are combined in group order.
+// Per sink k and source j (u = x_k - x_j, s^2 = |u|^2 + eps^2; the pair with
+// itself and pairs with s = 0 contribute nothing):
+//   Psi      += src_j.xyz . u / s^3 - src_j.w / s
+//   grad Psi += src_j.xyz / s^3 + (src_j.w / s^3 - 3 (src_j.xyz . u) / s^5) u
+//   tidal    += m_j [tv_k / s^3 - 3 (u . tv_k) u / s^5]
+// written to out[2k] = (grad Psi, Psi) and out[2k+1] = (tidal, 0).
+constexpr int ADJ_WAVES = 4;
+
+__device__ __forceinline__ void adj_pair(const double4& me, const double4& g, const double4& s,
+                                         const double4& gj, bool use, double eps2, double& psi,
+                                         double& px, double& py, double& pz, double& kx, double& ky,
+                                         double& kz) {
+  double ux = me.x - s.x, uy = me.y - s.y, uz = me.z - s.z;
+  double s2 = fma(ux, ux, fma(uy, uy, fma(uz, uz, eps2)));
+  double inv = rsqrt_fp64(s2);
+  inv = (use && s2 > 0.0) ? inv : 0.0;
+  double inv2 = inv * inv, inv3 = inv2 * inv, inv5 = inv3 * inv2;
+  double ugj = fma(ux, gj.x, fma(uy, gj.y, uz * gj.z));
+  psi = fma(ugj, inv3, fma(-gj.w, inv, psi));
+  double c1 = -3.0 * ugj * inv5, c2 = gj.w * inv3;
+  px = fma(gj.x, inv3, fma(c1 + c2, ux, px));
+  py = fma(gj.y, inv3, fma(c1 + c2, uy, py));
+  pz = fma(gj.z, inv3, fma(c1 + c2, uz, pz));
+  double ug = fma(ux, g.x, fma(uy, g.y, uz * g.z));
+  double w3 = s.w * inv3, w5 = -3.0 * s.w * ug * inv5;
+  kx = fma(w3, g.x, fma(w5, ux, kx));
+  ky = fma(w3, g.y, fma(w5, uy, ky));
+  kz = fma(w3, g.z, fma(w5, uz, kz));
+}
+
+__global__ void __launch_bounds__(64 * ADJ_WAVES) k_adj_near(const int* __restrict__ leaves, int nleaves,
+                                                           const int* __restrict__ cb, const int* __restrict__ ce,
+                                                           const int* __restrict__ off,
+                                                           const int* __restrict__ srcl,
+                                                           const double4* __restrict__ pm,
+                                                           const double4* __restrict__ tv,
+                                                           const double4* __restrict__ src, double eps2,
+                                                           double4* __restrict__ out) {
+  __shared__ double4 spm[ADJ_WAVES][64];
+  __shared__ double4 ssrc[ADJ_WAVES][64];
+  __shared__ double rbuf[ADJ_WAVES][7][64];
+  int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  int nblk = (nleaves + ADJ_WAVES - 1) / ADJ_WAVES;
+  int blk = xcd_block();
+  int li = blk * ADJ_WAVES + wv;
+  if (blk >= nblk || li >= nleaves) return;
+  int B = leaves[li];
+  int b = cb[B], e = ce[B];
+  int qb = off[B], qe = off[B + 1];
+  for (int i0 = b; i0 < e; i0 += 64) {
+    int nB = min(64, e - i0);
+    int G = 64 / nB;
+    int g = lane / nB, sl = lane - g * nB;
+    bool act = g < G;
+    int i = i0 + sl;
+    double4 me = pm[i], gk = tv[i];
+    double psi = 0.0, px = 0.0, py = 0.0, pz = 0.0, kx = 0.0, ky = 0.0, kz = 0.0;
+    int q = qb, j0 = 0, je = 0;
+    if (q < qe) {
+      int A = srcl[q];
+      j0 = cb[A];
+      je = ce[A];
+    }
+    double4 cpm = make_double4(0.0, 0.0, 0.0, 0.0), csrc = cpm;
+    if (q < qe && lane < je - j0) {
+      cpm = pm[j0 + lane];
+      csrc = src[j0 + lane];
+    }
+    while (q < qe) {
+      int na = min(64, je - j0);
+      int nq = q, nj0 = j0 + 64, nje = je;
+      if (nj0 >= je) {
+        nq = q + 1;
+        if (nq < qe) {
+          int A = srcl[nq];
+          nj0 = cb[A];
+          nje = ce[A];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      spm[wv][lane] = cpm;
+      ssrc[wv][lane] = csrc;
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the staged chunk is visible to the wave
+      if (nq < qe && lane < nje - nj0) {
+        cpm = pm[nj0 + lane];
+        csrc = src[nj0 + lane];
+      }
+      int tmax = act ? na : 0;
+      int ti = i - j0;  // the sink's own slot when this chunk holds it
+      for (int t = g; t < tmax; t += G)
+        adj_pair(me, gk, spm[wv][t], ssrc[wv][t], t != ti, eps2, psi, px, py, pz, kx, ky, kz);
+      q = nq;
+      j0 = nj0;
+      je = nje;
+    }
+    __builtin_amdgcn_wave_barrier();
+    rbuf[wv][0][lane] = px;
+    rbuf[wv][1][lane] = py;
+    rbuf[wv][2][lane] = pz;
+    rbuf[wv][3][lane] = psi;
+    rbuf[wv][4][lane] = kx;
+    rbuf[wv][5][lane] = ky;
+    rbuf[wv][6][lane] = kz;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    if (g == 0) {
+      double t[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int gg = 0; gg < G; gg++) {
+        int l = gg * nB + sl;
+#pragma unroll
+        for (int r = 0; r < 7; r++) t[r] += rbuf[wv][r][l];
+      }
+      out[2 * (int64_t)i] = make_double4(t[0], t[1], t[2], t[3]);
+      out[2 * (int64_t)i + 1] = make_double4(t[4], t[5], t[6], 0.0);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // One thread per body (sorted order); results in the caller's order.
 // tv[i]: the vector the tidal tensor acts on (ga_i; in the jerk, v_i) and
-// gp_i in .w; src[j]: source dipole -(.xyz) and charge (.w) of body j.
+// gp_i in .w; near[2i], near[2i+1]: the near sums of k_adj_near.
 //   gradient: gpos = T ga - gp a + m grad Psi,  gmass = Psi;
 //   jerk:     jerk = T v + grad Psi.
 template <bool JERK>
 __global__ void __launch_bounds__(256) k_adj_leaf(int p, int64_t n, const int* __restrict__ leaf_of,
-                                                  const int* __restrict__ cb, const int* __restrict__ ce,
-                                                  const int* __restrict__ off, const int* __restrict__ srcl,
                                                   const double* __restrict__ cx, const double* __restrict__ cy,
                                                   const double* __restrict__ cz,
                                                   const double* __restrict__ lfwd,
                                                   const double* __restrict__ ladj,
                                                   const double4* __restrict__ pm,
                                                   const double4* __restrict__ tv,
-                                                  const double4* __restrict__ src,
+                                                  const double4* __restrict__ near,
                                                   const double4* __restrict__ as,
-                                                  const int* __restrict__ perm, double eps2, double* gpos,
+                                                  const int* __restrict__ perm, double* gpos,
                                                   double* gmass) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -271,32 +395,10 @@ __global__ void __launch_bounds__(256) k_adj_leaf(int p, int64_t n, const int* _
   double gx = -(Hxx * g.x + Hxy * g.y + Hxz * g.z);
   double gy = -(Hxy * g.x + Hyy * g.y + Hyz * g.z);
   double gz = -(Hxz * g.x + Hyz * g.y + Hzz * g.z);
-  double psi = -ar[0];
-  double px = ar[2], py = ai[2], pz = -ar[1];
-  // near field, softened pair terms
-  double kx = 0.0, ky = 0.0, kz = 0.0;
-  for (int q = off[B]; q < off[B + 1]; q++) {
-    int A = srcl[q];
-    for (int j = cb[A]; j < ce[A]; j++) {
-      double4 s = pm[j];
-      double ux = me.x - s.x, uy = me.y - s.y, uz = me.z - s.z;
-      double s2 = fma(ux, ux, fma(uy, uy, fma(uz, uz, eps2)));
-      if (j == i || !(s2 > 0.0)) continue;
-      double4 gj = src[j];
-      double inv = rsqrt_fp64(s2), inv2 = inv * inv, inv3 = inv2 * inv, inv5 = inv3 * inv2;
-      double ugj = fma(ux, gj.x, fma(uy, gj.y, uz * gj.z));
-      psi = fma(ugj, inv3, fma(-gj.w, inv, psi));
-      double c1 = -3.0 * ugj * inv5, c2 = gj.w * inv3;
-      px = fma(gj.x, inv3, fma(c1 + c2, ux, px));
-      py = fma(gj.y, inv3, fma(c1 + c2, uy, py));
-      pz = fma(gj.z, inv3, fma(c1 + c2, uz, pz));
-      double ug = fma(ux, g.x, fma(uy, g.y, uz * g.z));
-      double w3 = s.w * inv3, w5 = -3.0 * s.w * ug * inv5;
-      kx = fma(w3, g.x, fma(w5, ux, kx));
-      ky = fma(w3, g.y, fma(w5, uy, ky));
-      kz = fma(w3, g.z, fma(w5, uz, kz));
-    }
-  }
+  double4 na = near[2 * i], nb = near[2 * i + 1];
+  double psi = -ar[0] + na.w;
+  double px = ar[2] + na.x, py = ai[2] + na.y, pz = -ar[1] + na.z;
+  double kx = nb.x, ky = nb.y, kz = nb.z;
   int64_t o = perm[i];
   if constexpr (JERK) {
     gpos[3 * o] = gx - kx + px;
@@ -331,9 +433,14 @@ static void source_pass(Ctx& c, const double4* tv, const double4* src, const dou
   HIPCHK(hipMemsetAsync(c.ladj.p, 0, ne * sizeof(double), s));
   launch_m2l_fp64_buffers(c, nc, c.madj.p, c.ladj.p);
   launch_l2l_buf(c, c.ladj.p);
-  hipLaunchKernelGGL(k_adj_leaf<JERK>, dim3(g), dim3(256), 0, s, c.p, n, c.leaf_of.p, c.c_begin.p, c.c_end.p,
-                     c.p2p.off.p, c.p2p.src.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.loc.p, c.ladj.p, c.pm.p, tv,
-                     src, as, c.idx[0].p, c.eps_soft * c.eps_soft, out3, out1);
+  ensure(c.ws, c.adjnear, 2 * (size_t)n);
+  int nblk = (int)((c.nleaf + ADJ_WAVES - 1) / ADJ_WAVES);
+  hipLaunchKernelGGL(k_adj_near, dim3(xcd_grid(nblk)), dim3(64 * ADJ_WAVES), 0, s, c.leaves.p, (int)c.nleaf,
+                     c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.pm.p, tv, src,
+                     c.eps_soft * c.eps_soft, c.adjnear.p);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_adj_leaf<JERK>, dim3(g), dim3(256), 0, s, c.p, n, c.leaf_of.p, c.c_cx.p, c.c_cy.p,
+                     c.c_cz.p, c.loc.p, c.ladj.p, c.pm.p, tv, c.adjnear.p, as, c.idx[0].p, out3, out1);
   HIPCHK(hipGetLastError());
 }
 

@@ -168,6 +168,7 @@ struct Ctx {
   // forward acceleration, forward outputs of the recomputed pass
   dbuf<double> madj, ladj, fwd_acc, fwd_pot;
   dbuf<double4> gsort, asort;
+  dbuf<double4> adjnear;  // adjoint near sums per sorted body: (grad Psi, Psi), (tidal term, 0)
 
   // walks
   dbuf<int2> front[2];
