@@ -101,6 +101,8 @@ typedef struct {
   double ms_sort;         /* the stable radix sort of the bodies' Morton keys (tree stage) */
   double ms_gather;       /* the gather of positions and masses into sorted order (tree stage) */
   double ms_walk_steps;   /* the acceptance walk alone, before its lists are grouped (walk stage) */
+  int64_t n_p2p_items;    /* near-field work items of the last evaluation: a sink leaf, or one
+                             segment of a leaf's source list when the list is long */
 } fmm_stats_t;
 
 /* export selectors for fmm_export (host buffer, element counts from fmm_stats) */

@@ -235,8 +235,9 @@ __device__ __forceinline__ double rsqrt_fp64(double x) {
   return y;
 }
 
-// Near field of the gradient and jerk operators, one wavefront per sink leaf
-// (the layout of the forward near field): the leaf's bodies are replicated
+// Near field of the gradient and jerk operators, one wavefront per work item of
+// the forward near field's plan (a sink leaf, or one segment of a long list;
+// the same layout as the forward near field): the leaf's bodies are replicated
 // over G = 64 / n_B lane groups, group g takes every G-th body of each source
 // leaf, whose positions and source records are staged in LDS by one coalesced
 // load per chunk (the next chunk is fetched into registers while the current
@@ -246,7 +247,8 @@ __device__ __forceinline__ double rsqrt_fp64(double x) {
 //   Psi      += src_j.xyz . u / s^3 - src_j.w / s
 //   grad Psi += src_j.xyz / s^3 + (src_j.w / s^3 - 3 (src_j.xyz . u) / s^5) u
 //   tidal    += m_j [tv_k / s^3 - 3 (u . tv_k) u / s^5]
-// written to out[2k] = (grad Psi, Psi) and out[2k+1] = (tidal, 0).
+// written to out[2k] = (grad Psi, Psi) and out[2k+1] = (tidal, 0), or for a
+// later segment of a split leaf to its partial slot (added by k_adj_combine).
 constexpr int ADJ_WAVES = 4;
 
 __device__ __forceinline__ void adj_pair(const double4& me, const double4& g, const double4& s,
@@ -271,25 +273,41 @@ __device__ __forceinline__ void adj_pair(const double4& me, const double4& g, co
   kz = fma(w3, g.z, fma(w5, uz, kz));
 }
 
-__global__ void __launch_bounds__(64 * ADJ_WAVES) k_adj_near(const int* __restrict__ leaves, int nleaves,
+__global__ void __launch_bounds__(64 * ADJ_WAVES) k_adj_near(const int* __restrict__ leaves, NfPlan plan,
                                                            const int* __restrict__ cb, const int* __restrict__ ce,
                                                            const int* __restrict__ off,
                                                            const int* __restrict__ srcl,
                                                            const double4* __restrict__ pm,
                                                            const double4* __restrict__ tv,
                                                            const double4* __restrict__ src, double eps2,
-                                                           double4* __restrict__ out) {
+                                                           double4* __restrict__ out,
+                                                           double4* __restrict__ part) {
   __shared__ double4 spm[ADJ_WAVES][64];
   __shared__ double4 ssrc[ADJ_WAVES][64];
   __shared__ double rbuf[ADJ_WAVES][7][64];
   int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  int nblk = (nleaves + ADJ_WAVES - 1) / ADJ_WAVES;
+  int nblk = (plan.max_items + ADJ_WAVES - 1) / ADJ_WAVES;
   int blk = xcd_block();
-  int li = blk * ADJ_WAVES + wv;
-  if (blk >= nblk || li >= nleaves) return;
+  int it = blk * ADJ_WAVES + wv;
+  if (blk >= nblk || it >= plan.max_items) return;
+  int li = it, seg = 0;
+  if (it >= plan.nleaf) {  // a later segment of a long list
+    int x = it - plan.nleaf;
+    if (x >= *plan.nextra) return;
+    int2 v = plan.extra[x];
+    li = v.x;
+    seg = v.y;
+  }
   int B = leaves[li];
+  int nseg = plan.cell_nseg[B];
   int b = cb[B], e = ce[B];
   int qb = off[B], qe = off[B + 1];
+  if (nseg > 1) {  // one segment of a long list (the leaf's bodies fit one wavefront)
+    qb += seg * plan.K;
+    qe = min(qe, qb + plan.K);
+  }
+  bool to_part = seg > 0;  // later segments of a long list: partial slots
+  int64_t pslot = to_part ? (int64_t)plan.cell_pbase[B] + (int64_t)(seg - 1) * (e - b) - b : 0;
   for (int i0 = b; i0 < e; i0 += 64) {
     int nB = min(64, e - i0);
     int G = 64 / nB;
@@ -354,11 +372,41 @@ __global__ void __launch_bounds__(64 * ADJ_WAVES) k_adj_near(const int* __restri
 #pragma unroll
         for (int r = 0; r < 7; r++) t[r] += rbuf[wv][r][l];
       }
-      out[2 * (int64_t)i] = make_double4(t[0], t[1], t[2], t[3]);
-      out[2 * (int64_t)i + 1] = make_double4(t[4], t[5], t[6], 0.0);
+      double4* dst = to_part ? part + 2 * (pslot + i) : out + 2 * (int64_t)i;
+      dst[0] = make_double4(t[0], t[1], t[2], t[3]);
+      dst[1] = make_double4(t[4], t[5], t[6], 0.0);
     }
     __builtin_amdgcn_wave_barrier();
   }
+}
+
+// the partial sums of segments 1..ns-1 of split leaves added, in segment
+// order, to the first segment's sums
+__global__ void k_adj_combine(int64_t n, const int* __restrict__ leaf_of, const int* __restrict__ cb,
+                              const int* __restrict__ ce, const int* __restrict__ cell_nseg,
+                              const int* __restrict__ cell_pbase, const double4* __restrict__ part,
+                              double4* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int B = leaf_of[i];
+  int ns = cell_nseg[B];
+  if (ns <= 1) return;
+  int nB = ce[B] - cb[B];
+  const double4* pp = part + 2 * ((int64_t)cell_pbase[B] + (i - cb[B]));
+  double4 a = out[2 * i], b = out[2 * i + 1];
+  for (int k = 1; k < ns; k++) {
+    const double4* q = pp + 2 * (int64_t)(k - 1) * nB;
+    double4 u = q[0], v = q[1];
+    a.x += u.x;
+    a.y += u.y;
+    a.z += u.z;
+    a.w += u.w;
+    b.x += v.x;
+    b.y += v.y;
+    b.z += v.z;
+  }
+  out[2 * i] = a;
+  out[2 * i + 1] = b;
 }
 
 // One thread per body (sorted order); results in the caller's order.
@@ -433,12 +481,19 @@ static void source_pass(Ctx& c, const double4* tv, const double4* src, const dou
   HIPCHK(hipMemsetAsync(c.ladj.p, 0, ne * sizeof(double), s));
   launch_m2l_fp64_buffers(c, nc, c.madj.p, c.ladj.p);
   launch_l2l_buf(c, c.ladj.p);
+  // the work items of the forward near field of this evaluation
   ensure(c.ws, c.adjnear, 2 * (size_t)n);
-  int nblk = (int)((c.nleaf + ADJ_WAVES - 1) / ADJ_WAVES);
-  hipLaunchKernelGGL(k_adj_near, dim3(xcd_grid(nblk)), dim3(64 * ADJ_WAVES), 0, s, c.leaves.p, (int)c.nleaf,
+  ensure(c.ws, c.adjpart, 2 * (size_t)c.nf.max_slots + 2);
+  int nblk = (c.nf.max_items + ADJ_WAVES - 1) / ADJ_WAVES;
+  hipLaunchKernelGGL(k_adj_near, dim3(xcd_grid(nblk)), dim3(64 * ADJ_WAVES), 0, s, c.leaves.p, c.nf,
                      c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.pm.p, tv, src,
-                     c.eps_soft * c.eps_soft, c.adjnear.p);
+                     c.eps_soft * c.eps_soft, c.adjnear.p, c.adjpart.p);
   HIPCHK(hipGetLastError());
+  if (c.nf.max_slots > 0) {
+    hipLaunchKernelGGL(k_adj_combine, dim3(g), dim3(256), 0, s, n, c.leaf_of.p, c.c_begin.p, c.c_end.p,
+                       c.nf.cell_nseg, c.nf.cell_pbase, c.adjpart.p, c.adjnear.p);
+    HIPCHK(hipGetLastError());
+  }
   hipLaunchKernelGGL(k_adj_leaf<JERK>, dim3(g), dim3(256), 0, s, c.p, n, c.leaf_of.p, c.c_cx.p, c.c_cy.p,
                      c.c_cz.p, c.loc.p, c.ladj.p, c.pm.p, tv, c.adjnear.p, as, c.idx[0].p, out3, out1);
   HIPCHK(hipGetLastError());

@@ -473,6 +473,10 @@ fmm_status fmm_stats(fmm_ctx* ctx, fmm_stats_t* out) {
         HIPCHK(hipMemcpyAsync(c.hbuf, d, 8, hipMemcpyDeviceToHost, c.stream));
         HIPCHK(hipStreamSynchronize(c.stream));
         out->n_p2p_pairs = c.hbuf[0];
+        // the near field's work items: the leaves and the extra segments
+        HIPCHK(hipMemcpyAsync(c.hbuf, c.counters.p + 44, 4, hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(hipStreamSynchronize(c.stream));
+        out->n_p2p_items = (int64_t)c.nleaf + *(const int*)c.hbuf;
       }
     }
     if (c.estimated) {
@@ -920,6 +924,8 @@ void fmm_destroy(fmm_ctx* ctx) {
   rel(c.c_sz); rel(c.c_cx); rel(c.c_cy); rel(c.c_cz); rel(c.c_rad); rel(c.c_rad2bits); rel(c.mult);
   rel(c.pk); rel(c.fcell); rel(c.fmin); rel(c.loc); rel(c.counters); rel(c.scan_tmp);
   rel(c.scan_tmp64);
+  rel(c.adjnear); rel(c.adjpart); rel(c.nf_cell_nseg); rel(c.nf_cell_pbase); rel(c.nf_extra);
+  rel(c.nf_part);
   for (CellList* L : {&c.est_far, &c.est_near, &c.m2l, &c.p2p}) {
     rel(L->raw); rel(L->tmp); rel(L->off); rel(L->src);
   }

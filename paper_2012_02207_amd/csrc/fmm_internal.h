@@ -101,6 +101,26 @@ struct CellList {
   int64_t count = 0;
 };
 
+// ------------------------------------------------------------------ near field
+// Work items of the near-field kernels: item li < nleaf is leaf li of the leaf
+// list (its whole source list, or the first segment of a long one); a leaf
+// whose list is longer than K entries (and whose bodies fit one wavefront) is
+// cut into ceil(len / K) contiguous segments, and segments 1.. are the extra
+// items (leaf, segment) after the leaves, in any order.  The first segment
+// writes the near field itself, segment k > 0 its partial sums to slots
+// cell_pbase[B] + (k - 1) n_B + body; these are added in segment order
+// afterwards, so the result does not depend on the order of the items.
+struct NfPlan {
+  const int* cell_nseg;   // segments of each leaf, by cell id
+  const int* cell_pbase;  // first partial slot of each split leaf, by cell id
+  const int2* extra;      // (leaf index, segment) of the extra items
+  const int* nextra;      // extra item count (device)
+  int nleaf;
+  int K;                  // list entries per segment
+  int max_items;          // host bound on the item count (grid size)
+  int max_slots;          // host bound on the partial slots
+};
+
 // ------------------------------------------------------------------ context
 struct Ctx {
   fmm_params prm{};
@@ -169,6 +189,7 @@ struct Ctx {
   dbuf<double> madj, ladj, fwd_acc, fwd_pot;
   dbuf<double4> gsort, asort;
   dbuf<double4> adjnear;  // adjoint near sums per sorted body: (grad Psi, Psi), (tidal term, 0)
+  dbuf<double4> adjpart;  // their partial sums for split leaves (two records per slot)
 
   // walks
   dbuf<int2> front[2];
@@ -205,6 +226,11 @@ struct Ctx {
   hipStream_t side = nullptr, side2 = nullptr;  // side2: root-level FP64 M2L
   hipEvent_t fork[9] = {};
   dbuf<double4> nearbuf;  // near-field (acc, pot) per sorted body
+  // near-field work items (plan_near_field) and the partial sums of split leaves
+  dbuf<int> nf_cell_nseg, nf_cell_pbase;
+  dbuf<int2> nf_extra;
+  dbuf<double4> nf_part;
+  NfPlan nf{};
 
   // replay of the frozen-tree evaluation as a HIP graph (captured per set of
   // buffers; dropped whenever the tree is rebuilt)
@@ -286,6 +312,7 @@ void launch_m2l_fp64_sinks(Ctx& c, int first_lo, const double* mult, double* loc
 void m2m_levels(Ctx& c, double* mult);
 void launch_l2l_buf(Ctx& c, double* loc);
 void launch_near_field(Ctx& c);
+void plan_near_field(Ctx& c);
 void launch_far_final(Ctx& c, double* acc, double* pot);
 void launch_m2l_mixed_lo(Ctx& c);
 void launch_m2l_mixed_root(Ctx& c, double* loc64);

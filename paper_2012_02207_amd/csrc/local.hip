@@ -5,6 +5,8 @@
 // plain O(N^2) direct sum used for checks.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fmm_device.h"
 
 namespace fmm {
@@ -220,23 +222,41 @@ constexpr int LG_WAVES = 4;
 
 template <bool MIXED>
 __global__ void __launch_bounds__(64 * LG_WAVES) __attribute__((amdgpu_waves_per_eu(MIXED ? 6 : 5))) k_leaf_group(const int* __restrict__ leaves,
-                                                              int nleaves, const int* __restrict__ cb,
+                                                              NfPlan plan, const int* __restrict__ cb,
                                                               const int* __restrict__ ce,
                                                               const int* __restrict__ off,
                                                               const int* __restrict__ srcl,
                                                               const double4* __restrict__ pm,
                                                               double eps2, double4* nearbuf,
+                                                              double4* __restrict__ part,
                                                               unsigned long long* npairs, int gmax) {
   __shared__ double4 sbuf[LG_WAVES][64];
   __shared__ double rbuf[LG_WAVES][4][64];
   int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  int nblk = (nleaves + LG_WAVES - 1) / LG_WAVES;
+  int nblk = (plan.max_items + LG_WAVES - 1) / LG_WAVES;
   int blk = xcd_block();
-  int li = blk * LG_WAVES + wv;
-  if (blk >= nblk || li >= nleaves) return;
+  int it = blk * LG_WAVES + wv;
+  if (blk >= nblk || it >= plan.max_items) return;
+  int li = it, seg = 0;
+  if (it >= plan.nleaf) {  // a later segment of a long list
+    int x = it - plan.nleaf;
+    if (x >= *plan.nextra) return;
+    int2 v = plan.extra[x];
+    li = v.x;
+    seg = v.y;
+  }
   int B = leaves[li];
+  int nseg = plan.cell_nseg[B];
   int b = cb[B], e = ce[B];
   int qb = off[B], qe = off[B + 1];
+  if (nseg > 1) {  // one segment of a long list (the leaf's bodies fit one wavefront)
+    qb += seg * plan.K;
+    qe = min(qe, qb + plan.K);
+  }
+  // output: the near field itself (a whole list, or the first segment of a
+  // long one), or the partial sums of a later segment
+  bool to_part = seg > 0;
+  int64_t pslot = to_part ? (int64_t)plan.cell_pbase[B] + (int64_t)(seg - 1) * (e - b) - b : 0;
   float eps2f = (float)eps2;
   long long pairs = 0;  // body pairs of this leaf (self pairs excluded), wave-uniform
   for (int i0 = b; i0 < e; i0 += 64) {
@@ -349,11 +369,83 @@ __global__ void __launch_bounds__(64 * LG_WAVES) __attribute__((amdgpu_waves_per
         tz += rbuf[wv][2][l];
         tp += rbuf[wv][3][l];
       }
-      nearbuf[i] = make_double4(tx, ty, tz, tp);
+      if (to_part)
+        part[pslot + i] = make_double4(tx, ty, tz, tp);
+      else
+        nearbuf[i] = make_double4(tx, ty, tz, tp);
     }
     __builtin_amdgcn_wave_barrier();
   }
   if (lane == 0 && pairs > 0) atomicAdd(npairs, (unsigned long long)pairs);
+}
+
+// Near-field work items (the plan above), one thread per leaf; ctr[0] counts
+// the extra items and ctr[1] the partial slots (both zero on entry).
+constexpr int NF_SEG_MIN = 256;    // list entries per segment, at least
+constexpr int NF_SEG_DIV = 8192;   // and at least the list total / NF_SEG_DIV
+
+__global__ void k_nf_plan(const int* __restrict__ leaves, int nleaf, const int* __restrict__ cb,
+                          const int* __restrict__ ce, const int* __restrict__ off, int K, int* cell_nseg,
+                          int* cell_pbase, int2* extra, int* ctr) {
+  int li = blockIdx.x * blockDim.x + threadIdx.x;
+  if (li >= nleaf) return;
+  int B = leaves[li];
+  int len = off[B + 1] - off[B], nB = ce[B] - cb[B];
+  int ns = (nB <= 64 && len > K) ? (len + K - 1) / K : 1;
+  cell_nseg[B] = ns;
+  if (ns > 1) {
+    int x = atomicAdd(ctr, ns - 1);
+    for (int k = 1; k < ns; k++) extra[x + k - 1] = make_int2(li, k);
+    cell_pbase[B] = atomicAdd(ctr + 1, (ns - 1) * nB);
+  }
+}
+
+// the partial sums of segments 1..ns-1 of split leaves added, in segment
+// order, to the first segment's sums
+__global__ void k_nf_combine(int64_t n, const int* __restrict__ leaf_of, const int* __restrict__ cb,
+                             const int* __restrict__ ce, const int* __restrict__ cell_nseg,
+                             const int* __restrict__ cell_pbase, const double4* __restrict__ part,
+                             double4* nearbuf) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int B = leaf_of[i];
+  int ns = cell_nseg[B];
+  if (ns <= 1) return;
+  int nB = ce[B] - cb[B];
+  const double4* pp = part + cell_pbase[B] + (i - cb[B]);
+  double4 t = nearbuf[i];
+  for (int k = 1; k < ns; k++) {
+    double4 v = pp[(size_t)(k - 1) * nB];
+    t.x += v.x;
+    t.y += v.y;
+    t.z += v.z;
+    t.w += v.w;
+  }
+  nearbuf[i] = t;
+}
+
+// Builds c.nf for the current leaves and near-field list (on c.stream; the
+// counters at c.counters[44..45] are cleared by the caller).
+void plan_near_field(Ctx& c) {
+  int nleaf = (int)c.nleaf;
+  int64_t cnt = c.p2p.count;
+  int K = (int)std::max<int64_t>(NF_SEG_MIN, ceil_div(cnt, NF_SEG_DIV));
+  // a split leaf holds len > K entries in ceil(len / K) < 2 len / K items, so
+  // extra items number fewer than cnt / K <= NF_SEG_DIV; its partial slots,
+  // (ceil(len / K) - 1) n_B < 64 len / K, fewer than 64 cnt / K in all
+  int64_t extra_max = std::min<int64_t>(NF_SEG_DIV, ceil_div(cnt, K));
+  int64_t slot_max = std::min<int64_t>(64 * (int64_t)NF_SEG_DIV, ceil_div(64 * cnt, K));
+  ensure(c.ws, c.nf_cell_nseg, (size_t)c.ncell);
+  ensure(c.ws, c.nf_cell_pbase, (size_t)c.ncell);
+  ensure(c.ws, c.nf_extra, (size_t)extra_max + 1);
+  ensure(c.ws, c.nf_part, (size_t)slot_max + 1);
+  int* ctr = c.counters.p + 44;
+  hipLaunchKernelGGL(k_nf_plan, dim3((unsigned)ceil_div(nleaf, 256)), dim3(256), 0, c.stream, c.leaves.p, nleaf,
+                     c.c_begin.p, c.c_end.p, c.p2p.off.p, K, c.nf_cell_nseg.p, c.nf_cell_pbase.p, c.nf_extra.p,
+                     ctr);
+  HIPCHK(hipGetLastError());
+  c.nf = NfPlan{c.nf_cell_nseg.p, c.nf_cell_pbase.p, c.nf_extra.p, ctr, nleaf, K, (int)(nleaf + extra_max),
+                (int)slot_max};
 }
 
 // Near field of every body into c.nearbuf (sorted order), on c.stream.
@@ -362,21 +454,29 @@ void launch_near_field(Ctx& c) {
   ensure(c.ws, c.nearbuf, (size_t)c.n);
   const int* leaves = c.leaves.p;
   // body-pair count of the near field, read by fmm_stats
+  // counters[40..41]: the body-pair count; [44], [45]: the plan's counts
   unsigned long long* npairs = (unsigned long long*)(c.counters.p + 40);
-  zero_fill(c, npairs, sizeof(unsigned long long));
-  int nblk = (int)((c.nleaf + LG_WAVES - 1) / LG_WAVES);
+  zero_fill(c, npairs, 6 * sizeof(int));
+  plan_near_field(c);
+  int nblk = (c.nf.max_items + LG_WAVES - 1) / LG_WAVES;
   unsigned grid = xcd_grid(nblk);
   double e2 = c.eps_soft * c.eps_soft;
   int gmax = c.prm.p2p_groups;
   if (c.prm.precision == FMM_MIXED)
-    hipLaunchKernelGGL(k_leaf_group<true>, dim3(grid), dim3(64 * LG_WAVES), 0, c.stream, leaves, (int)c.nleaf,
-                       c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.pm.p, e2, c.nearbuf.p, npairs,
-                       gmax);
+    hipLaunchKernelGGL(k_leaf_group<true>, dim3(grid), dim3(64 * LG_WAVES), 0, c.stream, leaves, c.nf,
+                       c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.pm.p, e2, c.nearbuf.p,
+                       c.nf_part.p, npairs, gmax);
   else
-    hipLaunchKernelGGL(k_leaf_group<false>, dim3(grid), dim3(64 * LG_WAVES), 0, c.stream, leaves, (int)c.nleaf,
-                       c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.pm.p, e2, c.nearbuf.p, npairs,
-                       gmax);
+    hipLaunchKernelGGL(k_leaf_group<false>, dim3(grid), dim3(64 * LG_WAVES), 0, c.stream, leaves, c.nf,
+                       c.c_begin.p, c.c_end.p, c.p2p.off.p, c.p2p.src.p, c.pm.p, e2, c.nearbuf.p,
+                       c.nf_part.p, npairs, gmax);
   HIPCHK(hipGetLastError());
+  if (c.nf.max_slots > 0) {
+    hipLaunchKernelGGL(k_nf_combine, dim3((unsigned)ceil_div(c.n, 256)), dim3(256), 0, c.stream, c.n,
+                       c.leaf_of.p, c.c_begin.p, c.c_end.p, c.nf_cell_nseg.p, c.nf_cell_pbase.p, c.nf_part.p,
+                       c.nearbuf.p);
+    HIPCHK(hipGetLastError());
+  }
 }
 
 // Far field by L2P (the leaf's local expansion shifted to the body:

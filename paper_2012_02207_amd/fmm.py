@@ -56,7 +56,7 @@ class Stats(C.Structure):
                 ("ms_walk", C.c_double), ("ms_m2l", C.c_double), ("ms_local", C.c_double),
                 ("ms_p2p", C.c_double), ("ms_total", C.c_double), ("workspace_bytes", C.c_size_t),
                 ("nsys", C.c_int64), ("ms_m2l_kernel", C.c_double), ("ms_sort", C.c_double),
-                ("ms_gather", C.c_double), ("ms_walk_steps", C.c_double)]
+                ("ms_gather", C.c_double), ("ms_walk_steps", C.c_double), ("n_p2p_items", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -48,34 +48,47 @@ def test_gpu_tables_equal_oracle_tables():
     assert np.array_equal(fa, oracle.factorials())
 
 
+def _check_layout(tmp_path, cname, pystruct):
+    """field names, offsets and size of the C struct `cname` (include/fmm.h, as
+    the C compiler lays it out) against the ctypes structure"""
+    import ctypes
+    import shutil
+    import subprocess
+    import pytest
+    txt = open(os.path.join(ROOT, "include", "fmm.h")).read()
+    body = txt.split("} " + cname + ";")[0].rsplit("typedef struct {", 1)[1]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = []
+    for decl in re.findall(r"\b(?:int|int64_t|int32_t|double|size_t)\s+([a-z_0-9, ]+);", body):
+        names += [d.strip() for d in decl.split(",")]
+    assert [f[0] for f in pystruct._fields_] == names
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / f"layout_{cname}.c"
+    prints = "".join(f'  printf("%zu\\n", offsetof({cname}, {n}));\n' for n in names)
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"fmm.h\"\n"
+                   f"int main(void) {{\n{prints}  printf(\"%zu\\n\", sizeof({cname}));\n"
+                   "  return 0;\n}\n")
+    exe = tmp_path / f"layout_{cname}"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert got == [getattr(pystruct, n).offset for n in names] + [ctypes.sizeof(pystruct)]
+
+
 def test_params_layout_matches_header(tmp_path):
     """The Python Params structure has the field names, offsets and size of
     fmm_params as the C compiler lays it out from include/fmm.h, and
     fmm_default_params (host code only) fills the defaults the header states."""
-    import ctypes
-    import shutil
-    import subprocess
     from paper_2012_02207_amd import fmm
-    txt = open(os.path.join(ROOT, "include", "fmm.h")).read()
-    body = txt.split("typedef struct {", 1)[1].split("} fmm_params;")[0]
-    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
-    names = re.findall(r"\b(?:int|double)\s+([a-z_0-9]+)\s*;", body)
-    assert [f[0] for f in fmm.Params._fields_] == names
-    cc = shutil.which("gcc") or shutil.which("cc")
-    if cc is None:
-        import pytest
-        pytest.skip("no C compiler")
-    src = tmp_path / "layout.c"
-    prints = "".join(f'  printf("%zu\\n", offsetof(fmm_params, {n}));\n' for n in names)
-    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"fmm.h\"\n"
-                   f"int main(void) {{\n{prints}  printf(\"%zu\\n\", sizeof(fmm_params));\n"
-                   "  return 0;\n}\n")
-    exe = tmp_path / "layout"
-    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
-    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
-                                          text=True).stdout.split()]
-    want = [getattr(fmm.Params, n).offset for n in names] + [ctypes.sizeof(fmm.Params)]
-    assert got == want
+    _check_layout(tmp_path, "fmm_params", fmm.Params)
     p = fmm.default_params()
     assert (p.p, p.err_tol, p.theta, p.theta_est, p.n_leaf) == (10, 1e-7, 1.0, 1.0, 64)
     assert (p.check_inputs, p.root_levels, p.m2l_waves, p.p2p_groups, p.p2p_start) == (0, 3, 1, 0, 0)
+
+
+def test_stats_layout_matches_header(tmp_path):
+    """The same for fmm_stats_t and the Python Stats structure."""
+    from paper_2012_02207_amd import fmm
+    _check_layout(tmp_path, "fmm_stats_t", fmm.Stats)

@@ -364,3 +364,36 @@ def test_tuning_knobs(fmm, m2l_waves, p2p_groups, p2p_start):
         fmm.FMM(p2p_groups=65)
     with pytest.raises(fmm.FmmError):
         fmm.FMM(p2p_start=2)
+
+
+def test_near_field_segments(fmm):
+    """Long near-field lists are cut into segments summed by separate
+    wavefronts, whose partial sums are added in segment order.  At N = 4096
+    nearly every leaf's list is longer than the 64-entry segment, so the
+    evaluation has more work items than leaves; the body-pair count equals
+    the oracle's (every list entry summed exactly once), the forces stay
+    within the FP64 (mixed) bound of the oracle, and repeated calls agree bit
+    for bit."""
+    pos, _, mass = W.plummer(4096, 77)
+    print("[gpu] near-field segments N=4096 p=10", flush=True)
+    o = oracle.Oracle()
+    oacc, _ = o.run(pos, mass, p=10, err_tol=1e-7, n_leaf=64)
+    pp = o.get("p2p")
+    size = o.get("cell_end") - o.get("cell_begin")
+    want_pairs = int((size[pp[:, 0]] * size[pp[:, 1]]).sum()) - len(mass)
+    for precision in ("fp64", "mixed"):
+        f = fmm.FMM(p=10, err_tol=1e-7, n_leaf=64, precision=precision)
+        acc, _ = f.forces(_dev(pos), _dev(mass))
+        acc = acc.cpu().numpy()
+        st = f.stats()
+        print(precision, "items", st["n_p2p_items"], "leaves", st["nleaf"], "pairs", st["n_p2p_pairs"], flush=True)
+        assert st["n_p2p_items"] > st["nleaf"]
+        assert st["n_p2p_pairs"] == want_pairs
+        rel = np.linalg.norm(acc - oacc, axis=1) / np.linalg.norm(oacc, axis=1)
+        if precision == "fp64":
+            assert np.median(rel) <= 1e-12 and rel.max() <= 1e-9, (np.median(rel), rel.max())
+        else:
+            assert np.median(rel) <= MIXED_MEDIAN_BOUND, np.median(rel)
+        a2, _ = f.forces(_dev(pos), _dev(mass))
+        assert np.array_equal(acc, a2.cpu().numpy())
+        f.close()
