@@ -326,7 +326,9 @@ def run_rollout(args):
     """The differentiable rollout: Plummer N = 2^18, 64 kick-drift-kick steps
     (dt = 1e-3), L = sum |x_T - target|^2 with seeded targets x_0 + 0.01 N(0, 1),
     gradients dL/dx_0, dL/dv_0, dL/dm through the FMM adjoint with checkpoints
-    every 8 steps (forces of a segment recomputed in the backward pass).  One
+    every 8 steps (forces of a segment recomputed in the backward pass, on one
+    context per step of the segment and one for the initial forces, so that
+    each adjoint reuses its step's tree, lists and expansions).  One
     step of the benchmark = one forward rollout plus its full gradient.  The
     gradient is checked against central differences (h = 1e-6) on 32 seeded
     coordinates of x_0, with every force evaluation of the perturbed rollouts
@@ -341,11 +343,11 @@ def run_rollout(args):
     target = pos + 0.01 * rng.normal(size=pos.shape)
     dev = torch.device("cuda:0")
     P, V, M, T = (torch.from_numpy(a).to(dev) for a in (pos, vel, mass, target))
-    solver = R.make_solver(p=p, err_tol=err_tol, n_leaf=args.n_leaf)
+    ctxs = [R.make_solver(p=p, err_tol=err_tol, n_leaf=args.n_leaf) for _ in range(every + 1)]
 
     def step():
         x0, v0, m = (a.clone().requires_grad_(True) for a in (P, V, M))
-        xT, _ = R.leapfrog(x0, v0, m, solver, dt, nsteps, checkpoint_every=every)
+        xT, _ = R.leapfrog(x0, v0, m, ctxs, dt, nsteps, checkpoint_every=every)
         loss = ((xT - T) ** 2).sum()
         loss.backward()
         return loss.item(), x0.grad, v0.grad, m.grad
@@ -364,7 +366,7 @@ def run_rollout(args):
     with torch.no_grad():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        xT, _ = R.leapfrog(P, V, M, solver, dt, nsteps, checkpoint_every=0)
+        xT, _ = R.leapfrog(P, V, M, ctxs[0], dt, nsteps, checkpoint_every=0)
         torch.cuda.synchronize()
         t_fwd = time.perf_counter() - t0
     # finite differences with frozen lists
@@ -385,7 +387,7 @@ def run_rollout(args):
         fd = (loss_frozen(P + e) - loss_frozen(P - e)) / (2 * h)
         rels.append(abs(fd - gxn[k, d]) / max(abs(fd), 1e-300))
         note(f"finite difference {len(rels)}/32: rel {rels[-1]:.2e}")
-    for s_ in solvers:
+    for s_ in solvers + ctxs:
         s_.close()
     rels = np.array(rels)
     out = {
@@ -406,7 +408,6 @@ def run_rollout(args):
         "finite_difference_check": {"coords": 32, "h": h, "median_rel": float(np.median(rels)),
                                     "max_rel": float(rels.max())},
     }
-    solver.close()
     print(json.dumps(out))
 
 

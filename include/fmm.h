@@ -211,6 +211,21 @@ fmm_status fmm_adjoint(fmm_ctx* ctx, int64_t n, const double* pos, const double*
                        int p, double err_tol, const double* gacc, const double* gpot, double* gpos,
                        double* gmass, void* stream);
 
+/* fmm_adjoint without its forward pass, for callers that keep the forward
+ * evaluation (a rollout's backward pass): the same gradient at the positions
+ * and masses of the context's last evaluation, whose tree, interaction lists,
+ * local expansions and near-field work items are reused.  That evaluation
+ * must be one system of n bodies in FP64 precision (fmm_forces,
+ * fmm_forces_frozen, fmm_forces_frozen_graph, fmm_adjoint or fmm_jerk;
+ * fmm_forces_noalloc leaves this state alone).  acc (n x 3, device, caller
+ * order) is the acceleration that evaluation returned.  gacc, gpot, gpos and
+ * gmass as in fmm_adjoint; the result equals fmm_adjoint's at the same inputs
+ * bit for bit.  Errors: a null pointer or n < 1 -> FMM_EINVAL; no such
+ * evaluation (none yet, another n, a batch, mixed or direct precision, or a
+ * tree built since) -> FMM_ENOTBUILT. */
+fmm_status fmm_adjoint_last(fmm_ctx* ctx, int64_t n, const double* acc, const double* gacc,
+                            const double* gpot, double* gpos, double* gmass, void* stream);
+
 /* Forces and their time derivative along the motion (the jerk, for
  * fourth-order Hermite integrators; section 5 of the paper):
  * jerk_k = sum_j m_j [w / s^3 - 3 (u . w) u / s^5], u = x_j - x_k,

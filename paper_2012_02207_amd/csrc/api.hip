@@ -295,6 +295,7 @@ static fmm_status common_checks(fmm_ctx* ctx, int64_t n, const double* pos, cons
 
 static void run_build(Ctx& c, int64_t n, const double* pos, const double* mass) {
   c.built = c.estimated = c.walked = c.evaluated = false;
+  c.adjoint_ready = false;
   c.graph_valid = false;
   build_tree(c, n, pos, mass);
   if (c.have_events) HIPCHK(hipEventRecord(c.ev[1], c.stream));
@@ -359,6 +360,7 @@ static fmm_status forces_on(fmm_ctx* ctx, Ctx& c, int64_t nsys, const int64_t* o
   return guarded(ctx, [&]() {
     c.stream = (hipStream_t)stream;
     c.err.clear();
+    c.adjoint_ready = false;
     c.p = p;
     c.err_tol = err_tol;
     c.eps_soft = eps_soft;
@@ -382,6 +384,7 @@ static fmm_status forces_on(fmm_ctx* ctx, Ctx& c, int64_t nsys, const int64_t* o
     c.walked = true;
     evaluate(c, acc, pot, true);
     c.evaluated = true;
+    c.adjoint_ready = c.prm.precision == FMM_FP64 && nsys == 1;
     HIPCHK(hipEventRecord(c.ev[8], c.stream));
     return FMM_OK;
   });
@@ -629,6 +632,7 @@ fmm_status fmm_forces_frozen(fmm_ctx* ctx, int64_t n, const double* pos, const d
     c.eps_soft = eps_soft;
     c.have_events = true;
     run_frozen(c, pos, mass, acc, pot);
+    c.adjoint_ready = c.prm.precision == FMM_FP64 && c.nsys == 1;
     return FMM_OK;
   });
 }
@@ -674,6 +678,7 @@ fmm_status fmm_forces_frozen_graph(fmm_ctx* ctx, int64_t n, const double* pos, c
       c.graph_valid = true;
     }
     HIPCHK(hipGraphLaunch(c.gexec, c.stream));
+    c.adjoint_ready = c.prm.precision == FMM_FP64 && c.nsys == 1;
     return FMM_OK;
   });
 }
@@ -702,6 +707,22 @@ fmm_status fmm_adjoint(fmm_ctx* ctx, int64_t n, const double* pos, const double*
     });
   c.prm = saved;
   return st;
+}
+
+fmm_status fmm_adjoint_last(fmm_ctx* ctx, int64_t n, const double* acc, const double* gacc,
+                            const double* gpot, double* gpos, double* gmass, void* stream) {
+  if (!ctx || !acc || !gacc || !gpos || !gmass || n < 1) return FMM_EINVAL;
+  Ctx& c = ctx->c;
+  if (!c.evaluated || !c.adjoint_ready || c.n != n) {
+    c.err = "fmm_adjoint_last: the last evaluation was not one FP64 system of this many bodies";
+    return FMM_ENOTBUILT;
+  }
+  return guarded(ctx, [&]() {
+    c.stream = (hipStream_t)stream;
+    c.err.clear();
+    adjoint_pass(c, gacc, gpot, acc, gpos, gmass);
+    return FMM_OK;
+  });
 }
 
 fmm_status fmm_jerk(fmm_ctx* ctx, int64_t n, const double* pos, const double* vel, const double* mass,

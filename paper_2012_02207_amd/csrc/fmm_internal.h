@@ -134,6 +134,9 @@ struct Ctx {
   double err_tol = 0;
   double eps_soft = 0;
   bool built = false, estimated = false, walked = false, evaluated = false;
+  // the last evaluation was one FP64 system: its tree, lists, local
+  // expansions and near-field plan serve fmm_adjoint_last
+  bool adjoint_ready = false;
 
   // bodies (sorted order)
   dbuf<uint64_t> key[2];

@@ -26,8 +26,8 @@ EXPORTS = dict(keys=(0, np.uint64), perm=(1, np.int32), cell_level=(2, np.int32)
                rootbox=(21, np.float64))
 SYMBOLS = ["fmm_default_params", "fmm_create", "fmm_set_params", "fmm_get_params", "fmm_build", "fmm_forces",
            "fmm_forces_noalloc", "fmm_forces_batch", "fmm_forces_frozen",
-           "fmm_forces_frozen_graph", "fmm_autotune", "fmm_adjoint", "fmm_jerk",
-           "fmm_stats", "fmm_export", "fmm_set_workspace_limit",
+           "fmm_forces_frozen_graph", "fmm_autotune", "fmm_adjoint", "fmm_adjoint_last",
+           "fmm_jerk", "fmm_stats", "fmm_export", "fmm_set_workspace_limit",
            "fmm_direct", "fmm_strerror", "fmm_last_error", "fmm_destroy"]
 
 
@@ -89,6 +89,7 @@ def load_library():
     lib.fmm_forces_frozen.argtypes = [P, C.c_int64, P, P, C.c_double, P, P, P]
     lib.fmm_forces_frozen_graph.argtypes = [P, C.c_int64, P, P, C.c_double, P, P, P]
     lib.fmm_adjoint.argtypes = [P, C.c_int64, P, P, C.c_double, C.c_int, C.c_double, P, P, P, P, P]
+    lib.fmm_adjoint_last.argtypes = [P, C.c_int64, P, P, P, P, P, P]
     lib.fmm_stats.argtypes = [P, C.POINTER(Stats)]
     lib.fmm_export.argtypes = [P, C.c_int, P, C.c_size_t]
     lib.fmm_set_workspace_limit.argtypes = [P, C.c_size_t]
@@ -99,8 +100,8 @@ def load_library():
     lib.fmm_last_error.restype = C.c_char_p
     lib.fmm_destroy.argtypes = [P]
     for f in ("fmm_create", "fmm_set_params", "fmm_get_params", "fmm_build", "fmm_forces", "fmm_forces_noalloc", "fmm_forces_batch",
-              "fmm_forces_frozen", "fmm_forces_frozen_graph", "fmm_autotune", "fmm_adjoint", "fmm_jerk", "fmm_stats", "fmm_export", "fmm_set_workspace_limit",
-              "fmm_direct"):
+              "fmm_forces_frozen", "fmm_forces_frozen_graph", "fmm_autotune", "fmm_adjoint", "fmm_adjoint_last", "fmm_jerk", "fmm_stats", "fmm_export",
+              "fmm_set_workspace_limit", "fmm_direct"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -166,6 +167,9 @@ class FMM:
             raise FmmError(st)
         self._h = h
         self.n = 0
+        # calls that changed the context's tree and expansions; fmm_adjoint_last
+        # needs the state of the latest one
+        self.evals = 0
 
     def close(self):
         if getattr(self, "_h", None):
@@ -206,6 +210,7 @@ class FMM:
         self._check(self._lib.fmm_build(self._h, n, _dev_ptr(pos, torch.float64, (n, 3), "pos"),
                                         _dev_ptr(mass, torch.float64, (n,), "mass"), _stream()))
         self.n = n
+        self.evals += 1
 
     def forces(self, pos, mass, eps_soft=0.0, p=None, err_tol=None, out=None, noalloc=False):
         """acc (n, 3) and pot (n,) as new (or given) float64 device tensors.
@@ -228,6 +233,7 @@ class FMM:
             _stream()))
         if not noalloc:  # the allocation-free call leaves the context's exports alone
             self.n = n
+            self.evals += 1
             self.last_p = int(self.params.p if p is None else p)
         return acc, pot
 
@@ -253,6 +259,7 @@ class FMM:
             _dev_ptr(acc, torch.float64, (n, 3), "acc"), _dev_ptr(pot, torch.float64, (n,), "pot"),
             _stream()))
         self.n = n
+        self.evals += 1
         self.last_p = int(self.params.p if p is None else p)
         return acc, pot
 
@@ -274,6 +281,7 @@ class FMM:
             float(self.params.err_tol if err_tol is None else err_tol),
             _dev_ptr(acc, torch.float64, (n, 3), "acc"), _dev_ptr(pot, torch.float64, (n,), "pot"),
             _stream(), C.byref(chosen)))
+        self.evals += 1
         self.params = self.get_params()
         return chosen.value
 
@@ -299,6 +307,7 @@ class FMM:
             _dev_ptr(mass, torch.float64, (n,), "mass"), float(eps_soft),
             _dev_ptr(acc, torch.float64, (n, 3), "acc"), _dev_ptr(pot, torch.float64, (n,), "pot"),
             _stream()))
+        self.evals += 1
         return acc, pot
 
     def jerk(self, pos, vel, mass, eps_soft=0.0, p=None, err_tol=None):
@@ -316,6 +325,7 @@ class FMM:
             _dev_ptr(acc, torch.float64, (n, 3), "acc"), _dev_ptr(pot, torch.float64, (n,), "pot"),
             _dev_ptr(jerk, torch.float64, (n, 3), "jerk"), _stream()))
         self.n = n
+        self.evals += 1
         return acc, pot, jerk
 
     def adjoint(self, pos, mass, gacc, gpot=None, eps_soft=0.0, p=None, err_tol=None):
@@ -335,6 +345,24 @@ class FMM:
             _dev_ptr(gpos, torch.float64, (n, 3), "gpos"), _dev_ptr(gmass, torch.float64, (n,), "gmass"),
             _stream()))
         self.n = n
+        self.evals += 1
+        return gpos, gmass
+
+    def adjoint_last(self, acc, gacc, gpot=None):
+        """(dL/dpos, dL/dmass) at the positions and masses of this context's last
+        evaluation (one FP64 system; acc is the acceleration it returned), reusing
+        its tree, lists and expansions (fmm_adjoint_last): fmm_adjoint's result
+        without its forward pass."""
+        torch = _torch()
+        n = acc.shape[0]
+        gpos = torch.empty((n, 3), dtype=torch.float64, device=acc.device)
+        gmass = torch.empty((n,), dtype=torch.float64, device=acc.device)
+        gp = None if gpot is None else _dev_ptr(gpot, torch.float64, (n,), "gpot")
+        self._check(self._lib.fmm_adjoint_last(
+            self._h, n, _dev_ptr(acc, torch.float64, (n, 3), "acc"),
+            _dev_ptr(gacc, torch.float64, (n, 3), "gacc"), gp,
+            _dev_ptr(gpos, torch.float64, (n, 3), "gpos"), _dev_ptr(gmass, torch.float64, (n,), "gmass"),
+            _stream()))
         return gpos, gmass
 
     def stats(self):

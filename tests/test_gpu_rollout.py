@@ -50,6 +50,37 @@ def test_force_adjoint_matches_direct_sum(fmm, eps_soft, p, tol):
     f.close()
 
 
+def test_adjoint_last_equals_adjoint(fmm):
+    """fmm_adjoint_last (the forward evaluation kept) gives fmm_adjoint's
+    gradient bit for bit, with and without softening, and refuses a context
+    whose last evaluation was none, mixed precision or another body count."""
+    pos, _, mass = W.plummer(4096, 123)
+    rng = np.random.default_rng(5)
+    ga, gp = rng.normal(size=(4096, 3)), rng.normal(size=4096)
+    print("[gpu] adjoint_last N=4096", flush=True)
+    f = fmm.FMM(p=10, err_tol=1e-7, n_leaf=64)
+    g = fmm.FMM(p=10, err_tol=1e-7, n_leaf=64)
+    with pytest.raises(fmm.FmmError):
+        f.adjoint_last(_dev(np.zeros((4096, 3))), _dev(ga), _dev(gp))
+    for eps in (0.0, 0.01):
+        acc, _ = f.forces(_dev(pos), _dev(mass), eps_soft=eps)
+        gx1, gm1 = f.adjoint_last(acc, _dev(ga), _dev(gp))
+        gx0, gm0 = g.adjoint(_dev(pos), _dev(mass), _dev(ga), _dev(gp), eps_soft=eps)
+        assert torch.equal(gx1, gx0) and torch.equal(gm1, gm0)
+        gx1, _ = f.adjoint_last(acc, _dev(ga))
+        gx0, _ = g.adjoint(_dev(pos), _dev(mass), _dev(ga), None, eps_soft=eps)
+        assert torch.equal(gx1, gx0)
+    f.forces(_dev(pos[:4000]), _dev(mass[:4000]))
+    with pytest.raises(fmm.FmmError):
+        f.adjoint_last(acc, _dev(ga), _dev(gp))
+    f.set_params(precision="mixed")
+    f.forces(_dev(pos), _dev(mass))
+    with pytest.raises(fmm.FmmError):
+        f.adjoint_last(acc, _dev(ga), _dev(gp))
+    f.close()
+    g.close()
+
+
 def _rollout_case(n, seed):
     pos, vel, mass = W.plummer(n, seed)
     rng = np.random.default_rng(seed + 1)
@@ -75,6 +106,16 @@ def test_rollout_gradient_matches_direct_sum_rollout(fmm):
     for g, r in ((x0.grad, gx), (v0.grad, gv), (m.grad, gm)):
         g = g.cpu().numpy()
         assert np.linalg.norm(g - r) <= 1e-6 * np.linalg.norm(r), np.linalg.norm(g - r) / np.linalg.norm(r)
+    # one context per step of a segment (and one for the initial forces): the
+    # adjoints reuse the kept evaluations, and the gradient is the same bit for bit
+    ctxs = [R.make_solver(p=10, err_tol=1e-9) for _ in range(9)]
+    x1, v1, m1 = (_dev(a).requires_grad_(True) for a in (pos, vel, mass))
+    xT1, _ = R.leapfrog(x1, v1, m1, ctxs, dt, steps, checkpoint_every=8)
+    ((xT1 - _dev(target)) ** 2).sum().backward()
+    for a, b in ((x0.grad, x1.grad), (v0.grad, v1.grad), (m.grad, m1.grad)):
+        assert torch.equal(a, b)
+    for c in ctxs:
+        c.close()
     solver.close()
 
 

@@ -56,3 +56,56 @@ def test_autograd_gradient_equals_reverse_mode_reference(every):
     assert np.isclose(loss.item(), L, rtol=1e-13)
     for g, r in ((x0.grad, gx), (v0.grad, gv), (m.grad, gm)):
         assert np.allclose(g.numpy(), r, rtol=1e-10, atol=1e-13 * np.abs(r).max())
+
+
+class ReuseSolver(DirectSolver):
+    """DirectSolver with the context's evaluation counter and adjoint_last: the
+    adjoint at the positions of its last evaluation (counted when used)."""
+
+    def __init__(self):
+        self.evals = 0
+        self.reused = self.recomputed = 0
+        self._last = None
+
+    def forces(self, pos, mass, eps_soft=0.0):
+        self.evals += 1
+        self._last = (pos.clone(), mass.clone(), eps_soft)
+        return super().forces(pos, mass, eps_soft)
+
+    def adjoint(self, pos, mass, gacc, gpot=None, eps_soft=0.0):
+        self.evals += 1  # the GPU adjoint re-evaluates the forward pass
+        self.recomputed += 1
+        self._last = (pos.clone(), mass.clone(), eps_soft)
+        return super().adjoint(pos, mass, gacc, gpot, eps_soft)
+
+    def adjoint_last(self, acc, gacc, gpot=None):
+        self.reused += 1
+        pos, mass, eps = self._last
+        return super().adjoint(pos, mass, gacc, gpot, eps)
+
+
+@pytest.mark.parametrize("every,nctx", [(3, 4), (3, 1), (2, 3), (0, 2)])
+def test_per_step_contexts_reuse_the_forward_state(every, nctx):
+    """With one context per step of a checkpoint segment (and one for the
+    initial forces) every adjoint reuses its step's evaluation, and the
+    gradient is still the reverse-mode reference; with fewer contexts, stale
+    ones fall back to the recomputing adjoint and give the same gradient.
+    (The last step's forces do not reach x_T, so five steps and the initial
+    forces have a backward.)"""
+    from paper_2012_02207_amd import rollout as R
+    pos, vel, mass, target = _case()
+    x0, v0, m = (torch.from_numpy(a).requires_grad_(True) for a in (pos, vel, mass))
+    solvers = [ReuseSolver() for _ in range(nctx)]
+    xT, _ = R.leapfrog(x0, v0, m, solvers, 1e-2, 6, checkpoint_every=every)
+    loss = ((xT - torch.from_numpy(target)) ** 2).sum()
+    loss.backward()
+    L, gx, gv, gm = A.rollout_gradient(pos, vel, mass, 1e-2, 6, target)
+    for g, r in ((x0.grad, gx), (v0.grad, gv), (m.grad, gm)):
+        assert np.allclose(g.numpy(), r, rtol=1e-10, atol=1e-13 * np.abs(r).max())
+    reused = sum(s.reused for s in solvers)
+    recomputed = sum(s.recomputed for s in solvers)
+    assert reused + recomputed == 6
+    if every and nctx == every + 1:
+        assert recomputed == 0
+    else:
+        assert reused >= 1 and recomputed >= 1
