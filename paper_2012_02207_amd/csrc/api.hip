@@ -946,7 +946,7 @@ void fmm_destroy(fmm_ctx* ctx) {
   rel(c.pk); rel(c.fcell); rel(c.fmin); rel(c.loc); rel(c.counters); rel(c.scan_tmp);
   rel(c.scan_tmp64);
   rel(c.adjnear); rel(c.adjpart); rel(c.nf_cell_nseg); rel(c.nf_cell_pbase); rel(c.nf_extra);
-  rel(c.nf_part);
+  rel(c.nf_part); rel(c.m2l_nseg); rel(c.m2l_pbase); rel(c.m2l_extra); rel(c.m2l_part);
   for (CellList* L : {&c.est_far, &c.est_near, &c.m2l, &c.p2p}) {
     rel(L->raw); rel(L->tmp); rel(L->off); rel(L->src);
   }

@@ -121,6 +121,21 @@ struct NfPlan {
   int max_slots;          // host bound on the partial slots
 };
 
+// Work items of the FP64 M2L over whole lists: item B < ncell is sink B (its
+// whole list, or the first K pairs of a long one), and a sink with more than
+// K pairs appends its later segments (sink, segment) as extra items, which
+// write partial expansions to slots pbase[B] + segment - 1; these are added
+// to the sink's expansion in segment order afterwards.
+struct M2lSeg {
+  const int* nseg;    // segments of each sink (null: one item per sink)
+  const int* pbase;   // first partial slot of each split sink
+  const int2* extra;  // (sink, segment) of the extra items
+  const int* nextra;  // extra item count (device)
+  double* part;       // partial expansions, one slot each
+  int K;              // pairs per segment
+  int max_items;      // host bound on the item count (grid size)
+};
+
 // ------------------------------------------------------------------ context
 struct Ctx {
   fmm_params prm{};
@@ -234,6 +249,9 @@ struct Ctx {
   dbuf<int2> nf_extra;
   dbuf<double4> nf_part;
   NfPlan nf{};
+  dbuf<int> m2l_nseg, m2l_pbase;
+  dbuf<int2> m2l_extra;
+  dbuf<double> m2l_part;
 
   // replay of the frozen-tree evaluation as a HIP graph (captured per set of
   // buffers; dropped whenever the tree is rebuilt)

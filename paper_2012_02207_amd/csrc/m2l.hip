@@ -20,6 +20,7 @@
 // parameter so that all coefficient arrays live in registers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "fmm_device.h"
@@ -112,31 +113,16 @@ __device__ __forceinline__ void zrot(T* v, T c1, T s1) {
 // which adds it to its accumulator acc_slot.
 constexpr int M2L_WAVES = 4;  // sinks per workgroup (one per wavefront)
 
-// M2L of the list of one sink cell B (one wavefront; lane = lane id); with
-// B >= first_lo only the sources below first_lo are taken
+// M2L of the pairs src[b .. e) of one sink cell B (one wavefront; lane =
+// lane id) into the expansion out (NC complex coefficients; zeros when b == e)
 template <int P>
-__device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, const int* __restrict__ off,
-                                              const int* __restrict__ src, const double* __restrict__ cx,
-                                              const double* __restrict__ cy, const double* __restrict__ cz,
-                                              const double* __restrict__ mult, double* __restrict__ loc,
-                                              double* acc) {
+__device__ __forceinline__ void m2l_range_fp64(int B, int b, int e, int lane, const int* __restrict__ src,
+                                               const double* __restrict__ cx, const double* __restrict__ cy,
+                                               const double* __restrict__ cz, const double* __restrict__ mult,
+                                               double* __restrict__ out, double* acc) {
   constexpr int NC = ncoef(P);
-  int b = off[B], e = off[B + 1];
-  if (B >= first_lo) {
-    // mixed precision: only the sources above the root levels (a prefix of
-    // the ascending, breadth-first list) are handled in FP64
-    int lo = b, hi = e;
-    while (lo < hi) {
-      int mid = (lo + hi) >> 1;
-      if (src[mid] < first_lo)
-        lo = mid + 1;
-      else
-        hi = mid;
-    }
-    e = lo;
-  }
   if (b == e) {  // no pair: the sink's expansion starts at zero (never a listed sink)
-    for (int k = lane; k < NC * 2; k += 64) loc[(size_t)B * NC * 2 + k] = 0.0;
+    for (int k = lane; k < NC * 2; k += 64) out[k] = 0.0;
     return;
   }
   // per-order sums, one LDS slot per lane: acc[64 n]
@@ -276,7 +262,6 @@ __device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, con
   // back to the unscaled basis: L_n^m = (n-m)!(n+m)! Lhat_n^m; real-basis
   // entry j of order n is held by lane reduce_owner(2n+1, j) (the cross-lane
   // sum in fmm_device.h)
-  double* out = loc + (size_t)B * NC * 2;
   static_for<0, P + 1>([&](auto nc) {
     constexpr int n = nc;
     int j, real;
@@ -289,6 +274,32 @@ __device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, con
       if (j == 0) out[2 * cidx(n, 0) + 1] = 0.0;
     }
   });
+}
+
+// M2L of the list of one sink cell B; with B >= first_lo only the sources
+// below first_lo are taken
+template <int P>
+__device__ __forceinline__ void m2l_sink_fp64(int B, int first_lo, int lane, const int* __restrict__ off,
+                                              const int* __restrict__ src, const double* __restrict__ cx,
+                                              const double* __restrict__ cy, const double* __restrict__ cz,
+                                              const double* __restrict__ mult, double* __restrict__ loc,
+                                              double* acc) {
+  constexpr int NC = ncoef(P);
+  int b = off[B], e = off[B + 1];
+  if (B >= first_lo) {
+    // mixed precision: only the sources above the root levels (a prefix of
+    // the ascending, breadth-first list) are handled in FP64
+    int lo = b, hi = e;
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (src[mid] < first_lo)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    e = lo;
+  }
+  m2l_range_fp64<P>(B, b, e, lane, src, cx, cy, cz, mult, loc + (size_t)B * NC * 2, acc);
 }
 
 // All sinks (one wavefront each; consecutive workgroups, which the hardware
@@ -307,7 +318,8 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) __attribute__((amdgpu_waves_pe
                                                              const double* __restrict__ cy,
                                                              const double* __restrict__ cz,
                                                              const double* __restrict__ mult,
-                                                             double* __restrict__ loc) {
+                                                             double* __restrict__ loc, M2lSeg sg) {
+  constexpr int NC = ncoef(P);
   int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   __shared__ double accs[M2L_WAVES][P + 1][64];
   double* acc = &accs[wv][0][0] + lane;
@@ -316,12 +328,91 @@ __global__ void __launch_bounds__(64 * M2L_WAVES) __attribute__((amdgpu_waves_pe
     for (int it = blockIdx.x * M2L_WAVES + wv; it < cnt; it += gridDim.x * M2L_WAVES)
       m2l_sink_fp64<P>(sinks[it], first_lo, lane, off, src, cx, cy, cz, mult, loc, acc);
   } else {
-    int nblk = (ncell + M2L_WAVES - 1) / M2L_WAVES;
+    int nitems = sg.nseg ? sg.max_items : ncell;
+    int nblk = (nitems + M2L_WAVES - 1) / M2L_WAVES;
     int blk = xcd_block();
-    int B = blk * M2L_WAVES + wv;
-    if (blk < nblk && B < ncell)
-      m2l_sink_fp64<P>(B, first_lo, lane, off, src, cx, cy, cz, mult, loc, acc);
+    int it = blk * M2L_WAVES + wv;
+    if (blk >= nblk || it >= nitems) return;
+    if (!sg.nseg) {
+      m2l_sink_fp64<P>(it, first_lo, lane, off, src, cx, cy, cz, mult, loc, acc);
+      return;
+    }
+    // whole lists, long ones in segments of K pairs
+    int B = it, seg = 0;
+    if (it >= ncell) {
+      int x = it - ncell;
+      if (x >= *sg.nextra) return;
+      int2 v = sg.extra[x];
+      B = v.x;
+      seg = v.y;
+    }
+    int b = off[B], e = off[B + 1];
+    double* out = loc + (size_t)B * NC * 2;
+    if (sg.nseg[B] > 1) {
+      b += seg * sg.K;
+      e = min(e, b + sg.K);
+      if (seg > 0) out = sg.part + (size_t)(sg.pbase[B] + seg - 1) * NC * 2;
+    }
+    m2l_range_fp64<P>(B, b, e, lane, src, cx, cy, cz, mult, out, acc);
   }
+}
+
+// The segment plan of the M2L over whole lists (one thread per sink); ctr[0]
+// counts the extra items (zero on entry), and a split sink's partial slots
+// follow its extra items.
+__global__ void k_m2l_plan(int ncell, const int* __restrict__ off, int K, int* nseg, int* pbase, int2* extra,
+                           int* ctr) {
+  int B = blockIdx.x * blockDim.x + threadIdx.x;
+  if (B >= ncell) return;
+  int len = off[B + 1] - off[B];
+  int ns = len > K ? (len + K - 1) / K : 1;
+  nseg[B] = ns;
+  if (ns > 1) {
+    int x = atomicAdd(ctr, ns - 1);
+    for (int k = 1; k < ns; k++) extra[x + k - 1] = make_int2(B, k);
+    pbase[B] = x;
+  }
+}
+
+// the partial expansions of split sinks added in segment order (threads of
+// each sink's first extra item, one per coefficient)
+__global__ void k_m2l_combine(int ncd, int max_extra, const int* __restrict__ nseg, const int* __restrict__ pbase,
+                              const int2* __restrict__ extra, const int* __restrict__ nextra,
+                              const double* __restrict__ part, double* loc) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int x = (int)(t / ncd), k = (int)(t % ncd);
+  if (x >= max_extra || x >= *nextra) return;
+  int2 v = extra[x];
+  if (v.y != 1) return;
+  int B = v.x, ns = nseg[B];
+  double s = loc[(size_t)B * ncd + k];
+  for (int g = 1; g < ns; g++) s += part[(size_t)(pbase[B] + g - 1) * ncd + k];
+  loc[(size_t)B * ncd + k] = s;
+}
+
+constexpr int M2L_SEG_MIN = 512;    // pairs per segment, at least
+constexpr int M2L_SEG_DIV = 8192;   // and at least the list total / M2L_SEG_DIV
+
+// the plan for the M2L over whole lists (on c.stream)
+static M2lSeg plan_m2l(Ctx& c) {
+  int nc = (int)c.ncell;
+  int64_t cnt = c.m2l.count;
+  int K = (int)std::max<int64_t>(M2L_SEG_MIN, ceil_div(cnt, M2L_SEG_DIV));
+  // a split sink holds len > K pairs in ceil(len / K) < 2 len / K segments, so
+  // the extra items number fewer than cnt / K <= M2L_SEG_DIV
+  int64_t extra_max = std::min<int64_t>(M2L_SEG_DIV, ceil_div(cnt, K));
+  size_t ncd = (size_t)ncoef(c.p) * 2;
+  ensure(c.ws, c.m2l_nseg, (size_t)nc + 1);
+  ensure(c.ws, c.m2l_pbase, (size_t)nc + 1);
+  ensure(c.ws, c.m2l_extra, (size_t)extra_max + 1);
+  ensure(c.ws, c.m2l_part, (size_t)(extra_max + 1) * ncd);
+  ensure(c.ws, c.counters, 512);
+  int* ctr = c.counters.p + 46;
+  zero_fill(c, ctr, sizeof(int));
+  hipLaunchKernelGGL(k_m2l_plan, dim3((unsigned)ceil_div(nc, 256)), dim3(256), 0, c.stream, nc, c.m2l.off.p, K,
+                     c.m2l_nseg.p, c.m2l_pbase.p, c.m2l_extra.p, ctr);
+  HIPCHK(hipGetLastError());
+  return M2lSeg{c.m2l_nseg.p, c.m2l_pbase.p, c.m2l_extra.p, ctr, c.m2l_part.p, K, (int)(nc + extra_max)};
 }
 
 // sinks == nullptr: every sink cell; otherwise the listed sinks (count on the
@@ -332,14 +423,23 @@ static void launch_p(Ctx& c, int first_lo, const double* mult, double* loc, cons
   if (sinks) {
     constexpr unsigned LIST_BLOCKS = 512;
     hipLaunchKernelGGL((k_m2l_fp64<P, true>), dim3(LIST_BLOCKS), dim3(64 * M2L_WAVES), 0, c.stream, nc, first_lo,
-                       sinks, nsinks, c.m2l.off.p, c.m2l.src.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, mult, loc);
+                       sinks, nsinks, c.m2l.off.p, c.m2l.src.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, mult, loc, M2lSeg{});
     return;
   }
-  int nblk = (nc + M2L_WAVES - 1) / M2L_WAVES;
+  M2lSeg sg{};
+  if (first_lo >= nc) sg = plan_m2l(c);  // whole lists: long ones in segments
+  int nitems = sg.nseg ? sg.max_items : nc;
+  int nblk = (nitems + M2L_WAVES - 1) / M2L_WAVES;
   unsigned grid = xcd_grid(nblk);
   hipLaunchKernelGGL((k_m2l_fp64<P, false>), dim3(grid), dim3(64 * M2L_WAVES), 0, c.stream, nc, first_lo,
                      (const int*)nullptr, (const int*)nullptr, c.m2l.off.p, c.m2l.src.p, c.c_cx.p, c.c_cy.p,
-                     c.c_cz.p, mult, loc);
+                     c.c_cz.p, mult, loc, sg);
+  if (sg.nseg) {
+    int ncd = ncoef(P) * 2, max_extra = sg.max_items - nc;
+    if (max_extra > 0)
+      hipLaunchKernelGGL(k_m2l_combine, dim3((unsigned)ceil_div((int64_t)max_extra * ncd, 256)), dim3(256), 0,
+                         c.stream, ncd, max_extra, sg.nseg, sg.pbase, sg.extra, sg.nextra, sg.part, loc);
+  }
 }
 
 template <int P>
