@@ -397,3 +397,47 @@ def test_near_field_segments(fmm):
         a2, _ = f.forces(_dev(pos), _dev(mass))
         assert np.array_equal(acc, a2.cpu().numpy())
         f.close()
+
+
+def test_m2l_segments(fmm):
+    """Long M2L lists are cut into segments of K = max(512, list total / 8192)
+    pairs summed by separate wavefronts, whose partial expansions are added in
+    segment order.  At N = 8192 with 16-body leaves, over a thousand sinks
+    have more than 512 pairs at p = 8 (the oracle's lists), so the FP64
+    evaluation takes that path: forces within 1e-12 (median) of the oracle,
+    repeated calls bit for bit.  The adjoint's source pass takes it too (at
+    p = 12, 130 sinks): within 10 err_tol (median) and 1e3 err_tol (99th
+    percentile) of the direct-sum adjoint.  (With 16-body leaves more of the
+    gradient comes from the far field, and the adjoint's median error at p = 8
+    is 1.35e-6, the same before the lists were segmented.)"""
+    from oracle import adjoint as A
+    pos, _, mass = W.plummer(8192, 77)
+    print("[gpu] M2L segments N=8192 p=8 n_leaf=16", flush=True)
+    o = oracle.Oracle()
+    oacc, _ = o.run(pos, mass, p=8, err_tol=1e-7, n_leaf=16)
+    ml = o.get("m2l")
+    lens = np.bincount(ml[:, 0])
+    assert lens.max() > 512 and len(ml) / 8192 < 512  # K = 512, and some lists are longer
+    f = fmm.FMM(p=8, err_tol=1e-7, n_leaf=16)
+    acc, _ = f.forces(_dev(pos), _dev(mass))
+    acc = acc.cpu().numpy()
+    rel = np.linalg.norm(acc - oacc, axis=1) / np.linalg.norm(oacc, axis=1)
+    assert np.median(rel) <= 1e-12 and rel.max() <= 1e-9, (np.median(rel), rel.max())
+    a2, _ = f.forces(_dev(pos), _dev(mass))
+    assert np.array_equal(acc, a2.cpu().numpy())
+    f.close()
+    o12 = oracle.Oracle()
+    o12.run(pos, mass, p=12, err_tol=1e-7, n_leaf=16, stage="walk")
+    ml = o12.get("m2l")
+    assert np.bincount(ml[:, 0]).max() > 512 and len(ml) / 8192 < 512
+    rng = np.random.default_rng(6)
+    ga, gp = rng.normal(size=(8192, 3)), rng.normal(size=8192)
+    f = fmm.FMM(p=12, err_tol=1e-7, n_leaf=16)
+    gx, gm = f.adjoint(_dev(pos), _dev(mass), _dev(ga), _dev(gp))
+    rx, rm = A.direct_adjoint(pos, mass, ga, gp, 0.0)
+    ex = np.linalg.norm(gx.cpu().numpy() - rx, axis=1) / np.linalg.norm(rx, axis=1)
+    em = np.abs(gm.cpu().numpy() - rm) / np.abs(rm)
+    print(f"adjoint p=12: gpos median {np.median(ex):.2e} p99 {np.percentile(ex, 99):.2e}", flush=True)
+    assert np.median(ex) <= 1e-6 and np.percentile(ex, 99) <= 1e-4, (np.median(ex),)
+    assert np.median(em) <= 1e-6 and np.percentile(em, 99) <= 1e-4, (np.median(em),)
+    f.close()
