@@ -15,6 +15,7 @@
 // back to the standard local coefficients in FP64.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 #include <vector>
@@ -175,30 +176,48 @@ __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per
                                                             const double* __restrict__ cz,
                                                             const double* __restrict__ scale,
                                                             const float* __restrict__ nmult,
-                                                            double* __restrict__ loc, int wps) {
+                                                            double* __restrict__ loc, int wps, M2lSeg sg) {
   using namespace mx;
   constexpr int NC = ncoef(P);
   constexpr int NR = (P + 1) * (P + 1);
   // wps wavefronts per sink: the sink's list, in batches of 64 sources, is
   // split into wps contiguous parts; each wave sums its part, and the parts
   // are added in order at the end (through LDS, one barrier)
+  // With one wave per sink and a plan (sg.nseg), the items are the sinks and
+  // the later segments of long lists (see M2lSeg): a segment writes a partial
+  // expansion, added to the sink's in segment order afterwards.
   int spb = MX_WAVES / wps;    // sinks per workgroup
   int nlo = ncell - first_lo;  // sinks below the root levels
-  int nblk = (nlo + spb - 1) / spb;
+  int nitems = sg.nseg ? sg.max_items : nlo;
+  int nblk = (nitems + spb - 1) / spb;
   int blk = xcd_block();
   int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: B and its data in SGPRs
   int slot = wv / wps, part = wv - slot * wps;
-  int B = first_lo + blk * spb + slot;
-  if (wps == 1 && (blk >= nblk || B >= ncell)) return;  // (no barrier below for one wave per sink)
+  int it = blk * spb + slot, seg = 0;
+  if (wps == 1 && (blk >= nblk || it >= nitems)) return;  // (no barrier below for one wave per sink)
+  int B = first_lo + it;
+  if (sg.nseg && it >= nlo) {  // a later segment of a long list (one wave per sink)
+    int x = it - nlo;
+    if (x >= *sg.nextra) return;
+    int2 v = sg.extra[x];
+    B = v.x;
+    seg = v.y;
+  }
   bool live = blk < nblk && B < ncell;
   int b = 0, e = 0;
+  double* out = loc + (size_t)B * NC * 2;
   if (live) {
     e = off[B + 1];
     b = split_point(src, off[B], e, first_lo);
+    if (sg.nseg && sg.nseg[B] > 1) {
+      b += seg * sg.K;
+      e = min(e, b + sg.K);
+      if (seg > 0) out = sg.part + (size_t)(sg.pbase[B] + seg - 1) * NC * 2;
+    }
   }
   int lane = threadIdx.x & 63;
   if (wps == 1 && b == e) {  // no FP32 pair: the sink's expansion starts at zero
-    for (int k = lane; k < NC * 2; k += 64) loc[(size_t)B * NC * 2 + k] = 0.0;
+    for (int k = lane; k < NC * 2; k += 64) out[k] = 0.0;
     return;
   }
   int nbat = (e - b + 63) >> 6;
@@ -339,14 +358,13 @@ __global__ void __launch_bounds__(64 * MX_WAVES) __attribute__((amdgpu_waves_per
     __syncthreads();  // every part's sums are in LDS
     if (!live || part != 0) return;
     if (b == e) {
-      for (int k = lane; k < NC * 2; k += 64) loc[(size_t)B * NC * 2 + k] = 0.0;
+      for (int k = lane; k < NC * 2; k += 64) out[k] = 0.0;
       return;
     }
   }
   // back to standard coefficients: L_n^0 = Lt n! / rho_B^n,
   // L_n^m = Lt sqrt((n-m)!(n+m)!/2) / rho_B^n; real-basis entry j of order n
   // is held by lane reduce_owner(2n+1, j) (the cross-lane sum in fmm_device.h)
-  double* out = loc + (size_t)B * NC * 2;
   double isB = 1.0 / sB, pw = 1.0;
   static_for<0, P + 1>([&](auto nc) {
     constexpr int n = nc;
@@ -388,6 +406,43 @@ __global__ void k_scale(int ncell, const double* rad, double* scale) {
   if (c < ncell) scale[c] = rad[c] > 0.0 ? rad[c] : 1.0;
 }
 
+// The segment plan of the FP32 M2L (one thread per sink below the root
+// levels; its FP32 pairs are the list's suffix from split_point); ctr[0]
+// counts the extra items (zero on entry).
+__global__ void k_m2l32_plan(int ncell, int first_lo, const int* __restrict__ off, const int* __restrict__ src,
+                             int K, int* nseg, int* pbase, int2* extra, int* ctr) {
+  int B = first_lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (B >= ncell) return;
+  int e = off[B + 1];
+  int len = e - split_point(src, off[B], e, first_lo);
+  int ns = len > K ? (len + K - 1) / K : 1;
+  nseg[B] = ns;
+  if (ns > 1) {
+    int x = atomicAdd(ctr, ns - 1);
+    for (int k = 1; k < ns; k++) extra[x + k - 1] = make_int2(B, k);
+    pbase[B] = x;
+  }
+}
+
+// partial expansions of split sinks added in segment order (threads of each
+// sink's first extra item, one per coefficient)
+__global__ void k_m2l32_combine(int ncd, int max_extra, const int* __restrict__ nseg, const int* __restrict__ pbase,
+                                const int2* __restrict__ extra, const int* __restrict__ nextra,
+                                const double* __restrict__ part, double* loc) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int x = (int)(t / ncd), k = (int)(t % ncd);
+  if (x >= max_extra || x >= *nextra) return;
+  int2 v = extra[x];
+  if (v.y != 1) return;
+  int B = v.x, ns = nseg[B];
+  double s = loc[(size_t)B * ncd + k];
+  for (int g = 1; g < ns; g++) s += part[(size_t)(pbase[B] + g - 1) * ncd + k];
+  loc[(size_t)B * ncd + k] = s;
+}
+
+constexpr int M2L32_SEG_MIN = 512;   // FP32 pairs per segment, at least
+constexpr int M2L32_SEG_DIV = 8192;  // and at least the list total / M2L32_SEG_DIV
+
 template <int P>
 static void launch_p32(Ctx& c, int first_lo) {
   int nc = (int)c.ncell;
@@ -395,11 +450,38 @@ static void launch_p32(Ctx& c, int first_lo) {
   if (nlo <= 0) return;
   int wps = c.prm.m2l_waves;
   int spb = MX_WAVES / wps;
-  int nblk = (nlo + spb - 1) / spb;
+  M2lSeg sg{};
+  int64_t extra_max = 0;
+  if (wps == 1) {  // long lists in segments (see M2lSeg)
+    int64_t cnt = c.m2l.count;
+    int K = (int)std::max<int64_t>(M2L32_SEG_MIN, ceil_div(cnt, M2L32_SEG_DIV));
+    // split sinks hold len > K pairs in ceil(len / K) < 2 len / K segments:
+    // fewer than cnt / K <= M2L32_SEG_DIV extra items
+    extra_max = std::min<int64_t>(M2L32_SEG_DIV, ceil_div(cnt, K));
+    size_t ncd = (size_t)ncoef(P) * 2;
+    ensure(c.ws, c.m2l_nseg, (size_t)nc + 1);
+    ensure(c.ws, c.m2l_pbase, (size_t)nc + 1);
+    ensure(c.ws, c.m2l_extra, (size_t)extra_max + 1);
+    ensure(c.ws, c.m2l_part, (size_t)(extra_max + 1) * ncd);
+    ensure(c.ws, c.counters, 512);
+    int* ctr = c.counters.p + 46;
+    zero_fill(c, ctr, sizeof(int));
+    hipLaunchKernelGGL(k_m2l32_plan, dim3((unsigned)ceil_div(nlo, 256)), dim3(256), 0, c.stream, nc, first_lo,
+                       c.m2l.off.p, c.m2l.src.p, K, c.m2l_nseg.p, c.m2l_pbase.p, c.m2l_extra.p, ctr);
+    HIPCHK(hipGetLastError());
+    sg = M2lSeg{c.m2l_nseg.p, c.m2l_pbase.p, c.m2l_extra.p, ctr, c.m2l_part.p, K, (int)(nlo + extra_max)};
+  }
+  int nitems = sg.nseg ? sg.max_items : nlo;
+  int nblk = (nitems + spb - 1) / spb;
   unsigned grid = xcd_grid(nblk);
   hipLaunchKernelGGL(k_m2l_fp32<P>, dim3(grid), dim3(64 * MX_WAVES), 0, c.stream, nc, first_lo,
                      c.m2l.off.p, c.m2l.src.p, c.c_cx.p, c.c_cy.p, c.c_cz.p, c.scale.p, c.nmult.p, c.loc.p,
-                     wps);
+                     wps, sg);
+  if (sg.nseg && extra_max > 0) {
+    int ncd = ncoef(P) * 2;
+    hipLaunchKernelGGL(k_m2l32_combine, dim3((unsigned)ceil_div(extra_max * ncd, 256)), dim3(256), 0, c.stream,
+                       ncd, (int)extra_max, sg.nseg, sg.pbase, sg.extra, sg.nextra, sg.part, c.loc.p);
+  }
 }
 
 template <int P>

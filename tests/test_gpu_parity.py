@@ -404,8 +404,9 @@ def test_m2l_segments(fmm):
     pairs summed by separate wavefronts, whose partial expansions are added in
     segment order.  At N = 8192 with 16-body leaves, over a thousand sinks
     have more than 512 pairs at p = 8 (the oracle's lists), so the FP64
-    evaluation takes that path: forces within 1e-12 (median) of the oracle,
-    repeated calls bit for bit.  The adjoint's source pass takes it too (at
+    evaluation takes that path, and so does the mixed one's FP32 kernel: forces
+    within 1e-12 (median; mixed: its bound) of the oracle, repeated calls bit
+    for bit.  The adjoint's source pass takes it too (at
     p = 12, 130 sinks): within 10 err_tol (median) and 1e3 err_tol (99th
     percentile) of the direct-sum adjoint.  (With 16-body leaves more of the
     gradient comes from the far field, and the adjoint's median error at p = 8
@@ -423,6 +424,16 @@ def test_m2l_segments(fmm):
     acc = acc.cpu().numpy()
     rel = np.linalg.norm(acc - oacc, axis=1) / np.linalg.norm(oacc, axis=1)
     assert np.median(rel) <= 1e-12 and rel.max() <= 1e-9, (np.median(rel), rel.max())
+    a2, _ = f.forces(_dev(pos), _dev(mass))
+    assert np.array_equal(acc, a2.cpu().numpy())
+    f.close()
+    # mixed precision: the FP32 kernel's lists (below the root levels) take
+    # the same segments
+    f = fmm.FMM(p=8, err_tol=1e-7, n_leaf=16, precision="mixed")
+    acc, _ = f.forces(_dev(pos), _dev(mass))
+    acc = acc.cpu().numpy()
+    rel = np.linalg.norm(acc - oacc, axis=1) / np.linalg.norm(oacc, axis=1)
+    assert np.median(rel) <= MIXED_MEDIAN_BOUND, np.median(rel)
     a2, _ = f.forces(_dev(pos), _dev(mass))
     assert np.array_equal(acc, a2.cpu().numpy())
     f.close()
