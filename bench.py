@@ -62,9 +62,9 @@ P2P_FLOPS = 20   # per directed body pair: acc + pot, softened, rsqrt counted on
 # (fetch x2.0, write x1.0).  Keyed by (kernel, workload, precision); valid only
 # while the kernel's source file has the recorded SHA-1 (else reported as null).
 MEASURED_TRAFFIC = {
-    ("k_m2l_fp32", "plummer_1m", "mixed"): (1599.0e6, "paper_2012_02207_amd/csrc/m2l_mixed.hip",
-                                             "7e08015d0f6a495e1743ecbbf4fec0dc56082f7a"),
-    ("k_leaf_group<true> (mixed P2P)", "plummer_1m", "mixed"): (664.0e6,
+    ("k_m2l_fp32", "plummer_1m", "mixed"): (1597.0e6, "paper_2012_02207_amd/csrc/m2l_mixed.hip",
+                                             "ed1126117fe88dda26a2bd2bc1bd2d18ba1f497b"),
+    ("k_leaf_group<true> (mixed P2P)", "plummer_1m", "mixed"): (666.0e6,
                                                                 "paper_2012_02207_amd/csrc/local.hip",
                                                                 "babcf4bb55be7a5c3c74f1314c40e02ccec38c25"),
 }
