@@ -369,8 +369,27 @@ def run_rollout(args):
         xT, _ = R.leapfrog(P, V, M, ctxs[0], dt, nsteps, checkpoint_every=0)
         torch.cuda.synchronize()
         t_fwd = time.perf_counter() - t0
-    # finite differences with frozen lists
+    # the same gradient without checkpoints: one context per force evaluation
+    # (a 2^18-body context holds ~0.6 GB of HBM), so that no forward pass is
+    # recomputed and every adjoint reuses its evaluation (fmm_adjoint_last)
     solvers = [R.make_solver(p=p, err_tol=err_tol, n_leaf=args.n_leaf) for _ in range(nsteps + 1)]
+
+    def step_nc():
+        x0, v0, m = (a.clone().requires_grad_(True) for a in (P, V, M))
+        xT, _ = R.leapfrog(x0, v0, m, solvers, dt, nsteps, checkpoint_every=0)
+        ((xT - T) ** 2).sum().backward()
+        return x0.grad, v0.grad, m.grad
+    step_nc()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        gx2, gv2, gm2 = step_nc()
+    torch.cuda.synchronize()
+    t_nc = (time.perf_counter() - t0) / args.steps
+    same_nc = bool(torch.equal(gx, gx2) and torch.equal(gv, gv2) and torch.equal(gm, gm2))
+    ws_nc = sum(s_.stats()["workspace_bytes"] for s_ in solvers)
+    note(f"without checkpoints: {1e3 * t_nc:.1f} ms per rollout gradient")
+    # finite differences with frozen lists
     R.leapfrog_frozen(P, V, M, solvers, dt, nsteps, record=True)
     note("recorded the lists of every force evaluation")
 
@@ -407,6 +426,9 @@ def run_rollout(args):
         "grad_norms": {"x0": float(gx.norm()), "v0": float(gv.norm()), "m": float(gm.norm())},
         "finite_difference_check": {"coords": 32, "h": h, "median_rel": float(np.median(rels)),
                                     "max_rel": float(rels.max())},
+        "no_checkpoint": {"ms_per_step": 1e3 * t_nc, "rollout_gradients_per_s": 1.0 / t_nc,
+                          "contexts": nsteps + 1, "workspace_gb": ws_nc / 1e9,
+                          "gradient_equal_to_checkpointed": same_nc},
     }
     print(json.dumps(out))
 
