@@ -285,7 +285,7 @@ fmm_status fmm_forces_batch(fmm_ctx* ctx, int64_t nsys, const int64_t* offsets, 
                             const double* mass, double eps_soft, int p, double err_tol,
                             double* acc, double* pot, void* stream);
 
-/* Autotuner (NEXT: batched ensembles): picks, for this workload, when the
+/* Autotuner (for batched ensembles and single systems alike): picks, for this workload, when the
  * near field starts (p2p_start in {0, 1}, at the given n_leaf), the leaf
  * capacity n_leaf (the balance between the near field and the expansions),
  * then in mixed precision the FP32 M2L's wavefronts per sink (m2l_waves in
