@@ -53,7 +53,8 @@ def test_force_adjoint_matches_direct_sum(fmm, eps_soft, p, tol):
 def test_adjoint_last_equals_adjoint(fmm):
     """fmm_adjoint_last (the forward evaluation kept) gives fmm_adjoint's
     gradient bit for bit, with and without softening, and refuses a context
-    whose last evaluation was none, mixed precision or another body count."""
+    whose last evaluation was none, another body count, mixed precision or a
+    batch of systems."""
     pos, _, mass = W.plummer(4096, 123)
     rng = np.random.default_rng(5)
     ga, gp = rng.normal(size=(4096, 3)), rng.normal(size=4096)
@@ -75,6 +76,10 @@ def test_adjoint_last_equals_adjoint(fmm):
         f.adjoint_last(acc, _dev(ga), _dev(gp))
     f.set_params(precision="mixed")
     f.forces(_dev(pos), _dev(mass))
+    with pytest.raises(fmm.FmmError):
+        f.adjoint_last(acc, _dev(ga), _dev(gp))
+    f.set_params(precision="fp64")
+    f.forces_batch(_dev(pos), _dev(mass), [0, 2048, 4096])  # two systems: no single-system state
     with pytest.raises(fmm.FmmError):
         f.adjoint_last(acc, _dev(ga), _dev(gp))
     f.close()
